@@ -1,0 +1,162 @@
+/*
+ * libbccb -- BCCB-structured LASSO solvers for single-snapshot 2D harmonic
+ * recovery with sparse planar arrays, on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. II): a planar array on the half-wavelength grid keeps M of its
+ * M1 x M2 elements (mask, eq. (6)); the snapshot y_s = D_s c + n_s (eq. (7))
+ * is explained by a coefficient grid c over the uniform harmonic grid
+ * f_{i,l} = -1/2 + l/L_i (eq. (16)).  The LASSO (eq. (8), taken with the factor
+ * 1/2 on the data term that its ISTA/FISTA/ADMM iterations imply) is solved by
+ * ISTA (eq. (9)), FISTA (eqs. (10)-(12)) or ADMM (eqs. (13)-(15)).  Because the
+ * Gram G = D_s^H D_s is block circulant with circulant blocks (eq. (17),
+ * Sec. III-A), every G-product is computed as IDFT2(Omega . DFT2(c)) (eq. (23))
+ * with the eigenvalues Omega of eq. (21).
+ *
+ * Layouts
+ *   mask      host uint8 [M2][M1], mask[m2*M1 + m1] != 0 keeps element (m1, m2).
+ *   y         device complex64 [M], the kept elements in increasing m1 + m2*M1
+ *             (the row order of Psi, eq. (6)).
+ *   grids     device complex64 [L2][L1] row-major: c[l1 + l2*L1] is the
+ *             amplitude of harmonic (f_{1,l1}, f_{2,l2}) (eq. (4), index l1 + l2*L1).
+ *   complex64 is interleaved (re, im) float pairs, i.e. bccb_c32.
+ *
+ * Ownership and ordering
+ *   The caller owns every buffer it passes (device memory from any allocator).
+ *   A plan owns its eigenvalues, twiddle tables and workspace and frees them
+ *   in bccb_plan_destroy.  Work is enqueued on the plan's HIP stream
+ *   (hipStream_t passed as void*, NULL = the null stream).  Solver and
+ *   diagnostic calls return after the stream has drained (they read a status
+ *   flag back), so their outputs are ready on return.  A plan is not thread
+ *   safe and serves one stream at a time; distinct plans are independent.
+ *
+ * Errors
+ *   Arguments are checked on the host before anything is enqueued; a negative
+ *   code means nothing was written.  BCCB_E_NONFINITE means the results were
+ *   computed from NaN/Inf input and must not be used.
+ */
+#ifndef BCCB_H
+#define BCCB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bccb_plan_s* bccb_plan_t;
+typedef struct { float re, im; } bccb_c32;
+
+enum bccb_status {
+  BCCB_OK = 0,
+  BCCB_E_INVALID = -1,      /* bad argument (null pointer, size, tau < 0, rho <= 0, ...)  */
+  BCCB_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. L_i not a power of two)    */
+  BCCB_E_NOMEM = -3,        /* device allocation failed                                   */
+  BCCB_E_DEVICE = -4,       /* a HIP call failed                                          */
+  BCCB_E_NONFINITE = -5     /* NaN or Inf in y or in the warm start                       */
+};
+
+/* Human-readable name of a status code (static string). */
+const char* bccb_status_string(int status);
+
+/*
+ * bccb_plan -- per-geometry setup (Sec. III-A, III-B).
+ *   Builds the first column r of G (property (iv) of Sec. III-A, from the
+ *   masked Kronecker sum of eq. (17)) and its eigenvalues Omega by eq. (21) in
+ *   FP64 on the host, stores Omega as FP32 on the device, sets the step
+ *   mu = 1/sigma_max(D_s)^2 = 1/max(Omega) (eq. (9)) and the DFT twiddles.
+ *   mask: host [M2][M1], at least one nonzero.  1 <= M1, M2 <= 4096.
+ *   L1, L2: powers of two in [8, 1024] (L1 != L2 allowed).  M_i > L_i
+ *   (aliasing) is accepted: eq. (21) stays exact.
+ *   stream: hipStream_t (may be NULL).  *out receives the plan.
+ *   Returns BCCB_OK, BCCB_E_INVALID, BCCB_E_UNSUPPORTED, BCCB_E_NOMEM, BCCB_E_DEVICE.
+ */
+int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream, bccb_plan_t* out);
+
+/* Free a plan and everything it owns (NULL is accepted). */
+int bccb_plan_destroy(bccb_plan_t plan);
+
+/* Rebind the plan to another hipStream_t. */
+int bccb_set_stream(bccb_plan_t plan, void* stream);
+
+/*
+ * bccb_plan_info -- geometry facts of a plan.  Any output pointer may be NULL.
+ *   M: number of kept elements; mu: step 1/max(Omega) in FP64;
+ *   omega_host: host float [L2][L1] receiving the FP32 eigenvalue grid
+ *   (Omega[k2][k1] is the eigenvalue of the mode e^{+j2pi(k1 l1/L1 + k2 l2/L2)}).
+ */
+int bccb_plan_info(bccb_plan_t plan, int* M, double* mu, float* omega_host);
+
+/*
+ * bccb_adjoint -- b = D_s^H y_s (the right-hand side of eqs. (9), (13)).
+ *   Computed as the unnormalised 2D inverse DFT of y scattered onto the
+ *   spectral grid with the (-1)^(m1+m2) factor that the grid offset -1/2 of
+ *   eq. (16) puts on element (m1, m2).  y: device [M]; b: device [L2][L1].
+ *   BCCB_E_NONFINITE if y holds NaN/Inf.
+ */
+int bccb_adjoint(bccb_plan_t plan, const bccb_c32* y, bccb_c32* b);
+
+/* max_l |(D_s^H y)_l| in FP64 (for the regularisation weight tau = frac * max|A^H y|). */
+int bccb_adjoint_maxabs(bccb_plan_t plan, const bccb_c32* y, double* maxabs);
+
+/*
+ * bccb_gram_apply -- gx = G x = IDFT2(Omega . DFT2(x)) (eq. (23)).
+ *   x, gx: device [L2][L1]; may alias.
+ */
+int bccb_gram_apply(bccb_plan_t plan, const bccb_c32* x, bccb_c32* gx);
+
+/*
+ * lasso_solve_ista -- `iters` iterations of eq. (9):
+ *   c <- S_{mu tau}(c - mu G c + mu D_s^H y), mu = 1/max(Omega).
+ *   tau >= 0 (absolute weight of ||c||_1); iters >= 0; c0 device [L2][L1] or
+ *   NULL for zeros; c_out device [L2][L1] (may alias c0).  iters = 0 copies c0
+ *   (or zeros) to c_out.
+ */
+int lasso_solve_ista(bccb_plan_t plan, const bccb_c32* y, float tau, int iters,
+                     const bccb_c32* c0, bccb_c32* c_out);
+
+/*
+ * lasso_solve_fista -- `iters` iterations of eqs. (10)-(12) with z^(1) = c^(0),
+ *   alpha_1 = 1 (first momentum weight 0), momentum weights computed in FP64.
+ *   Arguments as lasso_solve_ista.  Exactly `iters` Gram products.
+ */
+int lasso_solve_fista(bccb_plan_t plan, const bccb_c32* y, float tau, int iters,
+                      const bccb_c32* c0, bccb_c32* c_out);
+
+/*
+ * lasso_solve_admm -- `iters` iterations of eqs. (13)-(15) from z = v = 0 with
+ *   threshold tau/rho (scaled ADMM; equal to the printed rho*tau at rho = 1).
+ *   (G + rho I)^-1 is the BCCB with spectrum 1/(Omega + rho) (closure under
+ *   inversion, Sec. III-A (ii)), and (G + rho I)^-1 D_s^H y is precomputed.
+ *   rho > 0.  z_out: device [L2][L1], the sparse iterate z^T; c_out: device
+ *   [L2][L1] or NULL, the iterate c^T of eq. (13).
+ */
+int lasso_solve_admm(bccb_plan_t plan, const bccb_c32* y, float tau, float rho, int iters,
+                     bccb_c32* z_out, bccb_c32* c_out);
+
+/*
+ * bccb_objective_kkt -- diagnostics of a coefficient grid c (device [L2][L1]).
+ *   objective = 1/2 ||y - D_s c||^2 + tau ||c||_1 (eq. (8) with the factor 1/2),
+ *   with D_s c read from DFT2(c) at the kept elements' bins.
+ *   KKT: g = D_s^H y - G c, e_l = |g_l - tau c_l/|c_l|| (c_l != 0) or
+ *   max(|g_l| - tau, 0) (c_l = 0); r_kkt = ||e||_2 / ||D_s^H y||_2,
+ *   max_e_over_tau = max_l e_l / tau.  Sums in FP64 over FP32 terms.
+ *   Any output pointer may be NULL.
+ */
+int bccb_objective_kkt(bccb_plan_t plan, const bccb_c32* y, float tau, const bccb_c32* c,
+                       double* objective, double* r_kkt, double* max_e_over_tau);
+
+/*
+ * bccb_profile_passes -- measured duration of one solver iteration's passes.
+ *   Launches `reps` column passes, then `reps` row passes, of `solver`
+ *   (0 = ISTA, 1 = FISTA, 2 = ADMM) back to back on the plan's stream over the
+ *   plan's own workspace (whatever it holds; outputs are discarded), each
+ *   group bracketed by hipEvents, and returns the average milliseconds per
+ *   launch.  reps >= 1.  Used for the live roofline figures of the benchmark.
+ */
+int bccb_profile_passes(bccb_plan_t plan, int solver, int reps, double* col_ms, double* row_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCCB_H */

@@ -1,0 +1,214 @@
+"""Thin ctypes binding of libbccb (include/bccb.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch tensors (complex64, CUDA/HIP device); torch provides memory
+and the current stream, nothing else.  Importing this module loads the library
+and raises if it has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbccb.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "bccb.h")
+
+BCCB_OK = 0
+BCCB_E_INVALID = -1
+BCCB_E_UNSUPPORTED = -2
+BCCB_E_NOMEM = -3
+BCCB_E_DEVICE = -4
+BCCB_E_NONFINITE = -5
+
+
+class BCCBError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {code})")
+        self.code = code
+
+
+class NonFiniteError(BCCBError):
+    pass
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    return ctypes.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_f = ctypes.c_float
+_d = ctypes.c_double
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi = ctypes.POINTER(ctypes.c_int)
+
+_SIGS = {
+    "bccb_status_string": (ctypes.c_char_p, [_i]),
+    "bccb_plan": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
+    "bccb_plan_destroy": (_i, [_vp]),
+    "bccb_set_stream": (_i, [_vp, _vp]),
+    "bccb_plan_info": (_i, [_vp, _pi, _pd, _vp]),
+    "bccb_adjoint": (_i, [_vp, _vp, _vp]),
+    "bccb_adjoint_maxabs": (_i, [_vp, _vp, _pd]),
+    "bccb_gram_apply": (_i, [_vp, _vp, _vp]),
+    "lasso_solve_ista": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
+    "lasso_solve_fista": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
+    "lasso_solve_admm": (_i, [_vp, _vp, _f, _f, _i, _vp, _vp]),
+    "bccb_objective_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd, _pd]),
+    "bccb_profile_passes": (_i, [_vp, _i, _i, _pd, _pd]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions declared in include/bccb.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)))
+
+
+def status_string(code: int) -> str:
+    return lib.bccb_status_string(code).decode()
+
+
+def check(code: int, where: str) -> int:
+    if code == BCCB_E_NONFINITE:
+        raise NonFiniteError(code, where, status_string(code))
+    if code < 0:
+        raise BCCBError(code, where, status_string(code))
+    return code
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dtype != torch.complex64:
+        raise TypeError(f"expected complex64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def current_stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A per-geometry plan: mask (uint8 [M2][M1]) and grid size L1 x L2."""
+
+    def __init__(self, mask, L1: int, L2: int, stream: int | None = None):
+        mask = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+        if mask.ndim != 2:
+            raise ValueError("mask must be 2-D [M2][M1]")
+        self.mask = mask
+        self.M2, self.M1 = mask.shape
+        self.L1, self.L2 = int(L1), int(L2)
+        self.L = self.L1 * self.L2
+        self._h = _vp()
+        s = current_stream() if stream is None else stream
+        check(lib.bccb_plan(mask.ctypes.data, self.M1, self.M2, self.L1, self.L2, s, ctypes.byref(self._h)),
+              "bccb_plan")
+        M = ctypes.c_int()
+        mu = ctypes.c_double()
+        check(lib.bccb_plan_info(self._h, ctypes.byref(M), ctypes.byref(mu), None), "bccb_plan_info")
+        self.M = M.value
+        self.mu = mu.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib.bccb_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream: int):
+        check(lib.bccb_set_stream(self._h, stream), "bccb_set_stream")
+
+    def omega(self) -> np.ndarray:
+        out = np.empty((self.L2, self.L1), dtype=np.float32)
+        check(lib.bccb_plan_info(self._h, None, None, out.ctypes.data), "bccb_plan_info")
+        return out
+
+    def grid(self, device="cuda") -> torch.Tensor:
+        return torch.empty((self.L2, self.L1), dtype=torch.complex64, device=device)
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.grid(y.device) if out is None else out
+        check(lib.bccb_adjoint(self._h, _ptr(y), _ptr(out)), "bccb_adjoint")
+        return out
+
+    def adjoint_maxabs(self, y: torch.Tensor) -> float:
+        m = ctypes.c_double()
+        check(lib.bccb_adjoint_maxabs(self._h, _ptr(y), ctypes.byref(m)), "bccb_adjoint_maxabs")
+        return m.value
+
+    def gram_apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.grid(x.device) if out is None else out
+        check(lib.bccb_gram_apply(self._h, _ptr(x), _ptr(out)), "bccb_gram_apply")
+        return out
+
+    def ista(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
+        out = self.grid(y.device) if out is None else out
+        check(lib.lasso_solve_ista(self._h, _ptr(y), float(tau), int(iters), _ptr(c0), _ptr(out)),
+              "lasso_solve_ista")
+        return out
+
+    def fista(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
+        out = self.grid(y.device) if out is None else out
+        check(lib.lasso_solve_fista(self._h, _ptr(y), float(tau), int(iters), _ptr(c0), _ptr(out)),
+              "lasso_solve_fista")
+        return out
+
+    def admm(self, y, tau: float, rho: float, iters: int, z_out=None, c_out=None, want_c=False):
+        z_out = self.grid(y.device) if z_out is None else z_out
+        if want_c and c_out is None:
+            c_out = self.grid(y.device)
+        check(lib.lasso_solve_admm(self._h, _ptr(y), float(tau), float(rho), int(iters), _ptr(z_out),
+                                   _ptr(c_out)), "lasso_solve_admm")
+        return (z_out, c_out) if want_c else z_out
+
+    def objective_kkt(self, y, tau: float, c) -> tuple[float, float, float]:
+        obj, r, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib.bccb_objective_kkt(self._h, _ptr(y), float(tau), _ptr(c), ctypes.byref(obj), ctypes.byref(r),
+                                     ctypes.byref(mx)), "bccb_objective_kkt")
+        return obj.value, r.value, mx.value
+
+
+    def profile_passes(self, solver: str, reps: int = 200) -> tuple[float, float]:
+        """Average ms per launch of (column pass, row pass) of one iteration of `solver`."""
+        code = {"ista": 0, "fista": 1, "admm": 2}[solver]
+        col, row = ctypes.c_double(), ctypes.c_double()
+        check(lib.bccb_profile_passes(self._h, code, int(reps), ctypes.byref(col), ctypes.byref(row)),
+              "bccb_profile_passes")
+        return col.value, row.value
+
+
+def to_device(y: np.ndarray, device="cuda") -> torch.Tensor:
+    """complex64 numpy array -> contiguous complex64 device tensor."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(y, dtype=np.complex64))).to(device)

@@ -1,0 +1,458 @@
+// C ABI of libbccb: argument checks, plans, and the solver drivers that
+// enqueue the row/column passes (see include/bccb.h for the contract).
+#include "bccb.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "plan_internal.h"
+#include "plan_math.h"
+
+using bccb::ColArgs;
+using bccb::RowArgs;
+
+namespace bccb {
+
+bool is_pow2_in_range(int L) { return L >= 8 && L <= 1024 && (L & (L - 1)) == 0; }
+
+int check_geometry(const uint8_t* mask, int M1, int M2, int L1, int L2) {
+  if (!mask || M1 < 1 || M2 < 1 || M1 > 4096 || M2 > 4096 || L1 <= 0 || L2 <= 0) return BCCB_E_INVALID;
+  if (!is_pow2_in_range(L1) || !is_pow2_in_range(L2)) return BCCB_E_UNSUPPORTED;
+  long kept = 0;
+  for (long i = 0; i < static_cast<long>(M1) * M2; ++i) kept += mask[i] != 0;
+  if (kept == 0) return BCCB_E_INVALID;
+  return BCCB_OK;
+}
+
+template <typename T>
+static int dmalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return BCCB_E_NOMEM;
+  }
+  return BCCB_OK;
+}
+
+static void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void plan_free(bccb_plan_s* p) {
+  if (!p) return;
+  dfree(p->d_omega);
+  dfree(p->d_sensor_of);
+  dfree(p->d_sensors);
+  dfree(p->d_tw1);
+  dfree(p->d_tw2);
+  dfree(p->d_xy);
+  dfree(p->d_rhs);
+  dfree(p->d_state);
+  dfree(p->d_tmp);
+  dfree(p->d_coef);
+  dfree(p->d_red);
+  dfree(p->d_flag);
+  if (p->h_red) (void)hipHostFree(p->h_red);
+  if (p->h_flag) (void)hipHostFree(p->h_flag);
+  delete p;
+}
+
+#define BCCB_TRY(expr)              \
+  do {                              \
+    const int _rc = (expr);         \
+    if (_rc != BCCB_OK) return _rc; \
+  } while (0)
+#define BCCB_HIP(expr)                                  \
+  do {                                                  \
+    if ((expr) != hipSuccess) return BCCB_E_DEVICE;     \
+  } while (0)
+
+static int kern(int rc) { return rc == 0 ? BCCB_OK : (rc == -2 ? BCCB_E_UNSUPPORTED : BCCB_E_DEVICE); }
+
+// --- pass helpers on one plan ------------------------------------------------
+int row_pass(bccb_plan_s* p, int mode, RowArgs a) {
+  a.tw = p->d_tw1;
+  a.nrows = p->L2;
+  a.rows_per_scene = p->L2;
+  return kern(launch_row(p->L1, mode, a, p->stream));
+}
+
+int col_pass(bccb_plan_s* p, int mode, float2* xy, const float2* coef, float rho, float scale) {
+  ColArgs a;
+  a.xy = xy;
+  a.omega = p->d_omega;
+  a.coef = coef;
+  a.tw = p->d_tw2;
+  a.L1 = p->L1;
+  a.nscenes = 1;
+  a.rho = rho;
+  a.scale = scale;
+  return kern(launch_col(p->L2, mode, a, p->stream));
+}
+
+// b (or scale*b) = D_s^H y into dst, using p->d_tmp as the spectral scratch.
+int adjoint_into(bccb_plan_s* p, const float2* y, float scale, float2* dst) {
+  BCCB_TRY(kern(launch_scatter(y, p->d_sensor_of, p->M1, p->M2, p->L1, p->L2, scale, p->d_tmp, p->d_flag,
+                               p->stream)));
+  BCCB_TRY(col_pass(p, COL_INV, p->d_tmp, nullptr, 0.f, 1.f));
+  RowArgs a;
+  a.xy = p->d_tmp;
+  a.dst = dst;
+  a.scale = 1.f;
+  return row_pass(p, ROW_INV, a);
+}
+
+int begin_call(bccb_plan_s* p) {
+  BCCB_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), p->stream));
+  return BCCB_OK;
+}
+
+// Drain the stream and report a non-finite input seen by any pass.
+int end_call(bccb_plan_s* p) {
+  BCCB_HIP(hipMemcpyAsync(p->h_flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  BCCB_HIP(hipStreamSynchronize(p->stream));
+  return *p->h_flag ? BCCB_E_NONFINITE : BCCB_OK;
+}
+
+}  // namespace bccb
+
+using namespace bccb;
+
+extern "C" {
+
+const char* bccb_status_string(int status) {
+  switch (status) {
+    case BCCB_OK: return "BCCB_OK";
+    case BCCB_E_INVALID: return "BCCB_E_INVALID: invalid argument";
+    case BCCB_E_UNSUPPORTED: return "BCCB_E_UNSUPPORTED: unsupported size or option";
+    case BCCB_E_NOMEM: return "BCCB_E_NOMEM: device allocation failed";
+    case BCCB_E_DEVICE: return "BCCB_E_DEVICE: HIP runtime error";
+    case BCCB_E_NONFINITE: return "BCCB_E_NONFINITE: NaN or Inf in the input";
+    default: return "unknown bccb status";
+  }
+}
+
+int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream, bccb_plan_t* out) {
+  if (!out) return BCCB_E_INVALID;
+  *out = nullptr;
+  BCCB_TRY(check_geometry(mask, M1, M2, L1, L2));
+
+  bccb_plan_s* p = new (std::nothrow) bccb_plan_s();
+  if (!p) return BCCB_E_NOMEM;
+  p->M1 = M1;
+  p->M2 = M2;
+  p->L1 = L1;
+  p->L2 = L2;
+  p->L = static_cast<long>(L1) * L2;
+  p->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return BCCB_E_DEVICE;
+  }
+
+  // sensors in increasing m1 + m2*M1 (rows of Psi, eq. (6))
+  std::vector<int> sensor_of(static_cast<size_t>(M1) * M2, -1);
+  std::vector<int2> sensors;
+  for (int m2 = 0; m2 < M2; ++m2)
+    for (int m1 = 0; m1 < M1; ++m1)
+      if (mask[static_cast<size_t>(m2) * M1 + m1]) {
+        sensor_of[static_cast<size_t>(m2) * M1 + m1] = static_cast<int>(sensors.size());
+        sensors.push_back(make_int2(m1, m2));
+      }
+  p->M = static_cast<int>(sensors.size());
+
+  // eigenvalues (eq. (21)) in FP64 from the first column of the Gram
+  const std::vector<cd> r = gram_first_column(mask, M1, M2, L1, L2);
+  const std::vector<cd> om = eigenvalues_eq21(r, L1, L2);
+  p->omega32.resize(p->L);
+  double omax = 0.0;
+  for (long i = 0; i < p->L; ++i) {
+    const double v = om[i].real();  // G is Hermitian, so Omega is real (imaginary part is rounding)
+    p->omega32[i] = static_cast<float>(v);
+    if (v > omax) omax = v;
+  }
+  p->mu = 1.0 / omax;  // sigma_max(D_s)^2 = lambda_max(G) = max Omega
+
+  std::vector<float2> tw1(L1), tw2(L2);
+  {
+    const std::vector<cd> w1 = unit_roots(L1), w2 = unit_roots(L2);
+    for (int j = 0; j < L1; ++j) tw1[j] = make_float2(static_cast<float>(w1[j].real()), static_cast<float>(w1[j].imag()));
+    for (int j = 0; j < L2; ++j) tw2[j] = make_float2(static_cast<float>(w2[j].real()), static_cast<float>(w2[j].imag()));
+  }
+  const double invL = 1.0 / static_cast<double>(p->L);
+  const float2 coef[2] = {make_float2(static_cast<float>(invL), static_cast<float>(-p->mu * invL)),
+                          make_float2(0.f, static_cast<float>(invL))};
+
+  int rc = BCCB_OK;
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_omega, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sensor_of, sensor_of.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sensors, sensors.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_tw1, L1);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_tw2, L2);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_xy, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_rhs, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_state, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_tmp, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_red, static_cast<size_t>(kReduceBlocks) * 8);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_flag, 1);
+  if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_red), kReduceBlocks * 8 * sizeof(double)) != hipSuccess)
+    rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_flag), sizeof(int)) != hipSuccess) rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK) {
+    const bool ok =
+        hipMemcpy(p->d_omega, p->omega32.data(), p->L * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(p->d_sensor_of, sensor_of.data(), sensor_of.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(p->d_sensors, sensors.data(), sensors.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(p->d_tw1, tw1.data(), L1 * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(p->d_tw2, tw2.data(), L2 * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+        hipMemcpy(p->d_coef, coef, sizeof(coef), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) rc = BCCB_E_DEVICE;
+  }
+  if (rc != BCCB_OK) {
+    plan_free(p);
+    return rc;
+  }
+  *out = p;
+  return BCCB_OK;
+}
+
+int bccb_plan_destroy(bccb_plan_t plan) {
+  if (plan) {
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  plan_free(plan);
+  return BCCB_OK;
+}
+
+int bccb_set_stream(bccb_plan_t plan, void* stream) {
+  if (!plan) return BCCB_E_INVALID;
+  plan->stream = static_cast<hipStream_t>(stream);
+  return BCCB_OK;
+}
+
+int bccb_plan_info(bccb_plan_t plan, int* M, double* mu, float* omega_host) {
+  if (!plan) return BCCB_E_INVALID;
+  if (M) *M = plan->M;
+  if (mu) *mu = plan->mu;
+  if (omega_host) std::memcpy(omega_host, plan->omega32.data(), plan->L * sizeof(float));
+  return BCCB_OK;
+}
+
+int bccb_adjoint(bccb_plan_t p, const bccb_c32* y, bccb_c32* b) {
+  if (!p || !y || !b) return BCCB_E_INVALID;
+  BCCB_TRY(begin_call(p));
+  BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), 1.f, reinterpret_cast<float2*>(b)));
+  return end_call(p);
+}
+
+int bccb_adjoint_maxabs(bccb_plan_t p, const bccb_c32* y, double* maxabs) {
+  if (!p || !y || !maxabs) return BCCB_E_INVALID;
+  BCCB_TRY(begin_call(p));
+  BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), 1.f, p->d_rhs));
+  int nb = 0;
+  BCCB_TRY(kern(launch_absmax(p->d_rhs, p->L, p->d_red, &nb, p->stream)));
+  BCCB_HIP(hipMemcpyAsync(p->h_red, p->d_red, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  const int rc = end_call(p);
+  double m = 0.0;
+  for (int i = 0; i < nb; ++i) m = p->h_red[i] > m ? p->h_red[i] : m;
+  *maxabs = m;
+  return rc;
+}
+
+int bccb_gram_apply(bccb_plan_t p, const bccb_c32* x, bccb_c32* gx) {
+  if (!p || !x || !gx) return BCCB_E_INVALID;
+  BCCB_TRY(begin_call(p));
+  RowArgs a;
+  a.xy = p->d_xy;
+  a.src = reinterpret_cast<const float2*>(x);
+  BCCB_TRY(row_pass(p, ROW_FWD, a));
+  BCCB_TRY(col_pass(p, COL_FILTER_AFFINE, p->d_xy, p->d_coef + 1, 0.f, 1.f));
+  RowArgs b;
+  b.xy = p->d_xy;
+  b.dst = reinterpret_cast<float2*>(gx);
+  BCCB_TRY(row_pass(p, ROW_INV, b));
+  return end_call(p);
+}
+
+static int check_solve(bccb_plan_t p, const bccb_c32* y, float tau, int iters, const void* out) {
+  if (!p || !y || !out) return BCCB_E_INVALID;
+  if (!(tau >= 0.f) || !std::isfinite(tau) || iters < 0) return BCCB_E_INVALID;
+  return BCCB_OK;
+}
+
+// ISTA (mode ROW_ISTA) and FISTA (ROW_FISTA) share one driver.
+static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau, int iters, const bccb_c32* c0,
+                           bccb_c32* c_out) {
+  BCCB_TRY(check_solve(p, y, tau, iters, c_out));
+  float2* out = reinterpret_cast<float2*>(c_out);
+  const float2* init = reinterpret_cast<const float2*>(c0);
+  BCCB_TRY(begin_call(p));
+  // mu * D_s^H y
+  BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
+  // z^(1) = c^(0): its row DFT starts the first column pass; FISTA keeps c^(t-1) in c_out
+  RowArgs f;
+  f.xy = p->d_xy;
+  f.src = init;
+  f.flag = p->d_flag;
+  BCCB_TRY(row_pass(p, ROW_FWD, f));
+  if (mode == ROW_FISTA || iters == 0) {
+    if (init && init != out) BCCB_TRY(kern(launch_copy(out, init, p->L, p->stream)));
+    else if (!init) BCCB_TRY(kern(launch_fill(out, p->L, p->stream)));
+  }
+  const float kappa = static_cast<float>(p->mu * tau);
+  double alpha = 1.0;
+  for (int t = 1; t <= iters; ++t) {
+    BCCB_TRY(col_pass(p, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f));
+    const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    RowArgs a;
+    a.xy = p->d_xy;
+    a.rhs = p->d_rhs;
+    a.state = out;
+    a.out_c = out;
+    a.kappa = kappa;
+    a.beta = static_cast<float>((alpha - 1.0) / alpha_next);
+    a.last = (t == iters);
+    alpha = alpha_next;
+    BCCB_TRY(row_pass(p, mode, a));
+  }
+  return end_call(p);
+}
+
+int lasso_solve_ista(bccb_plan_t p, const bccb_c32* y, float tau, int iters, const bccb_c32* c0, bccb_c32* c_out) {
+  return solve_prox_grad(p, ROW_ISTA, y, tau, iters, c0, c_out);
+}
+
+int lasso_solve_fista(bccb_plan_t p, const bccb_c32* y, float tau, int iters, const bccb_c32* c0, bccb_c32* c_out) {
+  return solve_prox_grad(p, ROW_FISTA, y, tau, iters, c0, c_out);
+}
+
+int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int iters, bccb_c32* z_out,
+                     bccb_c32* c_out) {
+  BCCB_TRY(check_solve(p, y, tau, iters, z_out));
+  if (!(rho > 0.f) || !std::isfinite(rho)) return BCCB_E_INVALID;
+  float2* zo = reinterpret_cast<float2*>(z_out);
+  float2* co = reinterpret_cast<float2*>(c_out);
+  BCCB_TRY(begin_call(p));
+  // w = (G + rho I)^-1 D_s^H y: the scattered snapshot is already spectral, so
+  // w = IDFT2(S / (Omega + rho)) (unnormalised, since DFT2(b) = L S)
+  BCCB_TRY(kern(launch_scatter(reinterpret_cast<const float2*>(y), p->d_sensor_of, p->M1, p->M2, p->L1, p->L2, 1.f,
+                               p->d_tmp, p->d_flag, p->stream)));
+  BCCB_TRY(col_pass(p, COL_MULINV_ADMM, p->d_tmp, nullptr, rho, 1.f));
+  {
+    RowArgs a;
+    a.xy = p->d_tmp;
+    a.dst = p->d_rhs;
+    BCCB_TRY(row_pass(p, ROW_INV, a));
+  }
+  BCCB_TRY(kern(launch_fill(p->d_state, p->L, p->stream)));  // v^(0) = 0
+  BCCB_TRY(kern(launch_fill(p->d_xy, p->L, p->stream)));     // DFT_rows(z^(0) - v^(0)) = 0
+  if (iters == 0) {
+    BCCB_TRY(kern(launch_fill(zo, p->L, p->stream)));
+    if (co) BCCB_TRY(kern(launch_fill(co, p->L, p->stream)));
+  }
+  const float scale = static_cast<float>(static_cast<double>(rho) / static_cast<double>(p->L));
+  for (int t = 1; t <= iters; ++t) {
+    BCCB_TRY(col_pass(p, COL_FILTER_ADMM, p->d_xy, nullptr, rho, scale));
+    RowArgs a;
+    a.xy = p->d_xy;
+    a.rhs = p->d_rhs;
+    a.state = p->d_state;
+    a.out_z = zo;
+    a.out_c = co;
+    a.kappa = tau / rho;
+    a.last = (t == iters);
+    BCCB_TRY(row_pass(p, ROW_ADMM, a));
+  }
+  return end_call(p);
+}
+
+int bccb_objective_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c32* c, double* objective,
+                       double* r_kkt, double* max_e_over_tau) {
+  if (!p || !y || !c) return BCCB_E_INVALID;
+  if (!(tau >= 0.f) || !std::isfinite(tau)) return BCCB_E_INVALID;
+  const float2* cc = reinterpret_cast<const float2*>(c);
+  BCCB_TRY(begin_call(p));
+  // spec = DFT2(c); D_s c = (-1)^(m1+m2) spec at the kept elements' bins
+  RowArgs f;
+  f.xy = p->d_xy;
+  f.src = cc;
+  f.flag = p->d_flag;
+  BCCB_TRY(row_pass(p, ROW_FWD, f));
+  BCCB_TRY(col_pass(p, COL_FWD, p->d_xy, nullptr, 0.f, 1.f));
+  int nb_r = 0, nb_k = 0;
+  double* part_r = p->d_red;
+  double* part_k = p->d_red + kReduceBlocks;
+  BCCB_TRY(kern(launch_resid(p->d_xy, reinterpret_cast<const float2*>(y), p->d_sensors, p->M, p->L1, p->L2, part_r,
+                             &nb_r, p->stream)));
+  // G c = IDFT2(Omega/L . spec)
+  BCCB_TRY(col_pass(p, COL_MULINV_AFFINE, p->d_xy, p->d_coef + 1, 0.f, 1.f));
+  {
+    RowArgs a;
+    a.xy = p->d_xy;
+    a.dst = p->d_state;
+    BCCB_TRY(row_pass(p, ROW_INV, a));
+  }
+  BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), 1.f, p->d_rhs));
+  BCCB_TRY(kern(launch_kkt(cc, p->d_rhs, p->d_state, tau, p->L, part_k, &nb_k, p->stream)));
+  BCCB_HIP(hipMemcpyAsync(p->h_red, p->d_red, kReduceBlocks * 5 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  const int rc = end_call(p);
+  double rs = 0.0, e2 = 0.0, emax = 0.0, l1 = 0.0, b2 = 0.0;
+  for (int i = 0; i < nb_r; ++i) rs += p->h_red[i];
+  const double* hk = p->h_red + kReduceBlocks;
+  for (int i = 0; i < nb_k; ++i) {
+    e2 += hk[4 * i + 0];
+    emax = hk[4 * i + 1] > emax ? hk[4 * i + 1] : emax;
+    l1 += hk[4 * i + 2];
+    b2 += hk[4 * i + 3];
+  }
+  if (objective) *objective = 0.5 * rs + static_cast<double>(tau) * l1;
+  if (r_kkt) *r_kkt = b2 > 0.0 ? std::sqrt(e2) / std::sqrt(b2) : std::sqrt(e2);
+  if (max_e_over_tau) *max_e_over_tau = tau > 0.f ? emax / tau : emax;
+  return rc;
+}
+
+int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, double* row_ms) {
+  if (!p || reps < 1 || solver < 0 || solver > 2 || !col_ms || !row_ms) return BCCB_E_INVALID;
+  hipEvent_t e0, e1, e2;
+  BCCB_HIP(hipEventCreate(&e0));
+  BCCB_HIP(hipEventCreate(&e1));
+  BCCB_HIP(hipEventCreate(&e2));
+  int rc = BCCB_OK;
+  RowArgs a;
+  a.xy = p->d_xy;
+  a.rhs = p->d_rhs;
+  a.state = p->d_state;
+  a.out_z = p->d_tmp;
+  a.out_c = p->d_tmp;
+  a.kappa = 1.f;
+  a.beta = 0.5f;
+  const int row_mode = solver == 0 ? ROW_ISTA : (solver == 1 ? ROW_FISTA : ROW_ADMM);
+  const int col_mode = solver == 2 ? COL_FILTER_ADMM : COL_FILTER_AFFINE;
+  const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
+  if (hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+  for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = col_pass(p, col_mode, p->d_xy, p->d_coef, 1.f, scale);
+  if (rc == BCCB_OK && hipEventRecord(e1, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+  for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass(p, row_mode, a);
+  if (rc == BCCB_OK && hipEventRecord(e2, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+  if (rc == BCCB_OK && hipEventSynchronize(e2) != hipSuccess) rc = BCCB_E_DEVICE;
+  float m01 = 0.f, m12 = 0.f;
+  if (rc == BCCB_OK && (hipEventElapsedTime(&m01, e0, e1) != hipSuccess ||
+                        hipEventElapsedTime(&m12, e1, e2) != hipSuccess))
+    rc = BCCB_E_DEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  *col_ms = m01 / reps;
+  *row_ms = m12 / reps;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: per Gram product rel <= 1e-4 (L2 norm); solver objectives rel <= 1e-5
+against the oracle trajectory at the same iteration count.  Every comparison
+also prints the error against FP64 (eps_r = ||c_gpu - c_oracle|| / ||c_oracle||).
+"""
+import numpy as np
+import pytest
+
+from oracle import bccb_oracle as O
+from paper_2509_13592_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+B = pytest.importorskip("paper_2509_13592_amd.bccb")
+
+MATVEC_TOL = 1e-4
+OBJ_TOL = 1e-5
+
+
+def _np(t):
+    return t.detach().cpu().numpy().reshape(-1).astype(np.complex128)
+
+
+def _crandn(seed, n):
+    r = np.random.default_rng(seed)
+    return (r.standard_normal(n) + 1j * r.standard_normal(n)).astype(np.complex64)
+
+
+def _fold(mask, L1, L2):
+    P = np.zeros((L2, L1))
+    for m1, m2 in O.sensors(mask):
+        P[m2 % L2, m1 % L1] += 1
+    return P
+
+
+# grids spanning every supported transform length, square and rectangular
+GRIDS = [(8, 8), (16, 32), (32, 32), (64, 16), (128, 128), (256, 256), (512, 64), (1024, 8), (8, 1024),
+         (1024, 1024)]
+
+
+def _geom_scene(L1, L2, seed=0):
+    M1 = min(L1, 12)
+    M2 = min(L2, 9)
+    kept = max(1, (M1 * M2) // 2)
+    return S.custom_scene(M1, M2, kept, L1, L2, K=3, snr_db=20, seed=(11, seed, L1 * 7 + L2))
+
+
+@pytest.mark.parametrize("L1,L2", GRIDS)
+def test_plan_eigenvalues(L1, L2):
+    sc = _geom_scene(L1, L2)
+    print(f"case plan L1={L1} L2={L2}", flush=True)
+    plan = B.Plan(sc.mask, L1, L2)
+    om = plan.omega().astype(np.float64)
+    want = L1 * L2 * _fold(sc.mask, L1, L2)
+    assert np.abs(om - want).max() <= 1e-6 * L1 * L2
+    assert plan.M == int(sc.mask.sum())
+    assert abs(plan.mu * want.max() - 1.0) < 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("L1,L2", GRIDS)
+def test_gram_apply_matches_oracle(L1, L2):
+    sc = _geom_scene(L1, L2)
+    print(f"case gram L1={L1} L2={L2}", flush=True)
+    op = O.Operator(sc.mask, L1, L2)
+    plan = B.Plan(sc.mask, L1, L2)
+    for seed in (0, 1):
+        x = _crandn(seed, L1 * L2)
+        gx = _np(plan.gram_apply(B.to_device(x.reshape(L2, L1))))
+        ref = op.gram(x.astype(np.complex128))
+        rel = np.linalg.norm(gx - ref) / np.linalg.norm(ref)
+        print(f"  rel matvec error vs FP64 = {rel:.2e}")
+        assert rel <= MATVEC_TOL
+    # structured inputs: an impulse (gives the first column r of G) and a single Fourier mode
+    e0 = np.zeros(L1 * L2, np.complex64)
+    e0[0] = 1
+    r = _np(plan.gram_apply(B.to_device(e0.reshape(L2, L1))))
+    ref = op.gram(e0.astype(np.complex128))
+    assert np.linalg.norm(r - ref) <= MATVEC_TOL * np.linalg.norm(ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("L1,L2", GRIDS)
+def test_adjoint_matches_oracle(L1, L2):
+    sc = _geom_scene(L1, L2)
+    op = O.Operator(sc.mask, L1, L2)
+    plan = B.Plan(sc.mask, L1, L2)
+    y = B.to_device(sc.y)
+    b = _np(plan.adjoint(y))
+    ref = op.adjoint(sc.y.astype(np.complex128))
+    assert np.linalg.norm(b - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert abs(plan.adjoint_maxabs(y) - np.abs(ref).max()) <= 1e-5 * np.abs(ref).max()
+    plan.close()
+
+
+def _solver_parity(sc, iters, rho=1.0, solvers=("ista", "fista", "admm"), dense=None):
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=dense)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    out = {}
+    for name in solvers:
+        print(f"case {name} L1={sc.L1} L2={sc.L2} iters={iters}", flush=True)
+        if name == "ista":
+            g = _np(plan.ista(y, P.tau, iters))
+            ref = P.ista(iters)
+        elif name == "fista":
+            g = _np(plan.fista(y, P.tau, iters))
+            ref = P.fista(iters)
+        else:
+            g = _np(plan.admm(y, P.tau, rho, iters))
+            ref = P.admm(rho, iters)[0]
+        Fg, Fr = P.objective(g), P.objective(ref)
+        rel = abs(Fg - Fr) / abs(Fr)
+        nref = np.linalg.norm(ref)
+        eps = np.linalg.norm(g - ref) / nref if nref > 0 else np.linalg.norm(g)
+        print(f"  {name}: F_gpu={Fg:.9g} F_fp64={Fr:.9g} rel F={rel:.2e} eps_r={eps:.2e}")
+        assert rel <= OBJ_TOL, (name, rel)
+        out[name] = (g, ref, P)
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_tiny_config_solvers(idx):
+    """8x8 URA, 32 kept, 32x32 grid, 200 iterations (the tiny workload)."""
+    _solver_parity(S.tiny_scene(idx), 200)
+
+
+def test_ragged_rectangular_solvers():
+    sc = S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(12, 0, 0))
+    _solver_parity(sc, 120, rho=4.0)
+
+
+def test_aliasing_geometry_solvers():
+    """M1 > L1: several elements fold onto one bin; eq. (21) still gives the spectrum."""
+    sc = S.custom_scene(20, 6, 40, 16, 8, K=2, snr_db=20, seed=(13, 0, 0))
+    _solver_parity(sc, 100, rho=64.0)
+
+
+def test_paper_scale_solvers():
+    """16x16 URA, 64 kept, 256x256 grid, 500 iterations of ISTA, FISTA and ADMM (rho = 1)."""
+    _solver_parity(S.paper_scale_scene(0), 500, rho=1.0)
+
+
+def test_large_grid_admm():
+    """32x32 URA, 256 kept, 1024x1024 grid, ADMM rho = 0.5, 300 iterations (oracle: Woodbury)."""
+    _solver_parity(S.large_admm_scene(0), 300, rho=0.5, solvers=("admm",))
+
+
+def test_objective_and_kkt_match_oracle():
+    sc = S.paper_scale_scene(1)
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    c = plan.fista(y, P.tau, 300)
+    cn = _np(c)
+    obj, r, mx = plan.objective_kkt(y, P.tau, c)
+    r_ref, mx_ref = P.kkt(cn)
+    F_ref = P.objective(cn)
+    print(f"objective {obj:.9g} vs {F_ref:.9g}; r_kkt {r:.4e} vs {r_ref:.4e}; max e/tau {mx:.3e} vs {mx_ref:.3e}")
+    assert abs(obj - F_ref) <= 1e-6 * F_ref
+    assert abs(r - r_ref) <= 2e-2 * r_ref + 1e-6
+    plan.close()
+
+
+def test_edge_cases():
+    sc = S.tiny_scene(3)
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    # iters = 0 returns the warm start, or zeros
+    c0 = B.to_device(_crandn(5, plan.L).reshape(plan.L2, plan.L1))
+    assert torch.equal(plan.fista(y, P.tau, 0, c0=c0), c0)
+    assert torch.count_nonzero(plan.ista(y, P.tau, 0)) == 0
+    assert torch.count_nonzero(plan.admm(y, P.tau, 1.0, 0)) == 0
+    # tau >= max|A^H y| gives exactly zero
+    big = 1.01 * plan.adjoint_maxabs(y)
+    for c in (plan.ista(y, big, 20), plan.fista(y, big, 20), plan.admm(y, big, 64.0, 20)):
+        assert torch.count_nonzero(c) == 0
+    # ISTA warm start: 40 + 60 iterations equal 100 (ISTA is memoryless)
+    c40 = plan.ista(y, P.tau, 40)
+    c100a = _np(plan.ista(y, P.tau, 60, c0=c40))
+    c100b = _np(plan.ista(y, P.tau, 100))
+    assert np.abs(c100a - c100b).max() <= 1e-5 * np.abs(c100b).max()
+    # warm start against the oracle
+    c0n = _np(c40)
+    ref = P.ista(60, c0=c0n)
+    assert abs(P.objective(c100a) - P.objective(ref)) <= OBJ_TOL * P.objective(ref)
+    # determinism: same inputs, bitwise equal outputs
+    a = plan.fista(y, P.tau, 50)
+    b = plan.fista(y, P.tau, 50)
+    assert torch.equal(a, b)
+    # non-finite snapshot is reported
+    ybad = y.clone()
+    ybad[3] = complex(float("nan"), 0.0)
+    with pytest.raises(B.NonFiniteError):
+        plan.fista(ybad, P.tau, 5)
+    c0bad = c0.clone()
+    c0bad[0, 0] = complex(float("inf"), 0.0)
+    with pytest.raises(B.NonFiniteError):
+        plan.ista(y, P.tau, 5, c0=c0bad)
+    # host-side argument checks
+    with pytest.raises(B.BCCBError):
+        plan.fista(y, -1.0, 5)
+    with pytest.raises(B.BCCBError):
+        plan.admm(y, P.tau, 0.0, 5)
+    with pytest.raises(B.BCCBError):
+        plan.ista(y, P.tau, -3)
+    plan.close()
+
+
+def test_full_ura_one_step_exact():
+    """M_i = L_i: G = L I, ISTA reaches the closed-form minimiser S_{tau/L}(b/L) in one step."""
+    mask = np.ones((16, 16), np.uint8)
+    sc = S.custom_scene(16, 16, 256, 16, 16, K=3, snr_db=20, seed=(14, 0, 0), mask=mask)
+    P = O.Problem(mask, 16, 16, sc.y)
+    plan = B.Plan(mask, 16, 16)
+    y = B.to_device(sc.y)
+    c1 = _np(plan.ista(y, P.tau, 1))
+    c5 = _np(plan.ista(y, P.tau, 5))
+    star = O.soft_threshold(P.b / 256, P.tau / 256)
+    assert np.linalg.norm(c1 - star) <= 1e-5 * np.linalg.norm(star)
+    assert np.linalg.norm(c5 - star) <= 1e-5 * np.linalg.norm(star)
+    plan.close()
