@@ -62,6 +62,58 @@ def cpu_baseline(sc, tau, budget_s=12.0):
             "sample": f"{n} FP64 FISTA iterations on the 256x256 scene (factored D_s^H D_s, numpy)"}
 
 
+def _batch_rate(B, scenes, iters, reps, tune=True):
+    """Build plans + a batch for `scenes`, solve `reps` times; returns (seconds per solve, info)."""
+    import numpy as np
+    import torch
+    plans = [B.Plan(sc.mask, sc.L1, sc.L2) for sc in scenes]
+    ys = [B.to_device(sc.y) for sc in scenes]
+    taus = [float(np.float32(0.1 * p.adjoint_maxabs(y))) for p, y in zip(plans, ys)]
+    batch = B.Batch(plans)
+    if tune:
+        batch.autotune(reps=5)
+    outs = batch.fista(ys, taus, iters)          # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.fista(ys, taus, iters, outs=outs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    classes = batch.classes()
+    batch.close()
+    for p in plans:
+        p.close()
+    return dt, classes
+
+
+def batched_runs(args):
+    """The uneven 4096-scene workload (FISTA 300 iterations, one graph launch per solve)
+    and a uniform batch of 1024 paper-scale 256^2 scenes (working set far above the caches)."""
+    from paper_2509_13592_amd import bccb as B
+    from paper_2509_13592_amd import scenes as S
+    out = {}
+    n = args.batch_scenes
+    scenes = [S.batched_scene(i) for i in range(n)]
+    pts = sum(sc.L1 * sc.L2 for sc in scenes)
+    iters = 300
+    dt, classes = _batch_rate(B, scenes, iters, reps=3)
+    algo = ALGO_BYTES_PER_POINT["fista"] * pts * iters
+    out["uneven"] = {"workload": f"{n} scenes, grids 64^2/128^2/256^2 mixed, own masks, FISTA {iters} iterations",
+                     "scenes_per_s": round(n / dt, 1), "scene_iters_per_s": round(n * iters / dt, 1),
+                     "s_per_solve": round(dt, 5), "classes": classes,
+                     "algorithmic_GBps": round(algo / dt / 1e9, 1),
+                     "frac_hbm_peak": round(algo / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    n2 = 1024
+    sc0 = [S.paper_scale_scene(i) for i in range(n2)]
+    dt2, _ = _batch_rate(B, sc0, 100, reps=3)
+    algo2 = ALGO_BYTES_PER_POINT["fista"] * 65536 * n2 * 100
+    out["uniform_256"] = {"workload": f"{n2} paper-scale 256^2 scenes, FISTA 100 iterations",
+                          "scene_iters_per_s": round(n2 * 100 / dt2, 1),
+                          "algorithmic_GBps": round(algo2 / dt2 / 1e9, 1),
+                          "frac_hbm_peak": round(algo2 / dt2 / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scenes", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the workloads are single-GPU by design; "
@@ -85,6 +139,7 @@ def main():
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     y = B.to_device(sc.y)
     tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    tuned = plan.autotune(reps=50)
     out = plan.grid()
     T = args.iters
     L = sc.L1 * sc.L2
@@ -127,7 +182,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "paper-scale single scene: 16x16 URA, 64 of 256 elements, L1=L2=256, "
                                "K=5, 20 dB, FISTA 500 iterations per step",
-                   "iters_per_step": T},
+                   "iters_per_step": T, "launch_config": tuned},
         "other_rates": {"ista_iters_per_s": round(side_steps * T / dt_i, 1),
                         "admm_iters_per_s": round(side_steps * T / dt_a, 1)},
         "roofline": {"bound": "hbm", "kernel": "fista iteration = column pass + row pass",
@@ -137,9 +192,11 @@ def main():
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
                      "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
     }
+    plan.close()
+    if not args.no_batch:
+        rec["batched"] = batched_runs(args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, tau)
-    plan.close()
     print(json.dumps(rec))
 
 

@@ -146,6 +146,77 @@ int bccb_objective_kkt(bccb_plan_t plan, const bccb_c32* y, float tau, const bcc
                        double* objective, double* r_kkt, double* max_e_over_tau);
 
 /*
+ * Batched solves -- many independent snapshots, each with its own plan (its
+ * own array mask and grid size; plans may repeat), solved together.
+ *
+ * bccb_batch_create groups the scenes by grid size (L1, L2) into classes and
+ * allocates, per class, contiguous device arenas for the iterates, the
+ * right-hand sides and the eigenvalue grids (copied from the plans).  Each
+ * solve then runs every class's column and row passes over all of its scenes
+ * at once, with the whole iteration loop captured in one hipGraph (replayed
+ * while `iters` repeats).  plans: host array of nscenes plan handles (they must
+ * outlive the batch); stream: hipStream_t.  Memory: about 24 bytes per grid
+ * point of every scene plus 4 for its eigenvalues.
+ */
+typedef struct bccb_batch_s* bccb_batch_t;
+
+int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_batch_t* out);
+int bccb_batch_destroy(bccb_batch_t batch);
+
+/* Number of size classes and, per class c < nclasses, its (L1, L2) and scene count. */
+int bccb_batch_info(bccb_batch_t batch, int* nclasses, int* L1, int* L2, int* count);
+
+/*
+ * lasso_solve_batch_fista -- `iters` FISTA iterations (as lasso_solve_fista,
+ *   from c^(0) = 0) on every scene of the batch.  y: host array of nscenes
+ *   device pointers (complex64 [M_s]); tau: host array of nscenes weights
+ *   (>= 0, finite); c_out: host array of nscenes device pointers
+ *   (complex64 [L2_s][L1_s]).  BCCB_E_NONFINITE if any snapshot holds NaN/Inf.
+ */
+int lasso_solve_batch_fista(bccb_batch_t batch, const bccb_c32* const* y, const float* tau, int iters,
+                            bccb_c32* const* c_out);
+
+/*
+ * bccb_batch_autotune -- per class, time the launchable row and column pass
+ *   shapes over the whole class (`reps` launches each) and keep the fastest.
+ */
+int bccb_batch_autotune(bccb_batch_t batch, int reps);
+
+/*
+ * Launch configuration of a plan's passes.  A length-L transform runs as a
+ * Stockham FFT over L/E threads holding E elements each; small E spreads one
+ * row or column over more threads (lower latency for a single scene), large
+ * E packs it into fewer threads (fewer LDS exchanges, better for batches).
+ *   row_elems, col_elems: E in {4, 8, 16, 32}, E <= L1 (rows) / L2 (columns);
+ *   row_rows_per_block: rows per workgroup, (L1/row_elems)*rows <= 256;
+ *   col_cols_per_block: columns per workgroup, divides L1, (L2/col_elems)*cols <= 256;
+ *   use_graph: 1 = capture each solve's iteration loop in a hipGraph (replayed
+ *   while the solve arguments repeat), 0 = launch every pass directly.
+ * The configuration changes timing only; results agree to FP32 rounding.
+ */
+typedef struct {
+  int row_elems;
+  int row_rows_per_block;
+  int col_elems;
+  int col_cols_per_block;
+  int use_graph;
+} bccb_config;
+
+/* Current configuration of a plan (a heuristic until set or tuned). */
+int bccb_plan_get_config(bccb_plan_t plan, bccb_config* cfg);
+
+/* Set a configuration; BCCB_E_INVALID if a pass shape cannot be launched. */
+int bccb_plan_set_config(bccb_plan_t plan, const bccb_config* cfg);
+
+/*
+ * bccb_plan_autotune -- time every launchable (E, rows per block) of the FISTA
+ *   row pass and every (E, columns per block) of the column pass on the plan's
+ *   workspace (`reps` launches each, hipEvents), keep the fastest, and return
+ *   it in *chosen (nullable).  use_graph is left as it was.
+ */
+int bccb_plan_autotune(bccb_plan_t plan, int reps, bccb_config* chosen);
+
+/*
  * bccb_profile_passes -- measured duration of one solver iteration's passes.
  *   Launches `reps` column passes, then `reps` row passes, of `solver`
  *   (0 = ISTA, 1 = FISTA, 2 = ADMM) back to back on the plan's stream over the

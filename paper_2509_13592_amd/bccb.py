@@ -26,6 +26,16 @@ BCCB_E_DEVICE = -4
 BCCB_E_NONFINITE = -5
 
 
+class Config(ctypes.Structure):
+    """bccb_config: launch shape of a plan's row and column passes."""
+    _fields_ = [("row_elems", ctypes.c_int), ("row_rows_per_block", ctypes.c_int),
+                ("col_elems", ctypes.c_int), ("col_cols_per_block", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BCCBError(RuntimeError):
     def __init__(self, code: int, where: str, msg: str):
         super().__init__(f"{where}: {msg} (status {code})")
@@ -67,6 +77,14 @@ _SIGS = {
     "lasso_solve_admm": (_i, [_vp, _vp, _f, _f, _i, _vp, _vp]),
     "bccb_objective_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd, _pd]),
     "bccb_profile_passes": (_i, [_vp, _i, _i, _pd, _pd]),
+    "bccb_plan_get_config": (_i, [_vp, _vp]),
+    "bccb_plan_set_config": (_i, [_vp, _vp]),
+    "bccb_plan_autotune": (_i, [_vp, _i, _vp]),
+    "bccb_batch_create": (_i, [_vp, _i, _vp, ctypes.POINTER(_vp)]),
+    "bccb_batch_destroy": (_i, [_vp]),
+    "bccb_batch_info": (_i, [_vp, _pi, _vp, _vp, _vp]),
+    "lasso_solve_batch_fista": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "bccb_batch_autotune": (_i, [_vp, _i]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -200,6 +218,23 @@ class Plan:
         return obj.value, r.value, mx.value
 
 
+    def get_config(self) -> dict:
+        c = Config()
+        check(lib.bccb_plan_get_config(self._h, ctypes.byref(c)), "bccb_plan_get_config")
+        return c.as_dict()
+
+    def set_config(self, **kw) -> dict:
+        cur = self.get_config()
+        cur.update(kw)
+        c = Config(**cur)
+        check(lib.bccb_plan_set_config(self._h, ctypes.byref(c)), "bccb_plan_set_config")
+        return self.get_config()
+
+    def autotune(self, reps: int = 50) -> dict:
+        c = Config()
+        check(lib.bccb_plan_autotune(self._h, int(reps), ctypes.byref(c)), "bccb_plan_autotune")
+        return c.as_dict()
+
     def profile_passes(self, solver: str, reps: int = 200) -> tuple[float, float]:
         """Average ms per launch of (column pass, row pass) of one iteration of `solver`."""
         code = {"ista": 0, "fista": 1, "admm": 2}[solver]
@@ -212,3 +247,49 @@ class Plan:
 def to_device(y: np.ndarray, device="cuda") -> torch.Tensor:
     """complex64 numpy array -> contiguous complex64 device tensor."""
     return torch.from_numpy(np.ascontiguousarray(np.asarray(y, dtype=np.complex64))).to(device)
+
+
+class Batch:
+    """Many independent scenes (each with its own Plan) solved together."""
+
+    def __init__(self, plans, stream: int | None = None):
+        self.plans = list(plans)
+        n = len(self.plans)
+        arr = (_vp * n)(*[p.handle for p in self.plans])
+        self._h = _vp()
+        s = current_stream() if stream is None else stream
+        check(lib.bccb_batch_create(arr, n, s, ctypes.byref(self._h)), "bccb_batch_create")
+        self.n = n
+
+    def close(self):
+        if self._h:
+            lib.bccb_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def classes(self):
+        nc = ctypes.c_int()
+        check(lib.bccb_batch_info(self._h, ctypes.byref(nc), None, None, None), "bccb_batch_info")
+        L1 = (ctypes.c_int * nc.value)()
+        L2 = (ctypes.c_int * nc.value)()
+        cnt = (ctypes.c_int * nc.value)()
+        check(lib.bccb_batch_info(self._h, ctypes.byref(nc), L1, L2, cnt), "bccb_batch_info")
+        return [(L1[i], L2[i], cnt[i]) for i in range(nc.value)]
+
+    def autotune(self, reps: int = 10):
+        check(lib.bccb_batch_autotune(self._h, int(reps)), "bccb_batch_autotune")
+
+    def fista(self, ys, taus, iters: int, outs=None):
+        n = self.n
+        if outs is None:
+            outs = [p.grid(ys[i].device) for i, p in enumerate(self.plans)]
+        ya = (_vp * n)(*[_ptr(t) for t in ys])
+        oa = (_vp * n)(*[_ptr(t) for t in outs])
+        ta = (ctypes.c_float * n)(*[float(t) for t in taus])
+        check(lib.lasso_solve_batch_fista(self._h, ya, ta, int(iters), oa), "lasso_solve_batch_fista")
+        return outs

@@ -44,8 +44,12 @@ static void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+void drop_graph(bccb_plan_s* p);
+
 void plan_free(bccb_plan_s* p) {
   if (!p) return;
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_omega);
   dfree(p->d_sensor_of);
   dfree(p->d_sensors);
@@ -63,27 +67,17 @@ void plan_free(bccb_plan_s* p) {
   delete p;
 }
 
-#define BCCB_TRY(expr)              \
-  do {                              \
-    const int _rc = (expr);         \
-    if (_rc != BCCB_OK) return _rc; \
-  } while (0)
-#define BCCB_HIP(expr)                                  \
-  do {                                                  \
-    if ((expr) != hipSuccess) return BCCB_E_DEVICE;     \
-  } while (0)
-
-static int kern(int rc) { return rc == 0 ? BCCB_OK : (rc == -2 ? BCCB_E_UNSUPPORTED : BCCB_E_DEVICE); }
 
 // --- pass helpers on one plan ------------------------------------------------
-int row_pass(bccb_plan_s* p, int mode, RowArgs a) {
+int row_pass_on(bccb_plan_s* p, const PassCfg& cfg, int mode, RowArgs a, hipStream_t s) {
   a.tw = p->d_tw1;
   a.nrows = p->L2;
   a.rows_per_scene = p->L2;
-  return kern(launch_row(p->L1, mode, a, p->stream));
+  return kern(launch_row(p->L1, cfg, mode, a, s));
 }
 
-int col_pass(bccb_plan_s* p, int mode, float2* xy, const float2* coef, float rho, float scale) {
+int col_pass_on(bccb_plan_s* p, const PassCfg& cfg, int mode, float2* xy, const float2* coef, float rho,
+                float scale, hipStream_t s) {
   ColArgs a;
   a.xy = xy;
   a.omega = p->d_omega;
@@ -93,7 +87,91 @@ int col_pass(bccb_plan_s* p, int mode, float2* xy, const float2* coef, float rho
   a.nscenes = 1;
   a.rho = rho;
   a.scale = scale;
-  return kern(launch_col(p->L2, mode, a, p->stream));
+  return kern(launch_col(p->L2, cfg, mode, a, s));
+}
+
+int row_pass(bccb_plan_s* p, int mode, RowArgs a) { return row_pass_on(p, p->cfg_row, mode, a, p->stream); }
+
+int col_pass(bccb_plan_s* p, int mode, float2* xy, const float2* coef, float rho, float scale) {
+  return col_pass_on(p, p->cfg_col, mode, xy, coef, rho, scale, p->stream);
+}
+
+// --- launch shapes -------------------------------------------------------------
+bool elems_ok(int N, int E) {
+  if (E != 4 && E != 8 && E != 16 && E != 32) return false;
+  if (E > N || N / E > 256) return false;
+  if (N == 8 && E > 8) return false;
+  return true;
+}
+
+bool row_shape_ok(int L1, const PassCfg& c) {
+  if (!elems_ok(L1, c.E) || c.rpb < 1) return false;
+  const int T = L1 / c.E;
+  return c.rpb * T <= 256 && static_cast<long>(c.rpb + 1) * L1 * 8 <= 65536;
+}
+
+bool col_shape_ok(int L1, int L2, const PassCfg& c) {
+  if (!elems_ok(L2, c.E) || c.W < 1 || L1 % c.W != 0) return false;
+  const int T = L2 / c.E;
+  return c.W * T <= 256 && static_cast<long>(c.W + 1) * L2 * 8 <= 65536;
+}
+
+// Latency-oriented default: E = 4, about one wave per workgroup.
+void default_config(bccb_plan_s* p) {
+  p->cfg_row.E = 4;
+  const int Tr = p->L1 / 4;
+  p->cfg_row.rpb = Tr >= 64 ? 1 : 64 / Tr;
+  p->cfg_col.E = 4;
+  const int Tc = p->L2 / 4;
+  int W = Tc >= 64 ? 1 : 64 / Tc;
+  if (W > p->L1) W = p->L1;
+  p->cfg_col.W = W;
+}
+
+void drop_graph(bccb_plan_s* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  p->graph_exec = nullptr;
+  for (auto& k : p->graph_key) k = 0;
+}
+
+// Run `enqueue` (the iteration loop of a solve) on the plan's stream, through a
+// cached hipGraph when enabled: the loop is captured on a private stream (the
+// plan's stream may be the null stream, which cannot capture) and replayed
+// while the key -- every argument the captured launches depend on -- repeats.
+template <typename F>
+int run_loop(bccb_plan_s* p, const unsigned long long (&key)[8], F&& enqueue) {
+  if (!p->use_graph) return enqueue(p->stream);
+  bool hit = p->graph_exec != nullptr;
+  for (int i = 0; i < 8 && hit; ++i) hit = p->graph_key[i] == key[i];
+  if (!hit) {
+    drop_graph(p);
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      p->cap_stream = nullptr;
+      return BCCB_E_DEVICE;
+    }
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return BCCB_E_DEVICE;
+    const int rc = enqueue(p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc != BCCB_OK || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != BCCB_OK ? rc : BCCB_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return BCCB_E_DEVICE;
+    p->graph_exec = ex;
+    for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
+  }
+  BCCB_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+  return BCCB_OK;
+}
+
+static unsigned long long fbits(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, sizeof(u));
+  return u;
 }
 
 // b (or scale*b) = D_s^H y into dst, using p->d_tmp as the spectral scratch.
@@ -219,6 +297,7 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
     plan_free(p);
     return rc;
   }
+  default_config(p);
   *out = p;
   return BCCB_OK;
 }
@@ -308,20 +387,27 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
     else if (!init) BCCB_TRY(kern(launch_fill(out, p->L, p->stream)));
   }
   const float kappa = static_cast<float>(p->mu * tau);
-  double alpha = 1.0;
-  for (int t = 1; t <= iters; ++t) {
-    BCCB_TRY(col_pass(p, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f));
-    const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
-    RowArgs a;
-    a.xy = p->d_xy;
-    a.rhs = p->d_rhs;
-    a.state = out;
-    a.out_c = out;
-    a.kappa = kappa;
-    a.beta = static_cast<float>((alpha - 1.0) / alpha_next);
-    a.last = (t == iters);
-    alpha = alpha_next;
-    BCCB_TRY(row_pass(p, mode, a));
+  if (iters > 0) {
+    const unsigned long long key[8] = {static_cast<unsigned long long>(mode), static_cast<unsigned long long>(iters),
+                                       reinterpret_cast<unsigned long long>(out), fbits(kappa), 0, 0, 0, 1};
+    BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
+      double alpha = 1.0;
+      for (int t = 1; t <= iters; ++t) {
+        BCCB_TRY(col_pass_on(p, p->cfg_col, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, s));
+        const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+        RowArgs a;
+        a.xy = p->d_xy;
+        a.rhs = p->d_rhs;
+        a.state = out;
+        a.out_c = out;
+        a.kappa = kappa;
+        a.beta = static_cast<float>((alpha - 1.0) / alpha_next);
+        a.last = (t == iters);
+        alpha = alpha_next;
+        BCCB_TRY(row_pass_on(p, p->cfg_row, mode, a, s));
+      }
+      return BCCB_OK;
+    }));
   }
   return end_call(p);
 }
@@ -359,17 +445,26 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
     if (co) BCCB_TRY(kern(launch_fill(co, p->L, p->stream)));
   }
   const float scale = static_cast<float>(static_cast<double>(rho) / static_cast<double>(p->L));
-  for (int t = 1; t <= iters; ++t) {
-    BCCB_TRY(col_pass(p, COL_FILTER_ADMM, p->d_xy, nullptr, rho, scale));
-    RowArgs a;
-    a.xy = p->d_xy;
-    a.rhs = p->d_rhs;
-    a.state = p->d_state;
-    a.out_z = zo;
-    a.out_c = co;
-    a.kappa = tau / rho;
-    a.last = (t == iters);
-    BCCB_TRY(row_pass(p, ROW_ADMM, a));
+  const float kappa = tau / rho;
+  if (iters > 0) {
+    const unsigned long long key[8] = {static_cast<unsigned long long>(ROW_ADMM), static_cast<unsigned long long>(iters),
+                                       reinterpret_cast<unsigned long long>(zo), fbits(kappa),
+                                       reinterpret_cast<unsigned long long>(co), fbits(rho), fbits(scale), 1};
+    BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
+      for (int t = 1; t <= iters; ++t) {
+        BCCB_TRY(col_pass_on(p, p->cfg_col, COL_FILTER_ADMM, p->d_xy, nullptr, rho, scale, s));
+        RowArgs a;
+        a.xy = p->d_xy;
+        a.rhs = p->d_rhs;
+        a.state = p->d_state;
+        a.out_z = zo;
+        a.out_c = co;
+        a.kappa = kappa;
+        a.last = (t == iters);
+        BCCB_TRY(row_pass_on(p, p->cfg_row, ROW_ADMM, a, s));
+      }
+      return BCCB_OK;
+    }));
   }
   return end_call(p);
 }
@@ -417,6 +512,87 @@ int bccb_objective_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c
   if (r_kkt) *r_kkt = b2 > 0.0 ? std::sqrt(e2) / std::sqrt(b2) : std::sqrt(e2);
   if (max_e_over_tau) *max_e_over_tau = tau > 0.f ? emax / tau : emax;
   return rc;
+}
+
+int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
+  if (!p || !cfg) return BCCB_E_INVALID;
+  cfg->row_elems = p->cfg_row.E;
+  cfg->row_rows_per_block = p->cfg_row.rpb;
+  cfg->col_elems = p->cfg_col.E;
+  cfg->col_cols_per_block = p->cfg_col.W;
+  cfg->use_graph = p->use_graph;
+  return BCCB_OK;
+}
+
+int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
+  if (!p || !cfg) return BCCB_E_INVALID;
+  PassCfg r, c;
+  r.E = cfg->row_elems;
+  r.rpb = cfg->row_rows_per_block;
+  c.E = cfg->col_elems;
+  c.W = cfg->col_cols_per_block;
+  if (!row_shape_ok(p->L1, r) || !col_shape_ok(p->L1, p->L2, c)) return BCCB_E_INVALID;
+  p->cfg_row = r;
+  p->cfg_col = c;
+  p->use_graph = cfg->use_graph ? 1 : 0;
+  drop_graph(p);
+  return BCCB_OK;
+}
+
+int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
+  if (!p || reps < 1) return BCCB_E_INVALID;
+  hipEvent_t e0, e1;
+  BCCB_HIP(hipEventCreate(&e0));
+  BCCB_HIP(hipEventCreate(&e1));
+  RowArgs a;
+  a.xy = p->d_xy;
+  a.rhs = p->d_rhs;
+  a.state = p->d_state;
+  a.kappa = 1.f;
+  a.beta = 0.5f;
+  float best_r = 1e30f, best_c = 1e30f;
+  PassCfg br = p->cfg_row, bc = p->cfg_col;
+  int rc = BCCB_OK;
+  const int Es[4] = {4, 8, 16, 32};
+  for (int ei = 0; ei < 4 && rc == BCCB_OK; ++ei) {
+    for (int k = 1; k <= 256 && rc == BCCB_OK; k *= 2) {
+      PassCfg c;
+      c.E = Es[ei];
+      c.rpb = k;
+      if (row_shape_ok(p->L1, c)) {
+        rc = row_pass_on(p, c, ROW_FISTA, a, p->stream);  // warm
+        if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+        for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass_on(p, c, ROW_FISTA, a, p->stream);
+        float ms = 0.f;
+        if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = BCCB_E_DEVICE;
+        if (rc == BCCB_OK && ms < best_r) { best_r = ms; br = c; }
+      }
+      PassCfg d;
+      d.E = Es[ei];
+      d.W = k;
+      if (rc == BCCB_OK && col_shape_ok(p->L1, p->L2, d)) {
+        rc = col_pass_on(p, d, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
+        if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+        for (int i = 0; i < reps && rc == BCCB_OK; ++i)
+          rc = col_pass_on(p, d, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
+        float ms = 0.f;
+        if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = BCCB_E_DEVICE;
+        if (rc == BCCB_OK && ms < best_c) { best_c = ms; bc = d; }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BCCB_OK) return rc;
+  p->cfg_row = br;
+  p->cfg_col = bc;
+  drop_graph(p);
+  if (chosen) return bccb_plan_get_config(p, chosen);
+  return BCCB_OK;
 }
 
 int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, double* row_ms) {

@@ -1,0 +1,344 @@
+// Batched solves of many independent snapshots with uneven grids and masks.
+//
+// Scenes are grouped by grid size into classes; each class owns contiguous
+// arenas so one row-pass launch and one column-pass launch per class cover all
+// of its scenes per iteration, and the per-scene quantities (eigenvalues,
+// step, threshold, snapshot and output pointers) are read from per-scene
+// device arrays.  The whole iteration loop of a solve is one captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "bccb.h"
+#include "kernels.h"
+#include "plan_internal.h"
+
+using namespace bccb;
+
+namespace {
+
+struct BatchClass {
+  int L1 = 0, L2 = 0, n = 0;
+  long L = 0;
+  std::vector<int> scenes;        // batch scene indices in arena order
+  PassCfg cfg_row, cfg_col;
+  const float2* tw1 = nullptr;    // twiddles, borrowed from a plan of the class
+  const float2* tw2 = nullptr;
+  float* d_omega = nullptr;       // [n][L]
+  float2* d_coef = nullptr;       // [n] (1/L, -mu_s/L)
+  float* d_kscale = nullptr;      // [n] mu_s * tau_s
+  float2* d_xy = nullptr;         // [n][L]
+  float2* d_rhs = nullptr;        // [n][L] mu_s * b_s
+  float2* d_c = nullptr;          // [n][L] FISTA c^(t-1) -> c^(t)
+  SceneDesc* d_desc = nullptr;    // [n]
+};
+
+}  // namespace
+
+struct bccb_batch_s {
+  int n = 0;
+  hipStream_t stream = nullptr;
+  std::vector<bccb_plan_t> plans;
+  std::vector<BatchClass> cls;
+  SceneDesc* h_desc = nullptr;    // pinned [n], class-arena order
+  float* h_kscale = nullptr;      // pinned [n], class-arena order
+  int* d_flag = nullptr;
+  int* h_flag = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_iters = -1;
+};
+
+namespace {
+
+void batch_free(bccb_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (BatchClass& c : b->cls) {
+    for (void* p : {static_cast<void*>(c.d_omega), static_cast<void*>(c.d_coef), static_cast<void*>(c.d_kscale),
+                    static_cast<void*>(c.d_xy), static_cast<void*>(c.d_rhs), static_cast<void*>(c.d_c),
+                    static_cast<void*>(c.d_desc)})
+      if (p) (void)hipFree(p);
+  }
+  if (b->d_flag) (void)hipFree(b->d_flag);
+  if (b->h_flag) (void)hipHostFree(b->h_flag);
+  if (b->h_desc) (void)hipHostFree(b->h_desc);
+  if (b->h_kscale) (void)hipHostFree(b->h_kscale);
+  delete b;
+}
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  if (hipMalloc(reinterpret_cast<void**>(p), (n ? n : 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return BCCB_E_NOMEM;
+  }
+  return BCCB_OK;
+}
+
+// Throughput-oriented default: E = 16 (fewest LDS exchanges), 256-thread blocks.
+void default_batch_cfg(BatchClass& c) {
+  c.cfg_row.E = c.L1 >= 16 ? 16 : 8;
+  int Tr = c.L1 / c.cfg_row.E;
+  c.cfg_row.rpb = std::max(1, 256 / Tr);
+  while (!row_shape_ok(c.L1, c.cfg_row) && c.cfg_row.rpb > 1) c.cfg_row.rpb /= 2;
+  c.cfg_col.E = c.L2 >= 16 ? 16 : 8;
+  int Tc = c.L2 / c.cfg_col.E;
+  c.cfg_col.W = std::min(c.L1, std::max(1, 256 / Tc));
+  while (!col_shape_ok(c.L1, c.L2, c.cfg_col) && c.cfg_col.W > 1) c.cfg_col.W /= 2;
+}
+
+int class_row(const BatchClass& c, const PassCfg& cfg, int mode, RowArgs a, hipStream_t s) {
+  a.tw = c.tw1;
+  a.nrows = c.n * c.L2;
+  a.rows_per_scene = c.L2;
+  return kern(launch_row(c.L1, cfg, mode, a, s));
+}
+
+int class_col(const BatchClass& c, const PassCfg& cfg, int mode, float2* xy, float scale, hipStream_t s) {
+  ColArgs a;
+  a.xy = xy;
+  a.omega = c.d_omega;
+  a.omega_stride = c.L;
+  a.coef = c.d_coef;
+  a.tw = c.tw2;
+  a.L1 = c.L1;
+  a.nscenes = c.n;
+  a.scale = scale;
+  return kern(launch_col(c.L2, cfg, mode, a, s));
+}
+
+int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
+  double alpha = 1.0;
+  for (int t = 1; t <= iters; ++t) {
+    const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    const float beta = static_cast<float>((alpha - 1.0) / alpha_next);
+    alpha = alpha_next;
+    for (BatchClass& c : b->cls) {
+      BCCB_TRY(class_col(c, c.cfg_col, COL_FILTER_AFFINE, c.d_xy, 1.f, s));
+      RowArgs a;
+      a.xy = c.d_xy;
+      a.rhs = c.d_rhs;
+      a.state = c.d_c;
+      a.out_c = c.d_c;
+      a.kscale = c.d_kscale;
+      a.kappa = 1.f;
+      a.beta = beta;
+      a.last = (t == iters);
+      BCCB_TRY(class_row(c, c.cfg_row, ROW_FISTA, a, s));
+    }
+  }
+  return BCCB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_batch_t* out) {
+  if (!plans || nscenes < 1 || !out) return BCCB_E_INVALID;
+  *out = nullptr;
+  for (int i = 0; i < nscenes; ++i)
+    if (!plans[i]) return BCCB_E_INVALID;
+  bccb_batch_s* b = new (std::nothrow) bccb_batch_s();
+  if (!b) return BCCB_E_NOMEM;
+  b->n = nscenes;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->plans.assign(plans, plans + nscenes);
+
+  std::map<std::pair<int, int>, int> index;
+  for (int i = 0; i < nscenes; ++i) {
+    const auto key = std::make_pair(plans[i]->L1, plans[i]->L2);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      BatchClass c;
+      c.L1 = key.first;
+      c.L2 = key.second;
+      c.L = static_cast<long>(c.L1) * c.L2;
+      c.tw1 = plans[i]->d_tw1;
+      c.tw2 = plans[i]->d_tw2;
+      index[key] = static_cast<int>(b->cls.size());
+      b->cls.push_back(c);
+      it = index.find(key);
+    }
+    b->cls[it->second].scenes.push_back(i);
+  }
+  int rc = BCCB_OK;
+  for (BatchClass& c : b->cls) {
+    c.n = static_cast<int>(c.scenes.size());
+    if (c.n > 65535) rc = BCCB_E_UNSUPPORTED;
+    default_batch_cfg(c);
+    const size_t pts = static_cast<size_t>(c.n) * c.L;
+    if (rc == BCCB_OK) rc = dalloc(&c.d_omega, pts);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_coef, c.n);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_kscale, c.n);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_xy, pts);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_rhs, pts);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_c, pts);
+    if (rc == BCCB_OK) rc = dalloc(&c.d_desc, c.n);
+    if (rc != BCCB_OK) break;
+    std::vector<float2> coef(c.n);
+    for (int k = 0; k < c.n; ++k) {
+      const bccb_plan_s* p = plans[c.scenes[k]];
+      coef[k] = make_float2(static_cast<float>(1.0 / static_cast<double>(c.L)),
+                            static_cast<float>(-p->mu / static_cast<double>(c.L)));
+      if (hipMemcpyAsync(c.d_omega + static_cast<size_t>(k) * c.L, p->d_omega, c.L * sizeof(float),
+                         hipMemcpyDeviceToDevice, b->stream) != hipSuccess) {
+        rc = BCCB_E_DEVICE;
+        break;
+      }
+    }
+    if (rc == BCCB_OK && hipMemcpy(c.d_coef, coef.data(), c.n * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      rc = BCCB_E_DEVICE;
+    if (rc != BCCB_OK) break;
+  }
+  if (rc == BCCB_OK) rc = dalloc(&b->d_flag, 1);
+  if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), sizeof(int)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&b->h_desc), nscenes * sizeof(SceneDesc)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&b->h_kscale), nscenes * sizeof(float)) != hipSuccess))
+    rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = BCCB_E_DEVICE;
+  if (rc != BCCB_OK) {
+    batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return BCCB_OK;
+}
+
+int bccb_batch_destroy(bccb_batch_t b) {
+  if (b) (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
+  return BCCB_OK;
+}
+
+int bccb_batch_info(bccb_batch_t b, int* nclasses, int* L1, int* L2, int* count) {
+  if (!b) return BCCB_E_INVALID;
+  if (nclasses) *nclasses = static_cast<int>(b->cls.size());
+  for (size_t i = 0; i < b->cls.size(); ++i) {
+    if (L1) L1[i] = b->cls[i].L1;
+    if (L2) L2[i] = b->cls[i].L2;
+    if (count) count[i] = b->cls[i].n;
+  }
+  return BCCB_OK;
+}
+
+int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const float* tau, int iters,
+                            bccb_c32* const* c_out) {
+  if (!b || !y || !tau || !c_out || iters < 0) return BCCB_E_INVALID;
+  for (int i = 0; i < b->n; ++i) {
+    if (!y[i] || !c_out[i] || !(tau[i] >= 0.f) || !std::isfinite(tau[i])) return BCCB_E_INVALID;
+  }
+  hipStream_t s = b->stream;
+  BCCB_HIP(hipMemsetAsync(b->d_flag, 0, sizeof(int), s));
+  // per-scene descriptors and thresholds, in class-arena order
+  int off = 0;
+  for (BatchClass& c : b->cls) {
+    for (int k = 0; k < c.n; ++k) {
+      const int i = c.scenes[k];
+      const bccb_plan_s* p = b->plans[i];
+      SceneDesc& d = b->h_desc[off + k];
+      d.y = reinterpret_cast<const float2*>(y[i]);
+      d.sensor_of = p->d_sensor_of;
+      d.out = reinterpret_cast<float2*>(c_out[i]);
+      d.M1 = p->M1;
+      d.M2 = p->M2;
+      d.scale = static_cast<float>(p->mu);
+      b->h_kscale[off + k] = static_cast<float>(p->mu * tau[i]);
+    }
+    BCCB_HIP(hipMemcpyAsync(c.d_desc, b->h_desc + off, c.n * sizeof(SceneDesc), hipMemcpyHostToDevice, s));
+    BCCB_HIP(hipMemcpyAsync(c.d_kscale, b->h_kscale + off, c.n * sizeof(float), hipMemcpyHostToDevice, s));
+    off += c.n;
+  }
+  // mu_s * b_s = mu_s * D_s^H y_s for every scene; c^(0) = 0, DFT_rows(z^(1)) = 0
+  for (BatchClass& c : b->cls) {
+    BCCB_TRY(kern(launch_scatter_batch(c.d_desc, c.n, c.L1, c.L2, c.d_xy, b->d_flag, s)));
+    BCCB_TRY(class_col(c, c.cfg_col, COL_INV, c.d_xy, 1.f, s));
+    RowArgs a;
+    a.xy = c.d_xy;
+    a.dst = c.d_rhs;
+    BCCB_TRY(class_row(c, c.cfg_row, ROW_INV, a, s));
+    BCCB_TRY(kern(launch_fill(c.d_c, static_cast<long>(c.n) * c.L, s)));
+    BCCB_TRY(kern(launch_fill(c.d_xy, static_cast<long>(c.n) * c.L, s)));
+  }
+  if (iters > 0) {
+    if (!b->exec || b->graph_iters != iters) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+      if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        b->cap_stream = nullptr;
+        return BCCB_E_DEVICE;
+      }
+      BCCB_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int rc = fista_loop(b, iters, b->cap_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
+      if (rc != BCCB_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != BCCB_OK ? rc : BCCB_E_DEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        b->exec = nullptr;
+        return BCCB_E_DEVICE;
+      }
+      b->graph_iters = iters;
+    }
+    BCCB_HIP(hipGraphLaunch(b->exec, s));
+  }
+  for (BatchClass& c : b->cls) BCCB_TRY(kern(launch_gather_batch(c.d_desc, c.n, c.L, c.d_c, s)));
+  BCCB_HIP(hipMemcpyAsync(b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  BCCB_HIP(hipStreamSynchronize(s));
+  return *b->h_flag ? BCCB_E_NONFINITE : BCCB_OK;
+}
+
+int bccb_batch_autotune(bccb_batch_t b, int reps) {
+  if (!b || reps < 1) return BCCB_E_INVALID;
+  const int Es[4] = {4, 8, 16, 32};
+  for (BatchClass& c : b->cls) {
+    float best_r = 1e30f, best_c = 1e30f;
+    PassCfg br = c.cfg_row, bc = c.cfg_col;
+    for (int E : Es) {
+      for (int k = 1; k <= 256; k *= 2) {
+        PassCfg r;
+        r.E = E;
+        r.rpb = k;
+        if (row_shape_ok(c.L1, r)) {
+          RowArgs a;
+          a.xy = c.d_xy;
+          a.rhs = c.d_rhs;
+          a.state = c.d_c;
+          a.kscale = c.d_kscale;
+          a.kappa = 1.f;
+          a.beta = 0.5f;
+          const float ms = time_launches(b->stream, reps, [&] { return class_row(c, r, ROW_FISTA, a, b->stream); });
+          if (ms < 0.f) return BCCB_E_DEVICE;
+          if (ms < best_r) { best_r = ms; br = r; }
+        }
+        PassCfg w;
+        w.E = E;
+        w.W = k;
+        if (col_shape_ok(c.L1, c.L2, w)) {
+          const float ms = time_launches(b->stream, reps,
+                                         [&] { return class_col(c, w, COL_FILTER_AFFINE, c.d_xy, 1.f, b->stream); });
+          if (ms < 0.f) return BCCB_E_DEVICE;
+          if (ms < best_c) { best_c = ms; bc = w; }
+        }
+      }
+    }
+    c.cfg_row = br;
+    c.cfg_col = bc;
+  }
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->graph_iters = -1;
+  return BCCB_OK;
+}
+
+}  // extern "C"

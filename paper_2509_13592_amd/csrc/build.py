@@ -20,6 +20,8 @@ LIB = os.path.join(PKG, "libbccb.so")
 
 SOURCES = ["kernels.hip", "batch_kernels.hip", "learned_kernels.hip", "dense_kernels.hip",
            "plan_math.cpp", "api.cpp", "batch.cpp", "learned.cpp", "dense.cpp"]
+# the pass kernels are compiled once per transform length (parallel build)
+PASS_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024]
 
 ARCH = os.environ.get("BCCB_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{HERE}", "-Wall", "-Wno-unused-function"]
@@ -34,12 +36,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
+def _compile(job) -> str:
+    src, extra, tag = job
     path = os.path.join(HERE, src)
-    obj = os.path.join(OBJDIR, src + ".o")
-    cmd = [hipcc(), *COMMON, *DEVICE, "-c", path, "-o", obj]
+    obj = os.path.join(OBJDIR, f"{src}{tag}.o")
+    cmd = [hipcc(), *COMMON, *extra, *DEVICE, "-c", path, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), *COMMON, "-x", "hip", *DEVICE, "-c", path, "-o", obj]
+        cmd = [hipcc(), *COMMON, *extra, "-x", "hip", *DEVICE, "-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
@@ -48,9 +51,11 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    jobs = [(f"passes_n.hip", [f"-DPASS_N={n}"], f".{n}") for n in reversed(PASS_LENGTHS)]
+    jobs += [(s, [], "") for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    workers = max(1, min(int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16, len(jobs)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

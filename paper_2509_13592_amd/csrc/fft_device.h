@@ -1,17 +1,22 @@
 // Device building blocks for the power-of-two 2D DFT passes on gfx950.
 //
-// A length-N transform (N = A*B, 8 <= N <= 1024) is split four-step style:
-// B-strided columns of length A are transformed in registers, multiplied by
-// the twiddles W_N^{n2*k1}, transposed through LDS, and transformed again with
-// length B.  One LDS exchange per transform, natural-order input and output,
-// and every global access of a thread group is a contiguous run of T elements.
+// A length-N transform (8 <= N <= 1024) is a mixed-radix Stockham FFT spread
+// over T = N/E threads that hold E elements each.  Stage s has radix R_s (E,
+// or the remainder 2^(log2 N mod log2 E) last); a thread does E/R_s radix-R_s
+// butterflies per stage in registers and the stages exchange data through LDS
+// in natural (autosort) order, so input and output are in natural order and
+// every global access of the T threads is a contiguous run.
 //
-// Data distributions over the T = B threads that own one transform:
-//   D_in : thread t holds x[B*i + t],          i  in [0, A)
-//   D_out: thread t holds X[t + T*q + A*k2],   q in [0, A/T), k2 in [0, B)
-// The forward transform maps D_in -> D_out, the inverse maps D_out -> D_in.
-// The inverse is unnormalised (sum with e^{+j...}); callers fold 1/N where
-// the product needs it (Sec. III-B, eq. (23), reading R10).
+// E is the knob between latency and throughput: E = 4 spreads a 256-point row
+// over a full wave (4 stages, 3 exchanges), E = 16 packs it into 16 threads
+// (2 stages, 1 exchange).
+//
+// Register layouts (g < E/R, r < R, j = t + T*g):
+//   forward input : v[g*R0 + r]   = x[j + r*N/R0]        (R0 = first forward radix)
+//   forward output: v[g*Rl + r]   = X[j + r*N/Rl]        (Rl = last forward radix)
+// The inverse runs the stages in reverse order, so it takes the forward
+// output layout and returns the forward input layout.  The inverse is
+// unnormalised (e^{+j...}); callers fold 1/N where needed (eq. (23), R10).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,11 +79,12 @@ constexpr int brev(int i, int n) {
   for (int b = 1; b < n; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
   return r;
 }
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 }  // namespace detail
 
-// v * e^{-+ j 2 pi j / len} (minus for forward, plus for inverse); len | 32, all
-// arguments are compile-time constants after unrolling, so the trivial roots
-// (1, -+j, and the 45-degree ones) cost no multiply by zero.
+// v * e^{-+ j 2 pi j / len} (minus for forward, plus for inverse); len | 32 and
+// all arguments are compile-time constants after unrolling, so the trivial
+// roots cost no multiply by zero.
 template <bool INV>
 __device__ __forceinline__ float2 rot_const(float2 v, int j, int len) {
   const int k = (j * (32 / len)) & 31;
@@ -117,78 +123,89 @@ __device__ __forceinline__ void dft_reg(float2* v) {
 }
 
 // ---------------------------------------------------------------------------
-// Four-step shapes: N = A * B with A >= B, T = B threads per transform and
-// E = A elements per thread.
+// Mixed-radix Stockham FFT of N points over T = N/E threads.
 // ---------------------------------------------------------------------------
-template <int N> struct Shape;
-template <> struct Shape<8>    { static constexpr int A = 4,  B = 2;  };
-template <> struct Shape<16>   { static constexpr int A = 4,  B = 4;  };
-template <> struct Shape<32>   { static constexpr int A = 8,  B = 4;  };
-template <> struct Shape<64>   { static constexpr int A = 8,  B = 8;  };
-template <> struct Shape<128>  { static constexpr int A = 16, B = 8;  };
-template <> struct Shape<256>  { static constexpr int A = 16, B = 16; };
-template <> struct Shape<512>  { static constexpr int A = 32, B = 16; };
-template <> struct Shape<1024> { static constexpr int A = 32, B = 32; };
+template <int N, int E>
+struct Stockham {
+  static_assert((N & (N - 1)) == 0 && N >= 8 && N <= 1024, "N");
+  static_assert((E & (E - 1)) == 0 && E >= 2 && E <= 32 && E <= N, "E");
+  static constexpr int T = N / E;
+  static constexpr int LOGN = detail::ilog2(N);
+  static constexpr int LOGE = detail::ilog2(E);
+  static constexpr int NFULL = LOGN / LOGE;
+  static constexpr int REM = 1 << (LOGN % LOGE);          // 1 if none
+  static constexpr int NST = NFULL + (REM > 1 ? 1 : 0);  // number of stages
+  static constexpr int R0 = E;                            // first forward radix
+  static constexpr int RL = (REM > 1) ? REM : E;          // last forward radix
 
-template <int N>
-struct FFT {
-  static constexpr int A = Shape<N>::A;
-  static constexpr int B = Shape<N>::B;
-  static constexpr int T = B;        // threads per transform
-  static constexpr int E = A;        // elements per thread
-  static constexpr int Q = A / T;    // k1 groups per thread in D_out
-  static constexpr int PAD = 1;
-  static constexpr int LDS = A * (B + PAD);   // float2 slots per transform
-
-  // global element index of register slot e in each distribution
-  __device__ static __forceinline__ int in_index(int t, int e) { return B * e + t; }
-  __device__ static __forceinline__ int out_index(int t, int e) {
-    const int q = e / B, k2 = e % B;
-    return t + T * q + A * k2;
+  // radix of stage s in forward order; the inverse uses the reverse order
+  static constexpr int fwd_radix(int s) { return s < NFULL ? E : REM; }
+  static constexpr int radix(int s, bool inv) { return inv ? fwd_radix(NST - 1 - s) : fwd_radix(s); }
+  static constexpr int span(int s, bool inv) {  // product of the radices before stage s
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i, inv);
+    return p;
   }
 
-  // LDS slot of (k1, n2); `stride` separates the transforms that share one LDS array
-  __device__ static __forceinline__ int slot(int k1, int n2) { return k1 * (B + PAD) + n2; }
-
-  // D_in -> D_out.  tw[j] = e^{-j 2 pi j/N} (table in LDS or global); the LDS
-  // slot of (k1, n2) for this transform is sm[slot(k1, n2) * ss], so several
-  // transforms can interleave in one array.  Contains one __syncthreads():
-  // every thread of the block must call it.  Thread t only writes the slots
-  // (., t) it later reads back itself and reads rows (t + T q, .) it wrote
-  // itself in a preceding inverse, so back-to-back forward/inverse calls on
-  // the same area need no extra barrier.
-  __device__ static __forceinline__ void forward(float2* v, int t, const float2* tw, float2* sm, int ss) {
-    dft_reg<A, false>(v);
-#pragma unroll
-    for (int k1 = 1; k1 < A; ++k1) v[k1] = cmul(v[k1], tw[(t * k1) & (N - 1)]);
-#pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) sm[slot(k1, t) * ss] = v[k1];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int n2 = 0; n2 < B; ++n2) v[q * B + n2] = sm[slot(t + T * q, n2) * ss];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) dft_reg<B, false>(v + q * B);
+  // element index held in register slot e, for a layout whose stage radix is R
+  template <int R>
+  __device__ static __forceinline__ int layout_index(int t, int e) {
+    return t + T * (e / R) + (e % R) * (N / R);
   }
+  __device__ static __forceinline__ int in_index(int t, int e) { return layout_index<R0>(t, e); }
+  __device__ static __forceinline__ int out_index(int t, int e) { return layout_index<RL>(t, e); }
 
-  // D_out -> D_in, unnormalised inverse.  Same synchronisation contract.
-  __device__ static __forceinline__ void inverse(float2* v, int t, const float2* tw, float2* sm, int ss) {
+  // One stage.  On entry v holds the stage input in layout<R> (stage 0: the
+  // caller loaded it; later stages: read here from LDS).  Every LDS write
+  // phase is preceded by a barrier so that no thread overwrites a slot another
+  // thread of the previous read phase still needs; `sm[i*ss]` is slot i.
+  template <bool INV, int S>
+  __device__ static __forceinline__ void stage(float2* v, int t, const float2* tw, float2* sm, int ss) {
+    constexpr int R = radix(S, INV);
+    constexpr int NS = span(S, INV);
+    constexpr int G = E / R;
+    if constexpr (S > 0) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      dft_reg<B, true>(v + q * B);
-      const int k1 = t + T * q;
+      for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int n2 = 1; n2 < B; ++n2) v[q * B + n2] = cmulc(v[q * B + n2], tw[(n2 * k1) & (N - 1)]);
+        for (int r = 0; r < R; ++r) v[g * R + r] = sm[(t + T * g + r * (N / R)) * ss];
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int g = 0; g < G; ++g) {
+      const int j = t + T * g;
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
 #pragma unroll
-      for (int n2 = 0; n2 < B; ++n2) sm[slot(t + T * q, n2) * ss] = v[q * B + n2];
-    __syncthreads();
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw[(r * k * (N / (NS * R))) & (N - 1)];
+          v[g * R + r] = INV ? cmulc(v[g * R + r], w) : cmul(v[g * R + r], w);
+        }
+      }
+      dft_reg<R, INV>(v + g * R);
+    }
+    if constexpr (S + 1 < NST) {
+      __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) v[k1] = sm[slot(k1, t) * ss];
-    dft_reg<A, true>(v);
+      for (int g = 0; g < G; ++g) {
+        const int j = t + T * g;
+        const int k = j & (NS - 1);
+        const int base = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) sm[(base + r * NS) * ss] = v[g * R + r];
+      }
+      __syncthreads();
+      stage<INV, S + 1>(v, t, tw, sm, ss);
+    }
+  }
+
+  // v: forward input layout -> forward output layout.  Every thread of the
+  // block must call it (it contains barriers when NST > 1).
+  __device__ static __forceinline__ void forward(float2* v, int t, const float2* tw, float2* sm, int ss) {
+    stage<false, 0>(v, t, tw, sm, ss);
+  }
+  // v: forward output layout -> forward input layout, unnormalised inverse.
+  __device__ static __forceinline__ void inverse(float2* v, int t, const float2* tw, float2* sm, int ss) {
+    stage<true, 0>(v, t, tw, sm, ss);
   }
 };
 

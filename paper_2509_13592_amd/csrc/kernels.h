@@ -56,8 +56,31 @@ struct ColArgs {
   float rho = 0.f, scale = 1.f;
 };
 
-int launch_row(int N, int mode, const RowArgs& a, hipStream_t s);
-int launch_col(int N, int mode, const ColArgs& a, hipStream_t s);
+// Launch shape of the passes for one transform length: E elements per thread
+// (T = N/E threads per transform), rows per block of the row pass, columns per
+// block of the column pass.
+struct PassCfg {
+  int E = 16;
+  int rpb = 1;
+  int W = 1;
+};
+
+// Returns 0, -1 (shape not launchable), -2 (size not compiled), -4 (HIP error).
+int launch_row(int N, const PassCfg& cfg, int mode, const RowArgs& a, hipStream_t s);
+int launch_col(int N, const PassCfg& cfg, int mode, const ColArgs& a, hipStream_t s);
+
+#define BCCB_DECLARE_N(n)                                                                  \
+  int row_launch_##n(int E, int mode, const RowArgs& a, int rpb, hipStream_t s);           \
+  int col_launch_##n(int E, int mode, const ColArgs& a, int W, hipStream_t s);
+BCCB_DECLARE_N(8)
+BCCB_DECLARE_N(16)
+BCCB_DECLARE_N(32)
+BCCB_DECLARE_N(64)
+BCCB_DECLARE_N(128)
+BCCB_DECLARE_N(256)
+BCCB_DECLARE_N(512)
+BCCB_DECLARE_N(1024)
+#undef BCCB_DECLARE_N
 
 // S[k2][k1] = scale * sum over kept elements folding onto (k1, k2) of (-1)^(m1+m2) y_m
 int launch_scatter(const float2* y, const int* sensor_of, int M1, int M2, int L1, int L2,
@@ -74,5 +97,20 @@ int launch_fill(float2* p, long n, hipStream_t s);   // zero fill (graph-safe, n
 int launch_copy(float2* dst, const float2* src, long n, hipStream_t s);
 
 constexpr int kReduceBlocks = 512;
+
+// Per-scene descriptor of a batched solve.
+struct SceneDesc {
+  const float2* y = nullptr;      // snapshot [M]
+  const int* sensor_of = nullptr; // [M2][M1] index into y or -1
+  float2* out = nullptr;          // output grid [L2][L1]
+  int M1 = 0, M2 = 0;
+  float scale = 1.f;              // multiplier of the scattered snapshot (mu for mu*b)
+  int pad = 0;
+};
+
+// S[scene][k2][k1] = desc[scene].scale * (scatter of scene's snapshot), for n scenes of one size.
+int launch_scatter_batch(const SceneDesc* desc, int n, int L1, int L2, float2* S, int* flag, hipStream_t s);
+// desc[scene].out[i] = src[scene*L + i]
+int launch_gather_batch(const SceneDesc* desc, int n, long L, const float2* src, hipStream_t s);
 
 }  // namespace bccb

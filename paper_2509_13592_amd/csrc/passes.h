@@ -1,0 +1,255 @@
+// Row and column pass kernels (templates), instantiated per transform length
+// in passes_n.hip.
+//
+// The product R c = IDFT2(Omega . DFT2(C)) of eq. (23) is split into a row pass
+// (transforms along l1, contiguous) and a column pass (transforms along l2,
+// stride L1).  Grids are [L2][L1] row-major, c(l1 + l2*L1) = C(l1, l2)
+// (Sec. II-A).  One solver iteration is
+//   column pass: DFT_cols -> multiply by the BCCB spectrum -> IDFT_cols
+//   row pass   : IDFT_rows -> proximal/momentum/ADMM update -> DFT_rows
+// so the state crosses memory once per pass, and the spectral multiply, the
+// soft threshold (eq. (9)), the FISTA momentum (eqs. (10)-(12)) and the ADMM
+// updates (eqs. (13)-(15)) never take a pass of their own.
+#pragma once
+
+#include "fft_device.h"
+#include "kernels.h"
+
+namespace bccb {
+
+__device__ __forceinline__ bool finite2(float2 v) {
+  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
+}
+
+// Complex soft threshold S_k(z) = z max(1 - k/|z|, 0), zero for |z| <= k (R3).
+__device__ __forceinline__ float2 shrink(float2 z, float k) {
+  const float a2 = z.x * z.x + z.y * z.y;
+  if (!(a2 > k * k)) return make_float2(0.f, 0.f);
+  const float f = 1.f - k * __builtin_amdgcn_rsqf(a2);
+  return make_float2(z.x * f, z.y * f);
+}
+
+// ---------------------------------------------------------------------------
+// Row pass: a block owns `rpb` consecutive rows, T threads each.
+// Dynamic LDS: rpb * N float2 exchange slots + N twiddles.
+// ---------------------------------------------------------------------------
+template <int N, int E, int MODE>
+__global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
+  using F = Stockham<N, E>;
+  constexpr int T = F::T;
+  constexpr bool kIter = (MODE == ROW_ISTA || MODE == ROW_FISTA || MODE == ROW_ADMM);
+  constexpr bool kState = (MODE == ROW_FISTA || MODE == ROW_ADMM);
+  extern __shared__ float2 lds[];
+  float2* stw = lds + rpb * N;
+
+  const int tid = threadIdx.x;
+  const int nthreads = rpb * T;
+  const int r = tid / T, t = tid - (tid / T) * T;
+  const int row = blockIdx.x * rpb + r;
+  const bool active = row < a.nrows;
+  float2* sm = lds + r * N;
+  const size_t base = static_cast<size_t>(active ? row : 0) * N;
+  const float2 zero = make_float2(0.f, 0.f);
+
+  // Every global load of the pass is issued before the first barrier so the
+  // latencies of the iterate, the right-hand side, the state and the twiddle
+  // table overlap instead of adding up.
+  float2 v[E];
+  float2 rhs[kIter ? E : 1];
+  float2 st[kState ? E : 1];
+  if constexpr (MODE == ROW_FWD) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (active && a.src) ? a.src[base + F::in_index(t, e)] : zero;
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = active ? a.xy[base + F::out_index(t, e)] : zero;
+  }
+  if constexpr (kIter) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) rhs[e] = active ? a.rhs[base + F::in_index(t, e)] : zero;
+  }
+  if constexpr (kState) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) st[e] = active ? a.state[base + F::in_index(t, e)] : zero;
+  }
+  for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+  __syncthreads();
+
+  if constexpr (MODE == ROW_FWD) {
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < E; ++e) ok = ok && finite2(v[e]);
+    if (!ok && a.flag) *a.flag = 1;
+    F::forward(v, t, stw, sm, 1);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) a.xy[base + F::out_index(t, e)] = v[e];
+    }
+  } else if constexpr (MODE == ROW_INV) {
+    F::inverse(v, t, stw, sm, 1);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) a.dst[base + F::in_index(t, e)] = cscale(v[e], a.scale);
+    }
+  } else {
+    F::inverse(v, t, stw, sm, 1);
+    const int scene = active ? row / a.rows_per_scene : 0;
+    const float kappa = a.kscale ? a.kappa * a.kscale[scene] : a.kappa;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t idx = base + F::in_index(t, e);
+      if constexpr (MODE == ROW_ISTA) {
+        const float2 c = shrink(cadd(v[e], rhs[e]), kappa);
+        if (a.last && active) a.out_c[idx] = c;
+        v[e] = c;
+      } else if constexpr (MODE == ROW_FISTA) {
+        const float2 c = shrink(cadd(v[e], rhs[e]), kappa);
+        const float2 cp = st[e];
+        if (active) a.state[idx] = c;
+        v[e] = make_float2(c.x + a.beta * (c.x - cp.x), c.y + a.beta * (c.y - cp.y));
+      } else {  // ROW_ADMM
+        const float2 c = cadd(rhs[e], v[e]);
+        const float2 vv = st[e];
+        const float2 z = shrink(cadd(c, vv), kappa);
+        const float2 vn = csub(cadd(vv, c), z);
+        if (active) {
+          a.state[idx] = vn;
+          if (a.last) {
+            a.out_z[idx] = z;
+            if (a.out_c) a.out_c[idx] = c;
+          }
+        }
+        v[e] = csub(z, vn);
+      }
+    }
+    if (!a.last) {
+      F::forward(v, t, stw, sm, 1);
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a.xy[base + F::out_index(t, e)] = v[e];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: a block owns W adjacent columns of one scene; lane = c + W*t.
+// Dynamic LDS: W * N float2 exchange slots (column c at stride W) + N twiddles.
+// ---------------------------------------------------------------------------
+template <int N, int E, int MODE>
+__global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
+  using F = Stockham<N, E>;
+  constexpr int T = F::T;
+  extern __shared__ float2 lds[];
+  float2* stw = lds + W * N;
+
+  const int tid = threadIdx.x;
+  const int nthreads = W * T;
+  const int c = tid % W, t = tid / W;
+  const int strips = a.L1 / W;
+  const int scene = blockIdx.x / strips;
+  const int col = (blockIdx.x - scene * strips) * W + c;
+  const size_t plane = static_cast<size_t>(N) * a.L1;
+  float2* g = a.xy + scene * plane + col;
+  float2* sms = lds + c;
+
+  constexpr bool kFwd = (MODE == COL_FWD || MODE == COL_FILTER_AFFINE || MODE == COL_FILTER_ADMM ||
+                         MODE == COL_FILTER_CPLX);
+  constexpr bool kInv = (MODE != COL_FWD);
+  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV);
+  constexpr bool kCplx = (MODE == COL_FILTER_CPLX);
+
+  // all global loads first (iterate, spectral multiplier, twiddles)
+  float2 v[E];
+  if constexpr (kFwd) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::in_index(t, e)) * a.L1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::out_index(t, e)) * a.L1];
+  }
+  float om[(kMul && !kCplx) ? E : 1];
+  float2 mc[kCplx ? E : 1];
+  if constexpr (kCplx) {
+    const float2* m = a.mulc + scene * a.mulc_stride + col;
+#pragma unroll
+    for (int e = 0; e < E; ++e) mc[e] = m[static_cast<size_t>(F::out_index(t, e)) * a.L1];
+  } else if constexpr (kMul) {
+    const float* o = a.omega + scene * a.omega_stride + col;
+#pragma unroll
+    for (int e = 0; e < E; ++e) om[e] = o[static_cast<size_t>(F::out_index(t, e)) * a.L1];
+  }
+  for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+  __syncthreads();
+
+  if constexpr (kFwd) F::forward(v, t, stw, sms, W);
+
+  if constexpr (kCplx) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cmul(v[e], mc[e]);
+  } else if constexpr (MODE == COL_FILTER_AFFINE || MODE == COL_MULINV_AFFINE) {
+    const float2 ab = a.coef[scene];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ab.x + ab.y * om[e]);
+  } else if constexpr (kMul) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], a.scale / (om[e] + a.rho));
+  }
+
+  if constexpr (kInv) {
+    F::inverse(v, t, stw, sms, W);
+    const float s = (MODE == COL_INV) ? a.scale : 1.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::in_index(t, e)) * a.L1] = cscale(v[e], s);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::out_index(t, e)) * a.L1] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers for one N (instantiated in passes_n.hip)
+// ---------------------------------------------------------------------------
+template <int N, int E>
+int row_launch_e(int mode, const RowArgs& a, int rpb, hipStream_t s) {
+  constexpr int T = Stockham<N, E>::T;
+  if (rpb < 1 || rpb * T > 256) return -1;
+  const int blocks = (a.nrows + rpb - 1) / rpb;
+  if (blocks <= 0) return 0;
+  const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2);
+  if (shm > 65536) return -1;
+  const dim3 grid(blocks), block(rpb * T);
+  switch (mode) {
+    case ROW_FWD: hipLaunchKernelGGL((k_row<N, E, ROW_FWD>), grid, block, shm, s, a, rpb); break;
+    case ROW_INV: hipLaunchKernelGGL((k_row<N, E, ROW_INV>), grid, block, shm, s, a, rpb); break;
+    case ROW_ISTA: hipLaunchKernelGGL((k_row<N, E, ROW_ISTA>), grid, block, shm, s, a, rpb); break;
+    case ROW_FISTA: hipLaunchKernelGGL((k_row<N, E, ROW_FISTA>), grid, block, shm, s, a, rpb); break;
+    case ROW_ADMM: hipLaunchKernelGGL((k_row<N, E, ROW_ADMM>), grid, block, shm, s, a, rpb); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+template <int N, int E>
+int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
+  constexpr int T = Stockham<N, E>::T;
+  if (W < 1 || W * T > 256 || a.L1 % W != 0) return -1;
+  const int blocks = (a.L1 / W) * a.nscenes;
+  if (blocks <= 0) return 0;
+  const size_t shm = static_cast<size_t>(W + 1) * N * sizeof(float2);
+  if (shm > 65536) return -1;
+  const dim3 grid(blocks), block(W * T);
+  switch (mode) {
+    case COL_FWD: hipLaunchKernelGGL((k_col<N, E, COL_FWD>), grid, block, shm, s, a, W); break;
+    case COL_INV: hipLaunchKernelGGL((k_col<N, E, COL_INV>), grid, block, shm, s, a, W); break;
+    case COL_FILTER_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_FILTER_AFFINE>), grid, block, shm, s, a, W); break;
+    case COL_FILTER_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_FILTER_ADMM>), grid, block, shm, s, a, W); break;
+    case COL_FILTER_CPLX: hipLaunchKernelGGL((k_col<N, E, COL_FILTER_CPLX>), grid, block, shm, s, a, W); break;
+    case COL_MULINV_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_MULINV_AFFINE>), grid, block, shm, s, a, W); break;
+    case COL_MULINV_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_MULINV_ADMM>), grid, block, shm, s, a, W); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace bccb

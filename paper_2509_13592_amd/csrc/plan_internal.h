@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "bccb.h"
+#include "kernels.h"
 
 struct bccb_plan_s {
   int M1 = 0, M2 = 0, L1 = 0, L2 = 0, M = 0;
@@ -29,4 +30,51 @@ struct bccb_plan_s {
   int* d_flag = nullptr;           // non-finite input flag
   double* h_red = nullptr;         // pinned host copy of the partials
   int* h_flag = nullptr;           // pinned host copy of the flag
+
+  bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
+  bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
+  int use_graph = 1;
+
+  // one cached hipGraph of a solve's iteration loop, replayed while its key repeats
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  unsigned long long graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
+
+#define BCCB_TRY(expr)              \
+  do {                              \
+    const int _rc = (expr);         \
+    if (_rc != BCCB_OK) return _rc; \
+  } while (0)
+#define BCCB_HIP(expr)                              \
+  do {                                              \
+    if ((expr) != hipSuccess) return BCCB_E_DEVICE; \
+  } while (0)
+
+namespace bccb {
+
+// kernel-launcher return code -> status
+inline int kern(int rc) { return rc == 0 ? BCCB_OK : (rc == -2 ? BCCB_E_UNSUPPORTED : BCCB_E_DEVICE); }
+
+bool elems_ok(int N, int E);
+bool row_shape_ok(int L1, const PassCfg& c);
+bool col_shape_ok(int L1, int L2, const PassCfg& c);
+
+// Time `reps` launches of `launch()` on stream s with hipEvents; ms per launch, or < 0 on error.
+template <typename F>
+float time_launches(hipStream_t s, int reps, F&& launch) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.f; }
+  float ms = -1.f;
+  bool ok = launch() == 0;                                   // warm-up
+  ok = ok && hipEventRecord(e0, s) == hipSuccess;
+  for (int i = 0; i < reps && ok; ++i) ok = launch() == 0;
+  ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ok ? ms / reps : -1.f;
+}
+
+}  // namespace bccb

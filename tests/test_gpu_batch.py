@@ -1,0 +1,122 @@
+"""GPU parity of the batched uneven-scene FISTA solver (one graph launch per solve)."""
+import numpy as np
+import pytest
+
+from oracle import bccb_oracle as O
+from paper_2509_13592_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+B = pytest.importorskip("paper_2509_13592_amd.bccb")
+
+OBJ_TOL = 1e-5
+
+
+def _np(t):
+    return t.detach().cpu().numpy().reshape(-1).astype(np.complex128)
+
+
+def _setup(scenes):
+    plans = [B.Plan(sc.mask, sc.L1, sc.L2) for sc in scenes]
+    ys = [B.to_device(sc.y) for sc in scenes]
+    taus = [float(np.float32(0.1 * p.adjoint_maxabs(y))) for p, y in zip(plans, ys)]
+    return plans, ys, taus
+
+
+def test_uneven_batch_matches_oracle_and_single_solves():
+    # mixed grid sizes, masks, array sizes (drawn like the 4096-scene workload) plus a
+    # rectangular and an aliasing scene
+    scenes = [S.batched_scene(i) for i in range(14)]
+    scenes.append(S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(12, 0, 0)))
+    scenes.append(S.custom_scene(20, 6, 40, 16, 8, K=2, snr_db=20, seed=(13, 0, 0)))
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    print("classes", batch.classes(), flush=True)
+    iters = 150
+    outs = batch.fista(ys, taus, iters)
+    outs2 = batch.fista(ys, taus, iters)          # graph replay: same bits
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
+    for i, sc in enumerate(scenes):
+        P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(iters)
+        g = _np(outs[i])
+        single = _np(plans[i].fista(ys[i], taus[i], iters))
+        Fr = P.objective(ref)
+        rel = abs(P.objective(g) - Fr) / Fr
+        eps = np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(f"case batch scene {i} L={sc.L1}x{sc.L2} M={sc.M}: rel F={rel:.2e} eps_r={eps:.2e}", flush=True)
+        assert rel <= OBJ_TOL
+        assert abs(P.objective(single) - P.objective(g)) <= OBJ_TOL * Fr
+    batch.close()
+
+
+def test_batch_invariant_to_scene_order_and_autotune():
+    scenes = [S.batched_scene(100 + i) for i in range(9)]
+    plans, ys, taus = _setup(scenes)
+    b1 = B.Batch(plans)
+    o1 = b1.fista(ys, taus, 60)
+    perm = [4, 0, 8, 2, 6, 1, 7, 3, 5]
+    b2 = B.Batch([plans[i] for i in perm])
+    o2 = b2.fista([ys[i] for i in perm], [taus[i] for i in perm], 60)
+    for k, i in enumerate(perm):
+        assert torch.equal(o2[k], o1[i])
+    b2.autotune(reps=3)
+    o3 = b2.fista([ys[i] for i in perm], [taus[i] for i in perm], 60)
+    for k, i in enumerate(perm):
+        a, b = _np(o3[k]), _np(o1[i])
+        assert np.linalg.norm(a - b) <= 1e-4 * max(np.linalg.norm(b), 1e-30)
+    b1.close()
+    b2.close()
+
+
+def test_batch_edge_cases():
+    scenes = [S.batched_scene(200 + i) for i in range(3)]
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    outs = batch.fista(ys, taus, 0)
+    for o in outs:
+        assert torch.count_nonzero(o) == 0
+    big = [1.01 * p.adjoint_maxabs(y) for p, y in zip(plans, ys)]
+    for o in batch.fista(ys, big, 10):
+        assert torch.count_nonzero(o) == 0
+    bad = [y.clone() for y in ys]
+    bad[1][0] = complex(float("inf"), 0.0)
+    with pytest.raises(B.NonFiniteError):
+        batch.fista(bad, taus, 5)
+    with pytest.raises(B.BCCBError):
+        batch.fista(ys, [-1.0] + taus[1:], 5)
+    batch.close()
+
+
+def test_full_uneven_workload_sampled():
+    """All 4096 scenes of the uneven workload, 300 iterations, in the launch configuration
+    the benchmark times (autotuned); a sample of scenes of every size is checked
+    against the oracle one by one."""
+    n = 4096
+    scenes = [S.batched_scene(i) for i in range(n)]
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    batch.autotune(reps=3)
+    print("classes", batch.classes(), flush=True)
+    outs = batch.fista(ys, taus, 300)
+    sample = {}
+    for i, sc in enumerate(scenes):
+        sample.setdefault(sc.L1, [])
+        if len(sample[sc.L1]) < 2:
+            sample[sc.L1].append(i)
+    for L1, idx in sorted(sample.items()):
+        for i in idx:
+            sc = scenes[i]
+            P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+            ref = P.fista(300)
+            Fr = P.objective(ref)
+            rel = abs(P.objective(_np(outs[i])) - Fr) / Fr
+            print(f"case full-batch scene {i} L={L1}: rel F={rel:.2e}", flush=True)
+            assert rel <= OBJ_TOL
+    batch.close()
+    for p in plans:
+        p.close()
