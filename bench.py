@@ -114,6 +114,87 @@ def batched_runs(args):
     return out
 
 
+def dense_run(B, plan, y, tau, iters=5):
+    """FISTA through the explicit L x L matrix I - mu G (O(L^2) per iteration)."""
+    import torch
+    t0 = time.perf_counter()
+    dense = B.Dense(plan, kind=0)
+    t_build = time.perf_counter() - t0
+    out = plan.grid()
+    dense.solve("fista", y, tau, 1, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dense.solve("fista", y, tau, iters, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dense.close()
+    nbytes = 8.0 * plan.L * plan.L
+    return {"workload": "same 256^2 scene, explicit 65536^2 complex64 I - mu G, FISTA",
+            "iters_per_s": round(iters / dt, 2), "matrix_GB": round(nbytes / 1e9, 2),
+            "matrix_GBps": round(nbytes * iters / dt / 1e9, 1),
+            "frac_hbm_peak": round(nbytes * iters / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "build_s": round(t_build, 3), "iters_timed": iters}
+
+
+def large_admm_run(B, S, iters=300, reps=3):
+    """Single 1024^2 scene, ADMM rho = 0.5, 300 iterations."""
+    import numpy as np
+    import torch
+    sc = S.large_admm_scene(0)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    tuned = plan.autotune(reps=20)
+    out = plan.grid()
+    plan.admm(y, tau, 0.5, iters, z_out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.admm(y, tau, 0.5, iters, z_out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    col_ms, row_ms = plan.profile_passes("admm", reps=100)
+    algo = ALGO_BYTES_PER_POINT["admm"] * plan.L
+    plan.close()
+    return {"workload": "32x32 URA, 256 of 1024 kept, L1=L2=1024, ADMM rho=0.5, 300 iterations",
+            "iters_per_s": round(iters / dt, 1), "s_per_solve": round(dt, 5),
+            "col_pass_us": round(col_ms * 1e3, 2), "row_pass_us": round(row_ms * 1e3, 2),
+            "algorithmic_GBps": round(algo / ((col_ms + row_ms) * 1e-3) / 1e9, 1),
+            "launch_config": tuned}
+
+
+def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000):
+    """Scenes/s to r_KKT <= 1e-4: learned 16-layer network + KKT-gated FISTA vs plain FISTA."""
+    import numpy as np
+    import torch
+    from paper_2509_13592_amd import train_lista as T
+    params, rec = T.load_params()
+    mask = S.learned_fixed_mask()
+    plan = B.Plan(mask, 256, 256)
+    ys, taus = T.make_split(B, plan, 1, 0, n, mask)
+    net = B.Lista(plan, layers=rec["layers"], max_batch=n)
+    out = {}
+    for name, p in (("plain", None), ("learned", params)):
+        net.solve(p, ys[:64].contiguous(), taus[:64], kkt_target=target, check_every=check_every, max_iters=cap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, it, rk, rc = net.solve(p, ys, taus, kkt_target=target, check_every=check_every, max_iters=cap)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"scenes_per_s": round(n / dt, 1), "seconds": round(dt, 3),
+                     "fallback_iters_mean": round(float(it.mean()), 1),
+                     "fallback_iters_median": float(np.median(it)), "fallback_iters_max": int(it.max()),
+                     "unconverged": int((rk > target).sum()), "max_rkkt": float(rk.max())}
+    out["speedup_learned_over_plain"] = round(out["learned"]["scenes_per_s"] / out["plain"]["scenes_per_s"], 4)
+    out["workload"] = (f"{n} held-out scenes, 16x16 URA fixed 64-element mask, 256^2 grid, K~U{{1..8}}, "
+                       f"SNR~U[10,30] dB; target r_KKT <= {target}, checked every {check_every} iterations")
+    out["weights"] = {"train_scenes": rec["train_scenes"], "label_iters": rec["label_iters"],
+                      "steps": rec["steps"], "final_val_loss": rec["val_loss_curve"][-1][1]}
+    net.close()
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +203,10 @@ def main():
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-scenes", type=int, default=8192)
     ap.add_argument("--batch-scenes", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -192,9 +277,16 @@ def main():
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
                      "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
     }
+    # dense explicit-matrix baseline on the same scene (34.4 GB matrix)
+    if not args.no_dense:
+        rec["dense_baseline"] = dense_run(B, plan, y, tau)
     plan.close()
     if not args.no_batch:
         rec["batched"] = batched_runs(args)
+    if not args.no_large:
+        rec["large_admm"] = large_admm_run(B, S)
+    if not args.no_learned:
+        rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, tau)
     print(json.dumps(rec))

@@ -48,6 +48,7 @@ typedef struct { float re, im; } bccb_c32;
 
 enum bccb_status {
   BCCB_OK = 0,
+  BCCB_W_NOT_CONVERGED = 1, /* warning: results written, some scene missed its target     */
   BCCB_E_INVALID = -1,      /* bad argument (null pointer, size, tau < 0, rho <= 0, ...)  */
   BCCB_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. L_i not a power of two)    */
   BCCB_E_NOMEM = -3,        /* device allocation failed                                   */
@@ -181,6 +182,91 @@ int lasso_solve_batch_fista(bccb_batch_t batch, const bccb_c32* const* y, const 
  *   shapes over the whole class (`reps` launches each) and keep the fastest.
  */
 int bccb_batch_autotune(bccb_batch_t batch, int reps);
+
+/*
+ * Learned unrolled FISTA with a KKT-gated plain-FISTA fallback.
+ *
+ * Network (all scenes share one plan, i.e. one array mask and grid): layer k,
+ * k = 0 .. layers-1, is one FISTA step (eqs. (10)-(12)) with its own step
+ * mu_k = s_k / max(Omega), threshold kappa_k = theta_k mu_k tau (tau per scene)
+ * and a BCCB spectrum corrected by a learned 5x5 complex circular convolution,
+ * Omega'_k = Omega + Delta_k (*) Omega (still a BCCB: closure under linear
+ * combination, Sec. III-A (i)):
+ *   u_k = IDFT2((1 - mu_k Omega'_k) . DFT2(z_k)) + mu_k D_s^H y,
+ *   c_k = S_{kappa_k}(u_k),  z_{k+1} = c_k + beta_k (c_k - c_{k-1}),
+ * from z_0 = c_{-1} = 0, with the FISTA momentum weights beta_k.  Output c_{layers-1}.
+ *
+ * Parameters: device float [layers][52] = {s_k, theta_k, Re Delta_k[5][5],
+ * Im Delta_k[5][5]} (row-major taps, tap (a, b), a, b in -2..2, shifts the
+ * spectrum by a along k2 and b along k1).  s = theta = 1, Delta = 0 makes every
+ * layer one plain FISTA iteration.
+ * Snapshots: device complex64 [batch][M]; tau: host float [batch];
+ * grids: device complex64 [batch][L2][L1].
+ */
+typedef struct bccb_lista_s* bccb_lista_t;
+#define BCCB_LISTA_PER_LAYER 52
+
+/* Workspace for up to max_batch scenes; train != 0 also keeps every layer's
+ * activations (16 bytes per grid point per layer per scene) for lista_backward. */
+int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_lista_t* out);
+int lista_destroy(bccb_lista_t net);
+
+/* Forward pass; c_out (nullable) receives c_{layers-1}.  In training mode the
+ * activations are kept for the next lista_backward. */
+int lista_forward(bccb_lista_t net, const float* params, const bccb_c32* y, const float* tau, int batch,
+                  bccb_c32* c_out);
+
+/*
+ * lista_backward -- gradient of loss = mean_s ||c_s - c*_s||^2 / ||c*_s||^2 over the
+ *   batch of the last training-mode forward.  labels: device [batch][L2][L1];
+ *   grad: device float [layers][52] (overwritten); *loss (nullable) the loss.
+ *   The backward of the soft threshold and of each BCCB layer (adjoint spectrum
+ *   conj(1 - mu_k Omega'_k)) runs in the same row/column passes as the forward.
+ */
+int lista_backward(bccb_lista_t net, const float* params, const bccb_c32* labels, float* grad, double* loss);
+
+/* One Adam step on n device floats (bias-corrected, step >= 1).  lr_scale
+ * (device float [n], nullable) multiplies the learning rate per parameter, e.g.
+ * to move the 5x5 filter taps more slowly than the steps and thresholds. */
+int lista_adam(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
+               float beta2, float eps, const float* lr_scale, void* stream);
+
+/*
+ * lista_solve -- KKT-gated solve.  params != NULL: learned forward, then
+ *   plain FISTA (warm start from the network output, momentum restarted)
+ *   on the scenes whose KKT residual r = ||e||/||D_s^H y|| (as in
+ *   bccb_objective_kkt) exceeds kkt_target, checked every check_every
+ *   iterations; converged scenes drop out of the passes.  params == NULL:
+ *   the same plain FISTA from zero with the same checks.  Stops when every
+ *   scene meets the target or after max_iters fallback iterations.
+ *   c_out: device [batch][L2][L1]; iters_out (host int [batch], nullable):
+ *   fallback iterations per scene; rkkt_out (host double [batch], nullable):
+ *   final residuals.  Returns BCCB_W_NOT_CONVERGED (1) if some scene missed
+ *   the target.
+ */
+int lista_solve(bccb_lista_t net, const float* params, const bccb_c32* y, const float* tau, int batch,
+                double kkt_target, int check_every, int max_iters, bccb_c32* c_out, int* iters_out,
+                double* rkkt_out);
+
+/*
+ * Dense "regular" baseline (Sec. II-B and the runtime comparison of Sec. III-C):
+ * the explicit L x L complex64 iteration matrix, multiplied by the iterate
+ * every iteration -- O(L^2) bytes and flops per iteration against the
+ * O(L log L) of the BCCB passes.  kind 0: I - mu G (ISTA, FISTA); kind 1:
+ * (G + rho I)^-1 (ADMM).  The matrix is built on the device from its first
+ * column (property (iv) of Sec. III-A; the column computed in FP64 on the host)
+ * and needs 8 L^2 bytes (34.4 GB at L = 256^2).  BCCB_E_NOMEM if it does not fit.
+ */
+typedef struct bccb_dense_s* bccb_dense_t;
+
+int bccb_dense_create(bccb_plan_t plan, int kind, float rho, bccb_dense_t* out);
+int bccb_dense_destroy(bccb_dense_t dense);
+/* y = R x (x, y device [L2][L1], must not alias) */
+int bccb_dense_apply(bccb_dense_t dense, const bccb_c32* x, bccb_c32* y);
+/* `iters` iterations of solver 0 = ISTA, 1 = FISTA (kind 0 matrix) or 2 = ADMM
+ * (kind 1 matrix; rho fixed at creation), same arithmetic as the BCCB solvers
+ * with every Gram product taken through the dense matrix. */
+int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float tau, int iters, bccb_c32* out);
 
 /*
  * Launch configuration of a plan's passes.  A length-L transform runs as a

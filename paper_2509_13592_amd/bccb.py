@@ -85,6 +85,16 @@ _SIGS = {
     "bccb_batch_info": (_i, [_vp, _pi, _vp, _vp, _vp]),
     "lasso_solve_batch_fista": (_i, [_vp, _vp, _vp, _i, _vp]),
     "bccb_batch_autotune": (_i, [_vp, _i]),
+    "lista_create": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_vp)]),
+    "lista_destroy": (_i, [_vp]),
+    "lista_forward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
+    "lista_backward": (_i, [_vp, _vp, _vp, _vp, _pd]),
+    "lista_adam": (_i, [_vp, _vp, _vp, _vp, _i, _i, _f, _f, _f, _f, _vp, _vp]),
+    "lista_solve": (_i, [_vp, _vp, _vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp]),
+    "bccb_dense_create": (_i, [_vp, _i, _f, ctypes.POINTER(_vp)]),
+    "bccb_dense_destroy": (_i, [_vp]),
+    "bccb_dense_apply": (_i, [_vp, _vp, _vp]),
+    "lasso_solve_dense": (_i, [_vp, _i, _vp, _f, _i, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -293,3 +303,137 @@ class Batch:
         ta = (ctypes.c_float * n)(*[float(t) for t in taus])
         check(lib.lasso_solve_batch_fista(self._h, ya, ta, int(iters), oa), "lasso_solve_batch_fista")
         return outs
+
+
+LISTA_PER_LAYER = 52
+
+
+def _fptr(t):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 GPU tensor")
+    return t.data_ptr()
+
+
+def lista_init_params(layers: int, device="cuda") -> torch.Tensor:
+    """s = theta = 1, Delta = 0: every layer one plain FISTA iteration."""
+    p = torch.zeros((layers, LISTA_PER_LAYER), dtype=torch.float32)
+    p[:, 0] = 1.0
+    p[:, 1] = 1.0
+    return p.to(device)
+
+
+class Lista:
+    """Learned unrolled FISTA on one plan's geometry (device workspace for max_batch scenes)."""
+
+    def __init__(self, plan: Plan, layers: int = 16, max_batch: int = 256, train: bool = False):
+        self.plan = plan
+        self.layers = layers
+        self.max_batch = max_batch
+        self._h = _vp()
+        check(lib.lista_create(plan.handle, layers, max_batch, 1 if train else 0, ctypes.byref(self._h)),
+              "lista_create")
+
+    def close(self):
+        if self._h:
+            lib.lista_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _taus(tau):
+        arr = np.ascontiguousarray(np.asarray(tau, dtype=np.float32))
+        return arr, arr.ctypes.data
+
+    def forward(self, params, ys, taus, out=None):
+        """ys: complex64 [batch][M] device; taus: host floats [batch]."""
+        B = ys.shape[0]
+        if out is None:
+            out = torch.empty((B, self.plan.L2, self.plan.L1), dtype=torch.complex64, device=ys.device)
+        arr, tp = self._taus(taus)
+        check(lib.lista_forward(self._h, _fptr(params), _ptr(ys), tp, B, _ptr(out)), "lista_forward")
+        return out
+
+    def backward(self, params, labels, grad=None):
+        if grad is None:
+            grad = torch.zeros_like(params)
+        loss = ctypes.c_double()
+        check(lib.lista_backward(self._h, _fptr(params), _ptr(labels), _fptr(grad), ctypes.byref(loss)),
+              "lista_backward")
+        return grad, loss.value
+
+    def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None):
+        """KKT-gated solve (params=None: plain FISTA from zero).  Returns (c, iters, rkkt, status)."""
+        B = ys.shape[0]
+        if out is None:
+            out = torch.empty((B, self.plan.L2, self.plan.L1), dtype=torch.complex64, device=ys.device)
+        arr, tp = self._taus(taus)
+        iters = np.zeros(B, dtype=np.int32)
+        rk = np.zeros(B, dtype=np.float64)
+        rc = check(lib.lista_solve(self._h, _fptr(params) if params is not None else None, _ptr(ys), tp, B,
+                                   float(kkt_target), int(check_every), int(max_iters), _ptr(out),
+                                   iters.ctypes.data, rk.ctypes.data), "lista_solve")
+        return out, iters, rk, rc
+
+
+def lista_lr_scale(layers: int, delta_scale: float = 0.02, device="cuda") -> torch.Tensor:
+    """Per-parameter learning-rate multipliers: 1 for s_k and theta_k, delta_scale for the taps."""
+    sc = torch.full((layers, LISTA_PER_LAYER), float(delta_scale), dtype=torch.float32)
+    sc[:, :2] = 1.0
+    return sc.to(device)
+
+
+class Adam:
+    """Adam state for a float32 device parameter tensor; the update runs in the HIP library."""
+
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, lr_scale=None):
+        self.p = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.lr, self.b1, self.b2, self.eps = lr, betas[0], betas[1], eps
+        self.lr_scale = lr_scale
+        self.t = 0
+
+    def step(self, grad):
+        self.t += 1
+        check(lib.lista_adam(_fptr(self.p), _fptr(grad), _fptr(self.m), _fptr(self.v), self.p.numel(), self.t,
+                             self.lr, self.b1, self.b2, self.eps, _fptr(self.lr_scale), current_stream()),
+              "lista_adam")
+
+
+class Dense:
+    """The explicit L x L iteration matrix (kind 0: I - mu G; kind 1: (G + rho I)^-1)."""
+
+    def __init__(self, plan: Plan, kind: int = 0, rho: float = 1.0):
+        self.plan = plan
+        self.kind = kind
+        self._h = _vp()
+        check(lib.bccb_dense_create(plan.handle, int(kind), float(rho), ctypes.byref(self._h)), "bccb_dense_create")
+
+    def close(self):
+        if self._h:
+            lib.bccb_dense_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, x, out=None):
+        out = self.plan.grid(x.device) if out is None else out
+        check(lib.bccb_dense_apply(self._h, _ptr(x), _ptr(out)), "bccb_dense_apply")
+        return out
+
+    def solve(self, solver: str, y, tau: float, iters: int, out=None):
+        code = {"ista": 0, "fista": 1, "admm": 2}[solver]
+        out = self.plan.grid(y.device) if out is None else out
+        check(lib.lasso_solve_dense(self._h, code, _ptr(y), float(tau), int(iters), _ptr(out)), "lasso_solve_dense")
+        return out

@@ -244,6 +244,7 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
         sensors.push_back(make_int2(m1, m2));
       }
   p->M = static_cast<int>(sensors.size());
+  p->mask.assign(mask, mask + static_cast<size_t>(M1) * M2);
 
   // eigenvalues (eq. (21)) in FP64 from the first column of the Gram
   const std::vector<cd> r = gram_first_column(mask, M1, M2, L1, L2);

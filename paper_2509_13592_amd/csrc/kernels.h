@@ -30,6 +30,11 @@ struct RowArgs {
   int rows_per_scene = 1;
   float kappa = 0.f, beta = 0.f, scale = 1.f;
   int last = 0;                  // last iteration: write the outputs, skip the forward DFT
+  float rhs_scale = 1.f;         // ISTA/FISTA: u + rhs_scale * rhs
+  const float* dscal = nullptr;  // device {kappa, rhs_scale} overriding the two scalars (nullable)
+  float2* save_u = nullptr;      // FISTA: store u = IDFT_rows(xy) + rhs_scale*rhs (nullable)
+  float2* save_c = nullptr;      // FISTA: store c_t (nullable)
+  const int* scene_map = nullptr;// logical scene -> physical scene of the arenas (nullable = identity)
 };
 
 // Column pass (transforms along l2, stride L1).
@@ -54,6 +59,7 @@ struct ColArgs {
   int L1 = 0;
   int nscenes = 1;
   float rho = 0.f, scale = 1.f;
+  const int* scene_map = nullptr;// logical scene -> physical scene (nullable = identity)
 };
 
 // Launch shape of the passes for one transform length: E elements per thread
@@ -71,7 +77,8 @@ int launch_col(int N, const PassCfg& cfg, int mode, const ColArgs& a, hipStream_
 
 #define BCCB_DECLARE_N(n)                                                                  \
   int row_launch_##n(int E, int mode, const RowArgs& a, int rpb, hipStream_t s);           \
-  int col_launch_##n(int E, int mode, const ColArgs& a, int W, hipStream_t s);
+  int col_launch_##n(int E, int mode, const ColArgs& a, int W, hipStream_t s);             \
+  int lista_launch_##n(int which, const void* args, int E, int rpb_or_w, int groups, hipStream_t s);
 BCCB_DECLARE_N(8)
 BCCB_DECLARE_N(16)
 BCCB_DECLARE_N(32)
@@ -81,6 +88,67 @@ BCCB_DECLARE_N(256)
 BCCB_DECLARE_N(512)
 BCCB_DECLARE_N(1024)
 #undef BCCB_DECLARE_N
+
+struct ListaBwdRowArgs {
+  const float2* A_in = nullptr;    // row-spectral zbar_{j+1} (nullptr at j = K-1)
+  float2* zbar_store = nullptr;    // spatial zbar_{j+1} written here when A_in is set
+  const float2* zbar2 = nullptr;   // spatial zbar_{j+2} (nullable = 0)
+  const float2* U = nullptr;       // saved u_j
+  const float2* Cm1 = nullptr;     // saved c_{j-1} (nullable = 0)
+  const float2* Cm2 = nullptr;     // saved c_{j-2} (nullable = 0)
+  const float2* b = nullptr;       // D_s^H y per scene
+  const float2* cout = nullptr;    // c_{K-1} (loss gradient at j = K-1)
+  const float2* label = nullptr;   // c* (loss gradient at j = K-1)
+  const double* norm_label = nullptr;  // per scene ||c*||^2
+  const float* tau = nullptr;      // per scene
+  const float* dscal = nullptr;    // layer j {theta_j mu_j, mu_j}
+  float beta_j = 0.f, beta_j1 = 0.f, beta_jm1 = 0.f;
+  float loss_scale = 0.f;          // 2 / batch
+  float2* Aout = nullptr;          // DFT_rows(ubar_j)
+  float2* Zout = nullptr;          // DFT_rows(z_j)
+  double* part = nullptr;          // [rows][2] partial {dkappa, Re<ubar, b>}
+  const float2* tw = nullptr;
+  int nrows = 0, rows_per_scene = 1;
+};
+
+struct ListaBwdColArgs {
+  float2* A = nullptr;             // [B][N][L1] in: DFT_rows(ubar), out: row-spectral zbar
+  const float2* Z = nullptr;       // [B][N][L1] DFT_rows(z_j)
+  const float2* mulc = nullptr;    // [N][L1] m_j / L
+  float2* gm_part = nullptr;       // [groups][N][L1]
+  const float2* tw = nullptr;
+  int L1 = 0, nscenes = 0, groups = 1;
+};
+
+struct KktRowArgs {
+  const float2* gc = nullptr;      // row-spectral G c rows
+  const float2* c = nullptr;
+  const float2* b = nullptr;
+  const float* tau = nullptr;      // per physical scene
+  double* part = nullptr;          // [physical rows] sum of e^2
+  const int* scene_map = nullptr;
+  const float2* tw = nullptr;
+  int nrows = 0, rows_per_scene = 1;
+};
+
+// Dense iteration-matrix product (the O(L^2) baseline).
+struct DenseArgs {
+  const float2* R = nullptr;     // [L][L] row-major, complex64
+  const float2* x = nullptr;     // [L] input
+  float2* out = nullptr;         // [L] product (mode 0) or next input (modes 1, 2)
+  const float2* rhs = nullptr;   // mu*b (mode 1) or w = (G + rho I)^-1 b (mode 2)
+  float2* state = nullptr;       // c_{t-1} (mode 1) or v (mode 2)
+  float2* out_z = nullptr;       // mode 2: z (nullable)
+  long L = 0;
+  float kappa = 0.f, beta = 0.f, rho = 0.f;
+};
+int launch_dense_build(const float2* col, int L1, int L2, float2* R, hipStream_t s);
+int launch_dense_gemv(int mode, const DenseArgs& a, hipStream_t s);
+
+// Learned-FISTA backward and per-scene KKT passes: which = 0 backward row pass
+// (ListaBwdRowArgs), 1 backward column pass (ListaBwdColArgs), 2 KKT row pass
+// (KktRowArgs); E in {4, 8, 16}.
+int lista_launch(int N, int which, const void* args, int E, int rpb_or_w, int groups, hipStream_t s);
 
 // S[k2][k1] = scale * sum over kept elements folding onto (k1, k2) of (-1)^(m1+m2) y_m
 int launch_scatter(const float2* y, const int* sensor_of, int M1, int M2, int L1, int L2,

@@ -183,6 +183,20 @@ int launch_col(int N, const PassCfg& c, int mode, const ColArgs& a, hipStream_t 
   }
 }
 
+int lista_launch(int N, int which, const void* args, int E, int rpb_or_w, int groups, hipStream_t s) {
+  switch (N) {
+    case 8: return lista_launch_8(which, args, E, rpb_or_w, groups, s);
+    case 16: return lista_launch_16(which, args, E, rpb_or_w, groups, s);
+    case 32: return lista_launch_32(which, args, E, rpb_or_w, groups, s);
+    case 64: return lista_launch_64(which, args, E, rpb_or_w, groups, s);
+    case 128: return lista_launch_128(which, args, E, rpb_or_w, groups, s);
+    case 256: return lista_launch_256(which, args, E, rpb_or_w, groups, s);
+    case 512: return lista_launch_512(which, args, E, rpb_or_w, groups, s);
+    case 1024: return lista_launch_1024(which, args, E, rpb_or_w, groups, s);
+    default: return -2;
+  }
+}
+
 int launch_scatter(const float2* y, const int* sensor_of, int M1, int M2, int L1, int L2, float scale,
                    float2* S, int* flag, hipStream_t s) {
   const long L = static_cast<long>(L1) * L2;

@@ -1,0 +1,473 @@
+// Learned unrolled FISTA (forward, backward, Adam) and the KKT-gated solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "bccb.h"
+#include "kernels.h"
+#include "lista.h"
+#include "plan_internal.h"
+
+using namespace bccb;
+
+struct bccb_lista_s {
+  bccb_plan_t plan = nullptr;
+  int K = 0, cap = 0, train = 0, L1 = 0, L2 = 0;
+  long L = 0;
+  hipStream_t stream = nullptr;
+  std::vector<double> beta;        // FISTA momentum weights of the layers
+  PassCfg rcfg, ccfg;              // forward / FISTA pass shapes
+  int bwdE = 16, bwd_rpb = 1, bwd_W = 1, groups = 16;
+
+  float2 *d_b = nullptr, *d_c = nullptr, *d_xy = nullptr, *d_A = nullptr, *d_Z = nullptr;
+  float2* d_ring[2] = {nullptr, nullptr};
+  float2 *d_U = nullptr, *d_C = nullptr;        // [K][cap][L] (training)
+  float2 *d_mulc = nullptr, *d_omp = nullptr;   // [K][L]
+  float* d_dscal = nullptr;                     // [K][2]
+  float* d_tau = nullptr;                       // [cap]
+  float2 *d_coef_fista = nullptr, *d_coef_gram = nullptr;  // [cap]
+  double* d_rows = nullptr;                     // [cap * L2 * 2]
+  float2 *d_gm_part = nullptr, *d_gm = nullptr; // [groups][L], [L]
+  double* d_lg = nullptr;                       // [27][2]
+  double *d_sum_part = nullptr, *d_sums = nullptr, *d_sums2 = nullptr, *d_bnorm = nullptr;  // per scene
+  double* d_rk = nullptr;                       // [cap] sum e^2 per scene
+  SceneDesc* d_desc = nullptr;
+  SceneDesc* h_desc = nullptr;
+  int* d_map = nullptr;
+  int* h_map = nullptr;
+  float* h_tau = nullptr;
+  double* h_tmp = nullptr;
+  int* d_flag = nullptr;
+  int* h_flag = nullptr;
+  int batch = 0;                                // batch of the last training forward
+  bool have_acts = false;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  if (hipMalloc(reinterpret_cast<void**>(p), (n ? n : 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return BCCB_E_NOMEM;
+  }
+  return BCCB_OK;
+}
+
+void lista_free(bccb_lista_s* n) {
+  if (!n) return;
+  void* ptrs[] = {n->d_b, n->d_c, n->d_xy, n->d_A, n->d_Z, n->d_ring[0], n->d_ring[1], n->d_U, n->d_C,
+                  n->d_mulc, n->d_omp, n->d_dscal, n->d_tau, n->d_coef_fista, n->d_coef_gram, n->d_rows,
+                  n->d_gm_part, n->d_gm, n->d_lg, n->d_sum_part, n->d_sums, n->d_sums2, n->d_bnorm, n->d_rk,
+                  n->d_desc, n->d_map, n->d_flag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (n->h_desc) (void)hipHostFree(n->h_desc);
+  if (n->h_map) (void)hipHostFree(n->h_map);
+  if (n->h_tau) (void)hipHostFree(n->h_tau);
+  if (n->h_tmp) (void)hipHostFree(n->h_tmp);
+  if (n->h_flag) (void)hipHostFree(n->h_flag);
+  delete n;
+}
+
+int row(bccb_lista_s* n, int mode, RowArgs a, int nscenes) {
+  a.tw = n->plan->d_tw1;
+  a.nrows = nscenes * n->L2;
+  a.rows_per_scene = n->L2;
+  return kern(launch_row(n->L1, n->rcfg, mode, a, n->stream));
+}
+
+int col(bccb_lista_s* n, int mode, float2* xy, int nscenes, const float2* coef, const float2* mulc, const int* map) {
+  ColArgs a;
+  a.xy = xy;
+  a.omega = n->plan->d_omega;
+  a.omega_stride = 0;
+  a.mulc = mulc;
+  a.mulc_stride = 0;
+  a.coef = coef;
+  a.tw = n->plan->d_tw2;
+  a.L1 = n->L1;
+  a.nscenes = nscenes;
+  a.scene_map = map;
+  return kern(launch_col(n->L2, n->ccfg, mode, a, n->stream));
+}
+
+// b_s = D_s^H y_s for every scene (y contiguous [batch][M]) and tau to the device.
+int setup_rhs(bccb_lista_s* n, const bccb_c32* y, const float* tau, int batch) {
+  bccb_plan_s* p = n->plan;
+  for (int s = 0; s < batch; ++s) {
+    if (!(tau[s] >= 0.f) || !std::isfinite(tau[s])) return BCCB_E_INVALID;
+    SceneDesc& d = n->h_desc[s];
+    d.y = reinterpret_cast<const float2*>(y) + static_cast<size_t>(s) * p->M;
+    d.sensor_of = p->d_sensor_of;
+    d.out = nullptr;
+    d.M1 = p->M1;
+    d.M2 = p->M2;
+    d.scale = 1.f;
+    n->h_tau[s] = tau[s];
+  }
+  BCCB_HIP(hipMemsetAsync(n->d_flag, 0, sizeof(int), n->stream));
+  BCCB_HIP(hipMemcpyAsync(n->d_desc, n->h_desc, batch * sizeof(SceneDesc), hipMemcpyHostToDevice, n->stream));
+  BCCB_HIP(hipMemcpyAsync(n->d_tau, n->h_tau, batch * sizeof(float), hipMemcpyHostToDevice, n->stream));
+  BCCB_TRY(kern(launch_scatter_batch(n->d_desc, batch, n->L1, n->L2, n->d_xy, n->d_flag, n->stream)));
+  BCCB_TRY(col(n, COL_INV, n->d_xy, batch, nullptr, nullptr, nullptr));
+  RowArgs a;
+  a.xy = n->d_xy;
+  a.dst = n->d_b;
+  return row(n, ROW_INV, a, batch);
+}
+
+int finish(bccb_lista_s* n) {
+  BCCB_HIP(hipMemcpyAsync(n->h_flag, n->d_flag, sizeof(int), hipMemcpyDeviceToHost, n->stream));
+  BCCB_HIP(hipStreamSynchronize(n->stream));
+  return *n->h_flag ? BCCB_E_NONFINITE : BCCB_OK;
+}
+
+// The unrolled layers on the current b / tau (c and xy arenas start at zero).
+int run_layers(bccb_lista_s* n, const float* params, int batch, bool save) {
+  BCCB_TRY(kern(lista_prepare(params, n->plan->d_omega, static_cast<float>(n->plan->mu), n->L1, n->L2, n->K, n->d_mulc,
+                              n->d_omp, n->d_dscal, n->stream)));
+  BCCB_TRY(kern(launch_fill(n->d_c, static_cast<long>(batch) * n->L, n->stream)));
+  BCCB_TRY(kern(launch_fill(n->d_xy, static_cast<long>(batch) * n->L, n->stream)));
+  const size_t lay = static_cast<size_t>(n->cap) * n->L;
+  for (int k = 0; k < n->K; ++k) {
+    BCCB_TRY(col(n, COL_FILTER_CPLX, n->d_xy, batch, nullptr, n->d_mulc + k * n->L, nullptr));
+    RowArgs a;
+    a.xy = n->d_xy;
+    a.rhs = n->d_b;
+    a.state = n->d_c;
+    a.kscale = n->d_tau;
+    a.dscal = n->d_dscal + 2 * k;
+    a.beta = static_cast<float>(n->beta[k]);
+    a.last = (k == n->K - 1);
+    if (save) {
+      a.save_u = n->d_U + k * lay;
+      a.save_c = n->d_C + k * lay;
+    }
+    BCCB_TRY(row(n, ROW_FISTA, a, batch));
+  }
+  return BCCB_OK;
+}
+
+// sum of e^2 (KKT residual terms) per physical scene of the map, into d_rk
+int kkt_sums(bccb_lista_s* n, int nact, const int* map) {
+  RowArgs f;
+  f.xy = n->d_A;
+  f.src = n->d_c;
+  f.scene_map = map;
+  BCCB_TRY(row(n, ROW_FWD, f, nact));
+  BCCB_TRY(col(n, COL_FILTER_AFFINE, n->d_A, nact, n->d_coef_gram, nullptr, map));
+  KktRowArgs k;
+  k.gc = n->d_A;
+  k.c = n->d_c;
+  k.b = n->d_b;
+  k.tau = n->d_tau;
+  k.part = n->d_rows;
+  k.scene_map = map;
+  k.tw = n->plan->d_tw1;
+  k.nrows = nact * n->L2;
+  k.rows_per_scene = n->L2;
+  BCCB_TRY(kern(lista_launch(n->L1, 2, &k, n->bwdE, n->bwd_rpb, 1, n->stream)));
+  return kern(rows_to_scene(n->d_rows, n->L2, nact, map, n->d_rk, n->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_lista_t* out) {
+  if (!plan || layers < 1 || layers > 256 || max_batch < 1 || !out) return BCCB_E_INVALID;
+  *out = nullptr;
+  bccb_lista_s* n = new (std::nothrow) bccb_lista_s();
+  if (!n) return BCCB_E_NOMEM;
+  n->plan = plan;
+  n->K = layers;
+  n->cap = max_batch;
+  n->train = train ? 1 : 0;
+  n->L1 = plan->L1;
+  n->L2 = plan->L2;
+  n->L = plan->L;
+  n->stream = plan->stream;
+  double al = 1.0;
+  for (int k = 0; k < layers; ++k) {
+    const double an = (1.0 + std::sqrt(1.0 + 4.0 * al * al)) / 2.0;
+    n->beta.push_back((al - 1.0) / an);
+    al = an;
+  }
+  // throughput shapes: 16 elements per thread, 256-thread blocks
+  n->rcfg.E = n->L1 >= 16 ? 16 : 8;
+  n->rcfg.rpb = std::max(1, 256 / (n->L1 / n->rcfg.E));
+  while (!row_shape_ok(n->L1, n->rcfg) && n->rcfg.rpb > 1) n->rcfg.rpb /= 2;
+  n->ccfg.E = n->L2 >= 16 ? 16 : 8;
+  n->ccfg.W = std::min(n->L1, std::max(1, 256 / (n->L2 / n->ccfg.E)));
+  while (!col_shape_ok(n->L1, n->L2, n->ccfg) && n->ccfg.W > 1) n->ccfg.W /= 2;
+  n->bwdE = n->L1 >= 16 ? 16 : 8;
+  {
+    const int T = n->L1 / n->bwdE;
+    n->bwd_rpb = std::max(1, 128 / T);
+    while (n->bwd_rpb > 1 && (static_cast<long>(n->bwd_rpb + 1) * n->L1 * 8 + static_cast<long>(n->bwd_rpb) * T * 16 > 65536))
+      n->bwd_rpb /= 2;
+    const int Tc = n->L2 / (n->L2 >= 16 ? 16 : 8);
+    n->bwd_W = std::min(n->L1, std::max(1, 128 / Tc));
+    while (n->bwd_W > 1 && static_cast<long>(n->bwd_W + 1) * n->L2 * 8 > 65536) n->bwd_W /= 2;
+  }
+  n->groups = std::max(1, std::min(64, 512 / std::max(1, n->L1 / n->bwd_W)));
+
+  const size_t pts = static_cast<size_t>(max_batch) * n->L;
+  int rc = BCCB_OK;
+  if (rc == BCCB_OK) rc = dalloc(&n->d_b, pts);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_c, pts);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_xy, pts);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_A, pts);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_Z, pts);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_ring[0], pts);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_ring[1], pts);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_U, pts * layers);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_C, pts * layers);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_mulc, static_cast<size_t>(layers) * n->L);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_omp, static_cast<size_t>(layers) * n->L);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_dscal, 2 * layers);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_tau, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_coef_fista, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_coef_gram, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_rows, static_cast<size_t>(max_batch) * n->L2 * 2);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_gm_part, static_cast<size_t>(n->groups) * n->L);
+  if (rc == BCCB_OK && train) rc = dalloc(&n->d_gm, n->L);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_lg, 64);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_sum_part, static_cast<size_t>(max_batch) * kSumBlocksPerScene * 2);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_sums, static_cast<size_t>(max_batch) * 2);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_sums2, static_cast<size_t>(max_batch) * 2);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_bnorm, static_cast<size_t>(max_batch) * 2);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_rk, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_desc, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_map, max_batch);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_flag, 1);
+  if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&n->h_desc), max_batch * sizeof(SceneDesc)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&n->h_map), max_batch * sizeof(int)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&n->h_tau), max_batch * sizeof(float)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&n->h_tmp), max_batch * 2 * sizeof(double)) != hipSuccess ||
+                        hipHostMalloc(reinterpret_cast<void**>(&n->h_flag), sizeof(int)) != hipSuccess))
+    rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK) {
+    const float invL = static_cast<float>(1.0 / static_cast<double>(n->L));
+    std::vector<float2> cf(max_batch, make_float2(invL, static_cast<float>(-plan->mu / static_cast<double>(n->L))));
+    std::vector<float2> cg(max_batch, make_float2(0.f, invL));
+    if (hipMemcpy(n->d_coef_fista, cf.data(), cf.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->d_coef_gram, cg.data(), cg.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      rc = BCCB_E_DEVICE;
+  }
+  if (rc != BCCB_OK) {
+    lista_free(n);
+    return rc;
+  }
+  *out = n;
+  return BCCB_OK;
+}
+
+int lista_destroy(bccb_lista_t n) {
+  if (n) (void)hipStreamSynchronize(n->stream);
+  lista_free(n);
+  return BCCB_OK;
+}
+
+int lista_forward(bccb_lista_t n, const float* params, const bccb_c32* y, const float* tau, int batch,
+                  bccb_c32* c_out) {
+  if (!n || !params || !y || !tau || batch < 1 || batch > n->cap) return BCCB_E_INVALID;
+  BCCB_TRY(setup_rhs(n, y, tau, batch));
+  BCCB_TRY(run_layers(n, params, batch, n->train != 0));
+  if (c_out)
+    BCCB_TRY(kern(launch_copy(reinterpret_cast<float2*>(c_out), n->d_c, static_cast<long>(batch) * n->L, n->stream)));
+  n->batch = batch;
+  n->have_acts = n->train != 0;
+  return finish(n);
+}
+
+int lista_backward(bccb_lista_t n, const float* params, const bccb_c32* labels, float* grad, double* loss) {
+  if (!n || !params || !labels || !grad) return BCCB_E_INVALID;
+  if (!n->have_acts) return BCCB_E_INVALID;
+  const int B = n->batch;
+  const long L = n->L;
+  const size_t lay = static_cast<size_t>(n->cap) * L;
+  const float2* lab = reinterpret_cast<const float2*>(labels);
+  hipStream_t s = n->stream;
+  const float2* cK = n->d_C + (n->K - 1) * lay;
+  // ||c*||^2 and ||c_{K-1} - c*||^2 per scene
+  BCCB_TRY(kern(scene_sums(lab, cK, L, B, n->d_sum_part, n->d_sums, s)));
+  BCCB_HIP(hipMemcpyAsync(n->h_tmp, n->d_sums, B * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> ln(B);
+  BCCB_HIP(hipStreamSynchronize(s));
+  double total = 0.0;
+  for (int i = 0; i < B; ++i) {
+    ln[i] = n->h_tmp[2 * i];
+    if (!(ln[i] > 0.0)) return BCCB_E_INVALID;  // an all-zero label has no relative error
+    total += n->h_tmp[2 * i + 1] / ln[i];
+  }
+  if (loss) *loss = total / B;
+  // norms packed as [B] for the loss gradient (even entries of d_sums2 hold them)
+  BCCB_HIP(hipMemcpyAsync(n->d_bnorm, ln.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
+  BCCB_HIP(hipStreamSynchronize(s));
+  for (int j = n->K - 1; j >= 0; --j) {
+    ListaBwdRowArgs r;
+    r.A_in = (j == n->K - 1) ? nullptr : n->d_A;
+    r.zbar_store = (j == n->K - 1) ? nullptr : n->d_ring[(j + 1) & 1];
+    r.zbar2 = (j + 2 <= n->K - 1) ? n->d_ring[j & 1] : nullptr;
+    r.U = n->d_U + j * lay;
+    r.Cm1 = j >= 1 ? n->d_C + (j - 1) * lay : nullptr;
+    r.Cm2 = j >= 2 ? n->d_C + (j - 2) * lay : nullptr;
+    r.b = n->d_b;
+    r.cout = (j == n->K - 1) ? cK : nullptr;
+    r.label = (j == n->K - 1) ? lab : nullptr;
+    r.norm_label = n->d_bnorm;
+    r.tau = n->d_tau;
+    r.dscal = n->d_dscal + 2 * j;
+    r.beta_j = static_cast<float>(n->beta[j]);
+    r.beta_j1 = (j + 1 < n->K) ? static_cast<float>(n->beta[j + 1]) : 0.f;
+    r.beta_jm1 = j >= 1 ? static_cast<float>(n->beta[j - 1]) : 0.f;
+    r.loss_scale = 2.f / static_cast<float>(B);
+    r.Aout = n->d_A;
+    r.Zout = n->d_Z;
+    r.part = n->d_rows;
+    r.tw = n->plan->d_tw1;
+    r.nrows = B * n->L2;
+    r.rows_per_scene = n->L2;
+    BCCB_TRY(kern(lista_launch(n->L1, 0, &r, n->bwdE, n->bwd_rpb, 1, s)));
+    ListaBwdColArgs c;
+    c.A = n->d_A;
+    c.Z = n->d_Z;
+    c.mulc = n->d_mulc + j * L;
+    c.gm_part = n->d_gm_part;
+    c.tw = n->plan->d_tw2;
+    c.L1 = n->L1;
+    c.nscenes = B;
+    c.groups = n->groups;
+    BCCB_TRY(kern(lista_launch(n->L2, 1, &c, n->L2 >= 16 ? 16 : 8, n->bwd_W, n->groups, s)));
+    BCCB_TRY(kern(lista_layer_grad(n->d_gm_part, n->groups, n->d_gm, n->d_omp + j * L, n->plan->d_omega, n->L1,
+                                   n->L2, n->d_dscal + 2 * j, params + j * kListaPerLayer, n->d_rows, B, n->d_tau,
+                                   n->d_lg, static_cast<float>(n->plan->mu), grad + j * kListaPerLayer, s)));
+  }
+  BCCB_HIP(hipStreamSynchronize(s));
+  return BCCB_OK;
+}
+
+int lista_adam(float* params, const float* grad, float* m, float* v, int cnt, int step, float lr, float beta1,
+               float beta2, float eps, const float* lr_scale, void* stream) {
+  if (!params || !grad || !m || !v || cnt < 1 || step < 1) return BCCB_E_INVALID;
+  const float bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
+  const float bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+  return kern(launch_adam(params, grad, m, v, cnt, lr, beta1, beta2, eps, bc1, bc2, lr_scale,
+                          static_cast<hipStream_t>(stream)));
+}
+
+int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const float* tau, int batch,
+                double kkt_target, int check_every, int max_iters, bccb_c32* c_out, int* iters_out,
+                double* rkkt_out) {
+  if (!n || !y || !tau || !c_out || batch < 1 || batch > n->cap || check_every < 1 || max_iters < 0 ||
+      !(kkt_target > 0.0))
+    return BCCB_E_INVALID;
+  hipStream_t s = n->stream;
+  BCCB_TRY(setup_rhs(n, y, tau, batch));
+  // ||b_s||^2
+  BCCB_TRY(kern(scene_sums(n->d_b, nullptr, n->L, batch, n->d_sum_part, n->d_sums, s)));
+  std::vector<double> bn(batch), rk(batch, 0.0), r0(batch, 0.0);
+  std::vector<int> used(batch, 0);
+  BCCB_HIP(hipMemcpyAsync(n->h_tmp, n->d_sums, batch * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  BCCB_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < batch; ++i) bn[i] = n->h_tmp[2 * i];
+  // d_map always holds the current active list (uploaded whenever it changes;
+  // every upload is followed by a stream synchronisation before h_map is reused)
+  auto upload = [&](const std::vector<int>& act) -> int {
+    const int na = static_cast<int>(act.size());
+    for (int i = 0; i < na; ++i) n->h_map[i] = act[i];
+    if (na) BCCB_HIP(hipMemcpyAsync(n->d_map, n->h_map, na * sizeof(int), hipMemcpyHostToDevice, s));
+    return BCCB_OK;
+  };
+  auto residuals = [&](const std::vector<int>& act, std::vector<double>& r) -> int {
+    const int na = static_cast<int>(act.size());
+    BCCB_TRY(kkt_sums(n, na, n->d_map));
+    BCCB_HIP(hipMemcpyAsync(n->h_tmp, n->d_rk, batch * sizeof(double), hipMemcpyDeviceToHost, s));
+    BCCB_HIP(hipStreamSynchronize(s));
+    for (int i : act) r[i] = bn[i] > 0.0 ? std::sqrt(n->h_tmp[i] / bn[i]) : std::sqrt(n->h_tmp[i]);
+    return BCCB_OK;
+  };
+  std::vector<int> act(batch);
+  for (int i = 0; i < batch; ++i) act[i] = i;
+  BCCB_TRY(upload(act));
+  // residual of the zero start, the reference every warm start must beat
+  BCCB_TRY(kern(launch_fill(n->d_c, static_cast<long>(batch) * n->L, s)));
+  BCCB_TRY(residuals(act, r0));
+  if (params) {
+    BCCB_TRY(run_layers(n, params, batch, false));
+    BCCB_TRY(residuals(act, rk));
+  } else {
+    rk = r0;
+  }
+  {
+    // A network output that is non-finite (e.g. corrupted weights) or farther
+    // from stationarity than zero is discarded: that scene's fallback restarts
+    // from zero, so the gate never does worse than plain FISTA.
+    std::vector<int> keep;
+    for (int i : act) {
+      if (!std::isfinite(rk[i]) || rk[i] > r0[i]) {
+        BCCB_TRY(kern(launch_fill(n->d_c + static_cast<size_t>(i) * n->L, n->L, s)));
+        rk[i] = r0[i];
+      }
+      if (!(rk[i] <= kkt_target)) keep.push_back(i);
+    }
+    act.swap(keep);
+  }
+  int done_iters = 0;
+  double alpha = 1.0;
+  if (!act.empty() && max_iters > 0) {
+    // warm start z^(1) = c^(0) = current c (network output or zeros)
+    const int na = static_cast<int>(act.size());
+    BCCB_TRY(upload(act));
+    RowArgs f;
+    f.xy = n->d_xy;
+    f.src = n->d_c;
+    f.scene_map = n->d_map;
+    BCCB_TRY(row(n, ROW_FWD, f, na));
+  }
+  while (!act.empty() && done_iters < max_iters) {
+    const int na = static_cast<int>(act.size());
+    const int steps = std::min(check_every, max_iters - done_iters);
+    for (int t = 0; t < steps; ++t) {
+      const double an = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+      BCCB_TRY(col(n, COL_FILTER_AFFINE, n->d_xy, na, n->d_coef_fista, nullptr, n->d_map));
+      RowArgs a;
+      a.xy = n->d_xy;
+      a.rhs = n->d_b;
+      a.rhs_scale = static_cast<float>(n->plan->mu);
+      a.state = n->d_c;
+      a.kscale = n->d_tau;
+      a.kappa = static_cast<float>(n->plan->mu);
+      a.beta = static_cast<float>((alpha - 1.0) / an);
+      a.scene_map = n->d_map;
+      alpha = an;
+      BCCB_TRY(row(n, ROW_FISTA, a, na));
+    }
+    done_iters += steps;
+    for (int i : act) used[i] = done_iters;
+    BCCB_TRY(residuals(act, rk));
+    std::vector<int> keep;
+    for (int i : act)
+      if (!(rk[i] <= kkt_target)) keep.push_back(i);
+    if (keep.size() != act.size()) {
+      act.swap(keep);
+      BCCB_TRY(upload(act));
+      BCCB_HIP(hipStreamSynchronize(s));
+    }
+  }
+  BCCB_TRY(kern(launch_copy(reinterpret_cast<float2*>(c_out), n->d_c, static_cast<long>(batch) * n->L, s)));
+  const int rc = finish(n);
+  if (iters_out)
+    for (int i = 0; i < batch; ++i) iters_out[i] = used[i];
+  if (rkkt_out)
+    for (int i = 0; i < batch; ++i) rkkt_out[i] = rk[i];
+  if (rc != BCCB_OK) return rc;
+  return act.empty() ? BCCB_OK : BCCB_W_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -48,7 +48,15 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   const int row = blockIdx.x * rpb + r;
   const bool active = row < a.nrows;
   float2* sm = lds + r * N;
-  const size_t base = static_cast<size_t>(active ? row : 0) * N;
+  // logical row -> physical row of the arenas (scene compaction through scene_map)
+  int scene = 0, prow = 0;
+  if (active) {
+    scene = row / a.rows_per_scene;
+    const int within = row - scene * a.rows_per_scene;
+    if (a.scene_map) scene = a.scene_map[scene];
+    prow = scene * a.rows_per_scene + within;
+  }
+  const size_t base = static_cast<size_t>(prow) * N;
   const float2 zero = make_float2(0.f, 0.f);
 
   // Every global load of the pass is issued before the first barrier so the
@@ -93,19 +101,28 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
     }
   } else {
     F::inverse(v, t, stw, sm, 1);
-    const int scene = active ? row / a.rows_per_scene : 0;
-    const float kappa = a.kscale ? a.kappa * a.kscale[scene] : a.kappa;
+    float kbase = a.kappa, rs = a.rhs_scale;
+    if (a.dscal) {
+      kbase = a.dscal[0];
+      rs = a.dscal[1];
+    }
+    const float kappa = a.kscale ? kbase * a.kscale[scene] : kbase;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const size_t idx = base + F::in_index(t, e);
       if constexpr (MODE == ROW_ISTA) {
-        const float2 c = shrink(cadd(v[e], rhs[e]), kappa);
+        const float2 c = shrink(make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y), kappa);
         if (a.last && active) a.out_c[idx] = c;
         v[e] = c;
       } else if constexpr (MODE == ROW_FISTA) {
-        const float2 c = shrink(cadd(v[e], rhs[e]), kappa);
+        const float2 u = make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y);
+        const float2 c = shrink(u, kappa);
         const float2 cp = st[e];
-        if (active) a.state[idx] = c;
+        if (active) {
+          a.state[idx] = c;
+          if (a.save_u) a.save_u[idx] = u;
+          if (a.save_c) a.save_c[idx] = c;
+        }
         v[e] = make_float2(c.x + a.beta * (c.x - cp.x), c.y + a.beta * (c.y - cp.y));
       } else {  // ROW_ADMM
         const float2 c = cadd(rhs[e], v[e]);
@@ -147,8 +164,9 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   const int nthreads = W * T;
   const int c = tid % W, t = tid / W;
   const int strips = a.L1 / W;
-  const int scene = blockIdx.x / strips;
-  const int col = (blockIdx.x - scene * strips) * W + c;
+  const int lscene = blockIdx.x / strips;
+  const int col = (blockIdx.x - lscene * strips) * W + c;
+  const int scene = a.scene_map ? a.scene_map[lscene] : lscene;
   const size_t plane = static_cast<size_t>(N) * a.L1;
   float2* g = a.xy + scene * plane + col;
   float2* sms = lds + c;

@@ -1,6 +1,7 @@
 // Instantiation of the row/column pass kernels for one transform length,
 // selected at compile time with -DPASS_N=<8..1024>; the build compiles this
 // file once per length so the eight lengths build in parallel.
+#include "lista_passes.h"
 #include "passes.h"
 
 #ifndef PASS_N
@@ -35,6 +36,17 @@ int BCCB_CAT(col_launch_, PASS_N)(int E, int mode, const ColArgs& a, int W, hipS
 #endif
 #if PASS_N >= 32
     case 32: return col_launch_e<PASS_N, 32>(mode, a, W, s);
+#endif
+    default: return -2;
+  }
+}
+
+int BCCB_CAT(lista_launch_, PASS_N)(int which, const void* args, int E, int rpb_or_w, int groups, hipStream_t s) {
+  switch (E) {
+    case 4: return lista_launch_e<PASS_N, 4>(which, args, rpb_or_w, groups, s);
+    case 8: return lista_launch_e<PASS_N, 8>(which, args, rpb_or_w, groups, s);
+#if PASS_N >= 16
+    case 16: return lista_launch_e<PASS_N, 16>(which, args, rpb_or_w, groups, s);
 #endif
     default: return -2;
   }

@@ -7,6 +7,7 @@
 
 #include "bccb.h"
 #include "kernels.h"
+#include "plan_math.h"
 
 struct bccb_plan_s {
   int M1 = 0, M2 = 0, L1 = 0, L2 = 0, M = 0;
@@ -15,6 +16,7 @@ struct bccb_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   std::vector<float> omega32;      // host copy of the FP32 eigenvalue grid [L2][L1]
+  std::vector<uint8_t> mask;       // host copy of the array mask [M2][M1]
 
   float* d_omega = nullptr;        // [L2][L1] eigenvalues (eq. (21)), FP32
   int* d_sensor_of = nullptr;      // [M2][M1] index into y, or -1
@@ -57,6 +59,9 @@ namespace bccb {
 inline int kern(int rc) { return rc == 0 ? BCCB_OK : (rc == -2 ? BCCB_E_UNSUPPORTED : BCCB_E_DEVICE); }
 
 bool elems_ok(int N, int E);
+int adjoint_into(bccb_plan_s* p, const float2* y, float scale, float2* dst);
+int begin_call(bccb_plan_s* p);
+int end_call(bccb_plan_s* p);
 bool row_shape_ok(int L1, const PassCfg& c);
 bool col_shape_ok(int L1, int L2, const PassCfg& c);
 
@@ -77,4 +82,11 @@ float time_launches(hipStream_t s, int reps, F&& launch) {
   return ok ? ms / reps : -1.f;
 }
 
+}  // namespace bccb
+
+namespace bccb {
+// FP64 first column of the plan's Gram (eq. (17), property (iv) of Sec. III-A)
+inline std::vector<cd> gram_first_column_plan(const bccb_plan_s* p) {
+  return gram_first_column(p->mask.data(), p->M1, p->M2, p->L1, p->L2);
+}
 }  // namespace bccb

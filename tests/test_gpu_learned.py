@@ -1,0 +1,183 @@
+"""GPU parity of the learned unrolled FISTA (forward, backward, Adam) and of the
+KKT-gated solve, through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import bccb_oracle as O
+from oracle import learned_oracle as LO
+from paper_2509_13592_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+B = pytest.importorskip("paper_2509_13592_amd.bccb")
+
+
+def _geometry(kind):
+    if kind == "tiny":
+        mask = S.custom_scene(8, 8, 32, 32, 32, K=1, snr_db=20, seed=(31, 0, 0)).mask
+        return mask, 32, 32
+    return S.learned_fixed_mask(), 256, 256
+
+
+def _scenes(mask, L1, L2, n, seed=0):
+    out = []
+    for i in range(n):
+        sc = S.custom_scene(mask.shape[1], mask.shape[0], int(mask.sum()), L1, L2, K=1 + (i % 5), snr_db=15 + i,
+                            seed=(32, seed, i), mask=mask, modulus=(0.5, 1.0))
+        out.append(sc)
+    return out
+
+
+def _oracle_inputs(mask, L1, L2, scenes):
+    op = O.Operator(mask, L1, L2)
+    Om = O.bccb_eigenvalues(mask, L1, L2)
+    mu0 = O.step_size(op)
+    bs, taus = [], []
+    for sc in scenes:
+        b = op.adjoint(sc.y.astype(np.complex64).astype(np.complex128))
+        bs.append(b.reshape(L2, L1))
+        taus.append(float(np.float32(0.1 * np.abs(b).max())))
+    return op, Om, mu0, bs, taus
+
+
+def _random_params(K, seed, scale=0.02):
+    rng = np.random.default_rng(seed)
+    p = LO.init_params(K)
+    p[:, 0] += 0.1 * rng.standard_normal(K)
+    p[:, 1] += 0.1 * rng.standard_normal(K)
+    p[:, 2:] = scale * rng.standard_normal((K, 50))
+    return p
+
+
+def _ys(scenes):
+    return B.to_device(np.stack([sc.y for sc in scenes]))
+
+
+def test_identity_network_is_plain_fista():
+    mask, L1, L2 = _geometry("paper")
+    scenes = _scenes(mask, L1, L2, 3)
+    op, Om, mu0, bs, taus = _oracle_inputs(mask, L1, L2, scenes)
+    plan = B.Plan(mask, L1, L2)
+    K = 16
+    net = B.Lista(plan, layers=K, max_batch=3)
+    c = net.forward(B.lista_init_params(K), _ys(scenes), taus)
+    for i, sc in enumerate(scenes):
+        single = plan.fista(B.to_device(sc.y), taus[i], K)
+        g = c[i].cpu().numpy().reshape(-1).astype(np.complex128)
+        s = single.cpu().numpy().reshape(-1).astype(np.complex128)
+        assert np.linalg.norm(g - s) <= 1e-5 * np.linalg.norm(s)
+        P = O.Problem(mask, L1, L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(K)
+        rel = abs(P.objective(g) - P.objective(ref)) / P.objective(ref)
+        print(f"case identity net scene {i}: rel F vs FP64 FISTA = {rel:.2e}", flush=True)
+        assert rel <= 1e-5
+    net.close()
+
+
+@pytest.mark.parametrize("kind,K", [("tiny", 5), ("paper", 16)])
+def test_forward_matches_oracle(kind, K):
+    mask, L1, L2 = _geometry(kind)
+    scenes = _scenes(mask, L1, L2, 3, seed=1)
+    op, Om, mu0, bs, taus = _oracle_inputs(mask, L1, L2, scenes)
+    p = _random_params(K, 5)
+    plan = B.Plan(mask, L1, L2)
+    net = B.Lista(plan, layers=K, max_batch=3)
+    c = net.forward(torch.tensor(p, dtype=torch.float32, device="cuda"), _ys(scenes), taus)
+    for i in range(3):
+        ref = LO.forward(Om, mu0, p, bs[i], taus[i])
+        g = c[i].cpu().numpy().astype(np.complex128)
+        rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        print(f"case lista forward {kind} K={K} scene {i}: rel err vs FP64 = {rel:.2e}", flush=True)
+        assert rel <= 1e-4
+    net.close()
+
+
+def test_backward_matches_oracle():
+    mask, L1, L2 = _geometry("tiny")
+    K = 4
+    scenes = _scenes(mask, L1, L2, 3, seed=2)
+    op, Om, mu0, bs, taus = _oracle_inputs(mask, L1, L2, scenes)
+    labels = []
+    for i, sc in enumerate(scenes):
+        P = O.Problem(mask, L1, L2, sc.y, tau=taus[i])
+        labels.append(P.fista(100).reshape(L2, L1).astype(np.complex64).astype(np.complex128))
+    p = _random_params(K, 6)
+    loss_ref, g_ref = LO.loss_and_grad(Om, mu0, p, bs, taus, labels)
+    plan = B.Plan(mask, L1, L2)
+    net = B.Lista(plan, layers=K, max_batch=3, train=True)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    net.forward(pt, _ys(scenes), taus)
+    lab = B.to_device(np.stack(labels).astype(np.complex64))
+    g, loss = net.backward(pt, lab)
+    g = g.cpu().numpy().astype(np.float64)
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"case lista backward: loss {loss:.6e} vs {loss_ref:.6e}; max grad err / max grad = {err:.2e}", flush=True)
+    for k in range(K):
+        print("   layer", k, "ds", g[k, 0], g_ref[k, 0], "dtheta", g[k, 1], g_ref[k, 1])
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    assert err <= 1e-3
+    net.close()
+
+
+def test_training_reduces_loss():
+    mask, L1, L2 = _geometry("paper")
+    n = 32
+    scenes = [S.learned_scene(0, i, mask) for i in range(n)]
+    plan = B.Plan(mask, L1, L2)
+    ys = _ys(scenes)
+    taus = [float(np.float32(0.1 * plan.adjoint_maxabs(ys[i]))) for i in range(n)]
+    batch = B.Batch([plan] * n)
+    labels = batch.fista([ys[i] for i in range(n)], taus, 400)
+    lab = torch.stack(labels)
+    K = 16
+    net = B.Lista(plan, layers=K, max_batch=n, train=True)
+    params = B.lista_init_params(K)
+    opt = B.Adam(params, lr=1e-2, lr_scale=B.lista_lr_scale(K, 0.02))
+    losses = []
+    for step in range(25):
+        net.forward(params, ys, taus)
+        g, loss = net.backward(params, lab)
+        losses.append(loss)
+        opt.step(g)
+    print("case training losses", [f"{x:.4f}" for x in losses[::4]], flush=True)
+    assert losses[-1] < 0.98 * losses[0]
+    assert np.all(np.diff(losses) < 1e-3)
+    assert np.all(np.isfinite(losses))
+    net.close()
+    batch.close()
+
+
+def test_kkt_gated_solve():
+    mask, L1, L2 = _geometry("paper")
+    scenes = [S.learned_scene(1, i, mask) for i in range(6)]
+    plan = B.Plan(mask, L1, L2)
+    ys = _ys(scenes)
+    taus = [float(np.float32(0.1 * plan.adjoint_maxabs(ys[i]))) for i in range(6)]
+    K = 16
+    net = B.Lista(plan, layers=K, max_batch=6)
+    target = 1e-3
+    cases = {"plain": None, "identity": B.lista_init_params(K)}
+    bad = B.lista_init_params(K)
+    bad[3, 2] = float("nan")
+    cases["corrupted (NaN)"] = bad
+    zero = B.lista_init_params(K)
+    zero[:, 0] = 0.0
+    cases["zeroed steps"] = zero
+    boom = B.lista_init_params(K)
+    boom[:, 0] = 40.0
+    cases["diverging steps"] = boom
+    for name, params in cases.items():
+        c, iters, rk, rc = net.solve(params, ys, taus, kkt_target=target, check_every=10, max_iters=4000)
+        assert rc == 0, name
+        for i, sc in enumerate(scenes):
+            P = O.Problem(mask, L1, L2, sc.y, tau=taus[i], dense=False)
+            r_ref, _ = P.kkt(c[i].cpu().numpy().reshape(-1).astype(np.complex128))
+            print(f"case kkt solve {name} scene {i}: iters {iters[i]} r_gpu {rk[i]:.3e} r_fp64 {r_ref:.3e}",
+                  flush=True)
+            assert rk[i] <= target
+            assert r_ref <= 1.05 * target
+            assert abs(r_ref - rk[i]) <= 0.05 * target
+    net.close()
