@@ -207,6 +207,9 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
+    ap.add_argument("--only", choices=["all", "single", "batch256", "calib"], default="all",
+                    help="profiling subsets: the single-scene solve only, a uniform 256^2 batch only, "
+                         "or a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -220,6 +223,20 @@ def main():
     from paper_2509_13592_amd import scenes as S
 
     torch.cuda.set_device(0)
+    if args.only == "calib":
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this dispatch calibrate the counters
+        n = 1 << 27
+        a = torch.ones(n, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n * 8, "dispatches": 3}))
+        return
+    if args.only == "batch256":
+        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], 20, reps=2, tune=False)
+        print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": 20, "classes": classes}))
+        return
     sc = S.paper_scale_scene(0)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     y = B.to_device(sc.y)
@@ -277,6 +294,10 @@ def main():
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
                      "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
     }
+    if args.only == "single":
+        plan.close()
+        print(json.dumps(rec))
+        return
     # dense explicit-matrix baseline on the same scene (34.4 GB matrix)
     if not args.no_dense:
         rec["dense_baseline"] = dense_run(B, plan, y, tau)
