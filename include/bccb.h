@@ -278,6 +278,11 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   col_cols_per_block: columns per workgroup, divides L1, (L2/col_elems)*cols <= 256;
  *   use_graph: 1 = capture each solve's iteration loop in a hipGraph (replayed
  *   while the solve arguments repeat), 0 = launch every pass directly.
+ *   spectral_support: 1 = when Omega is sparse (the L1 L2 x fold-count grid of a
+ *   mask, nonzero on at most L/4 bins), apply the multiplier and the right-hand
+ *   side D_s^H y (whose 2D DFT is the scattered snapshot, nonzero on the same
+ *   bins) from a per-column list inside the column pass, so the row pass reads
+ *   no right-hand-side grid; 0 = dense Omega grid and a b grid.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -286,6 +291,7 @@ typedef struct {
   int col_elems;
   int col_cols_per_block;
   int use_graph;
+  int spectral_support;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */

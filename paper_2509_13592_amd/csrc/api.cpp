@@ -62,6 +62,13 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_coef);
   dfree(p->d_red);
   dfree(p->d_flag);
+  dfree(p->d_sup_ptr);
+  dfree(p->d_sup);
+  dfree(p->d_src_ptr);
+  dfree(p->d_src);
+  dfree(p->d_sup_rhs);
+  dfree(p->d_sup_desc);
+  if (p->h_sup_desc) (void)hipHostFree(p->h_sup_desc);
   if (p->h_red) (void)hipHostFree(p->h_red);
   if (p->h_flag) (void)hipHostFree(p->h_flag);
   delete p;
@@ -80,6 +87,9 @@ int col_pass_on(bccb_plan_s* p, const PassCfg& cfg, int mode, float2* xy, const 
                 float scale, hipStream_t s) {
   ColArgs a;
   a.xy = xy;
+  a.sup_ptr = p->d_sup_ptr;
+  a.sup = p->d_sup;
+  a.sup_rhs = p->d_sup_rhs;
   a.omega = p->d_omega;
   a.coef = coef;
   a.tw = p->d_tw2;
@@ -186,6 +196,20 @@ int adjoint_into(bccb_plan_s* p, const float2* y, float scale, float2* dst) {
   return row_pass(p, ROW_INV, a);
 }
 
+bool sparse_on(const bccb_plan_s* p) { return p->has_support && p->use_support; }
+
+// Spectral right-hand side on the support bins: scale * (scattered snapshot).
+int fill_sup_rhs(bccb_plan_s* p, const float2* y, float scale) {
+  SupRhsDesc& d = *p->h_sup_desc;
+  d.y = y;
+  d.entry_off = 0;
+  d.nentries = p->nsup;
+  d.rhs_off = 0;
+  d.scale = scale;
+  BCCB_HIP(hipMemcpyAsync(p->d_sup_desc, p->h_sup_desc, sizeof(SupRhsDesc), hipMemcpyHostToDevice, p->stream));
+  return kern(launch_sup_rhs(p->d_sup_desc, 1, p->nsup, p->d_src_ptr, p->d_src, p->d_sup_rhs, p->d_flag, p->stream));
+}
+
 int begin_call(bccb_plan_s* p) {
   BCCB_HIP(hipMemsetAsync(p->d_flag, 0, sizeof(int), p->stream));
   return BCCB_OK;
@@ -251,12 +275,39 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   const std::vector<cd> om = eigenvalues_eq21(r, L1, L2);
   p->omega32.resize(p->L);
   double omax = 0.0;
-  for (long i = 0; i < p->L; ++i) {
-    const double v = om[i].real();  // G is Hermitian, so Omega is real (imaginary part is rounding)
-    p->omega32[i] = static_cast<float>(v);
-    if (v > omax) omax = v;
-  }
+  for (long i = 0; i < p->L; ++i) omax = std::max(omax, om[i].real());
   p->mu = 1.0 / omax;  // sigma_max(D_s)^2 = lambda_max(G) = max Omega
+  // G is Hermitian PSD, so Omega is real and >= 0; eq. (21) gives L1 L2 times the
+  // number of elements folding onto each bin, so bins no element folds onto hold
+  // only FP64 rounding (~1e-12 of the maximum) and are stored as exact zeros.
+  for (long i = 0; i < p->L; ++i) {
+    const double v = om[i].real();
+    p->omega32[i] = (std::fabs(v) > 1e-9 * omax) ? static_cast<float>(v) : 0.f;
+  }
+  // support list by column, with the snapshot entries folding onto each bin
+  {
+    std::vector<std::vector<int>> bin_src(p->L);
+    for (int m = 0; m < p->M; ++m) {
+      const int m1 = sensors[m].x, m2 = sensors[m].y;
+      const long bin = static_cast<long>(m2 % L2) * L1 + (m1 % L1);
+      bin_src[bin].push_back((m << 1) | ((m1 + m2) & 1));
+    }
+    p->h_sup_ptr.assign(L1 + 1, 0);
+    p->h_src_ptr.assign(1, 0);
+    for (int k1 = 0; k1 < L1; ++k1) {
+      p->h_sup_ptr[k1] = static_cast<int>(p->h_sup.size());
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const long bin = static_cast<long>(k2) * L1 + k1;
+        if (p->omega32[bin] == 0.f && bin_src[bin].empty()) continue;
+        p->h_sup.push_back(bccb::SupEntry{k2, p->omega32[bin]});
+        for (int c : bin_src[bin]) p->h_src.push_back(c);
+        p->h_src_ptr.push_back(static_cast<int>(p->h_src.size()));
+      }
+    }
+    p->h_sup_ptr[L1] = static_cast<int>(p->h_sup.size());
+    p->nsup = static_cast<int>(p->h_sup.size());
+    p->has_support = p->nsup <= p->L / 4;
+  }
 
   std::vector<float2> tw1(L1), tw2(L2);
   {
@@ -284,6 +335,20 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_red), kReduceBlocks * 8 * sizeof(double)) != hipSuccess)
     rc = BCCB_E_NOMEM;
   if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_flag), sizeof(int)) != hipSuccess) rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sup_ptr, p->h_sup_ptr.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sup, p->h_sup.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_src_ptr, p->h_src_ptr.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_src, p->h_src.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sup_rhs, p->h_sup.size());
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sup_desc, 1);
+  if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_sup_desc), sizeof(SupRhsDesc)) != hipSuccess)
+    rc = BCCB_E_NOMEM;
+  if (rc == BCCB_OK &&
+      (hipMemcpy(p->d_sup_ptr, p->h_sup_ptr.data(), p->h_sup_ptr.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+       (p->nsup && hipMemcpy(p->d_sup, p->h_sup.data(), p->h_sup.size() * sizeof(SupEntry), hipMemcpyHostToDevice) != hipSuccess) ||
+       hipMemcpy(p->d_src_ptr, p->h_src_ptr.data(), p->h_src_ptr.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+       (!p->h_src.empty() && hipMemcpy(p->d_src, p->h_src.data(), p->h_src.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)))
+    rc = BCCB_E_DEVICE;
   if (rc == BCCB_OK) {
     const bool ok =
         hipMemcpy(p->d_omega, p->omega32.data(), p->L * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
@@ -375,8 +440,10 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
   float2* out = reinterpret_cast<float2*>(c_out);
   const float2* init = reinterpret_cast<const float2*>(c0);
   BCCB_TRY(begin_call(p));
-  // mu * D_s^H y
-  BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
+  const bool sparse = sparse_on(p);
+  // mu * D_s^H y: on the support bins of the spectrum (sparse) or as a grid
+  if (sparse) BCCB_TRY(fill_sup_rhs(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu)));
+  else BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
   // z^(1) = c^(0): its row DFT starts the first column pass; FISTA keeps c^(t-1) in c_out
   RowArgs f;
   f.xy = p->d_xy;
@@ -390,15 +457,17 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
   const float kappa = static_cast<float>(p->mu * tau);
   if (iters > 0) {
     const unsigned long long key[8] = {static_cast<unsigned long long>(mode), static_cast<unsigned long long>(iters),
-                                       reinterpret_cast<unsigned long long>(out), fbits(kappa), 0, 0, 0, 1};
+                                       reinterpret_cast<unsigned long long>(out), fbits(kappa), 0, 0,
+                                       sparse ? 1ull : 0ull, 1};
     BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
       double alpha = 1.0;
       for (int t = 1; t <= iters; ++t) {
-        BCCB_TRY(col_pass_on(p, p->cfg_col, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, s));
+        BCCB_TRY(col_pass_on(p, p->cfg_col, sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, p->d_xy, p->d_coef,
+                             0.f, 1.f, s));
         const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
         RowArgs a;
         a.xy = p->d_xy;
-        a.rhs = p->d_rhs;
+        a.rhs = sparse ? nullptr : p->d_rhs;
         a.state = out;
         a.out_c = out;
         a.kappa = kappa;
@@ -428,12 +497,16 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
   float2* zo = reinterpret_cast<float2*>(z_out);
   float2* co = reinterpret_cast<float2*>(c_out);
   BCCB_TRY(begin_call(p));
-  // w = (G + rho I)^-1 D_s^H y: the scattered snapshot is already spectral, so
-  // w = IDFT2(S / (Omega + rho)) (unnormalised, since DFT2(b) = L S)
-  BCCB_TRY(kern(launch_scatter(reinterpret_cast<const float2*>(y), p->d_sensor_of, p->M1, p->M2, p->L1, p->L2, 1.f,
-                               p->d_tmp, p->d_flag, p->stream)));
-  BCCB_TRY(col_pass(p, COL_MULINV_ADMM, p->d_tmp, nullptr, rho, 1.f));
-  {
+  const bool sparse = sparse_on(p);
+  // w = (G + rho I)^-1 D_s^H y: the scattered snapshot S is already spectral, so
+  // w = IDFT2(S / (Omega + rho)) (unnormalised, since DFT2(b) = L S).  With the
+  // sparse support S / (Omega + rho) is added in every column pass instead.
+  if (sparse) {
+    BCCB_TRY(fill_sup_rhs(p, reinterpret_cast<const float2*>(y), 1.f));
+  } else {
+    BCCB_TRY(kern(launch_scatter(reinterpret_cast<const float2*>(y), p->d_sensor_of, p->M1, p->M2, p->L1, p->L2, 1.f,
+                                 p->d_tmp, p->d_flag, p->stream)));
+    BCCB_TRY(col_pass(p, COL_MULINV_ADMM, p->d_tmp, nullptr, rho, 1.f));
     RowArgs a;
     a.xy = p->d_tmp;
     a.dst = p->d_rhs;
@@ -450,13 +523,15 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
   if (iters > 0) {
     const unsigned long long key[8] = {static_cast<unsigned long long>(ROW_ADMM), static_cast<unsigned long long>(iters),
                                        reinterpret_cast<unsigned long long>(zo), fbits(kappa),
-                                       reinterpret_cast<unsigned long long>(co), fbits(rho), fbits(scale), 1};
+                                       reinterpret_cast<unsigned long long>(co), fbits(rho), fbits(scale),
+                                       sparse ? 3ull : 1ull};
     BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
       for (int t = 1; t <= iters; ++t) {
-        BCCB_TRY(col_pass_on(p, p->cfg_col, COL_FILTER_ADMM, p->d_xy, nullptr, rho, scale, s));
+        BCCB_TRY(col_pass_on(p, p->cfg_col, sparse ? COL_SPARSE_ADMM : COL_FILTER_ADMM, p->d_xy, nullptr, rho, scale,
+                             s));
         RowArgs a;
         a.xy = p->d_xy;
-        a.rhs = p->d_rhs;
+        a.rhs = sparse ? nullptr : p->d_rhs;
         a.state = p->d_state;
         a.out_z = zo;
         a.out_c = co;
@@ -522,6 +597,7 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->col_elems = p->cfg_col.E;
   cfg->col_cols_per_block = p->cfg_col.W;
   cfg->use_graph = p->use_graph;
+  cfg->spectral_support = p->use_support;
   return BCCB_OK;
 }
 
@@ -536,6 +612,7 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   p->cfg_row = r;
   p->cfg_col = c;
   p->use_graph = cfg->use_graph ? 1 : 0;
+  p->use_support = cfg->spectral_support ? 1 : 0;
   drop_graph(p);
   return BCCB_OK;
 }
@@ -573,11 +650,12 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
       PassCfg d;
       d.E = Es[ei];
       d.W = k;
+      const int cmode = sparse_on(p) ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
       if (rc == BCCB_OK && col_shape_ok(p->L1, p->L2, d)) {
-        rc = col_pass_on(p, d, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
+        rc = col_pass_on(p, d, cmode, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
         if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
         for (int i = 0; i < reps && rc == BCCB_OK; ++i)
-          rc = col_pass_on(p, d, COL_FILTER_AFFINE, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
+          rc = col_pass_on(p, d, cmode, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
         float ms = 0.f;
         if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -612,7 +690,10 @@ int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, dou
   a.kappa = 1.f;
   a.beta = 0.5f;
   const int row_mode = solver == 0 ? ROW_ISTA : (solver == 1 ? ROW_FISTA : ROW_ADMM);
-  const int col_mode = solver == 2 ? COL_FILTER_ADMM : COL_FILTER_AFFINE;
+  const bool sparse = sparse_on(p);
+  const int col_mode = solver == 2 ? (sparse ? COL_SPARSE_ADMM : COL_FILTER_ADMM)
+                                   : (sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE);
+  if (sparse) a.rhs = nullptr;
   const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
   if (hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
   for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = col_pass(p, col_mode, p->d_xy, p->d_coef, 1.f, scale);

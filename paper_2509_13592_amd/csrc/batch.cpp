@@ -35,6 +35,17 @@ struct BatchClass {
   float2* d_rhs = nullptr;        // [n][L] mu_s * b_s
   float2* d_c = nullptr;          // [n][L] FISTA c^(t-1) -> c^(t)
   SceneDesc* d_desc = nullptr;    // [n]
+  // sparse spectral support of every scene, concatenated (see bccb_plan_s)
+  bool sparse = false;
+  int max_entries = 0;
+  std::vector<int> entry_off;     // per scene
+  int* d_sup_ptr = nullptr;       // [n][L1 + 1] global entry offsets
+  SupEntry* d_sup = nullptr;
+  int* d_src_ptr = nullptr;
+  int* d_src = nullptr;
+  float2* d_sup_rhs = nullptr;    // [total entries]
+  SupRhsDesc* d_sdesc = nullptr;  // [n]
+  SupRhsDesc* h_sdesc = nullptr;  // pinned [n]
 };
 
 }  // namespace
@@ -62,8 +73,11 @@ void batch_free(bccb_batch_s* b) {
   for (BatchClass& c : b->cls) {
     for (void* p : {static_cast<void*>(c.d_omega), static_cast<void*>(c.d_coef), static_cast<void*>(c.d_kscale),
                     static_cast<void*>(c.d_xy), static_cast<void*>(c.d_rhs), static_cast<void*>(c.d_c),
-                    static_cast<void*>(c.d_desc)})
+                    static_cast<void*>(c.d_desc), static_cast<void*>(c.d_sup_ptr), static_cast<void*>(c.d_sup),
+                    static_cast<void*>(c.d_src_ptr), static_cast<void*>(c.d_src), static_cast<void*>(c.d_sup_rhs),
+                    static_cast<void*>(c.d_sdesc)})
       if (p) (void)hipFree(p);
+    if (c.h_sdesc) (void)hipHostFree(c.h_sdesc);
   }
   if (b->d_flag) (void)hipFree(b->d_flag);
   if (b->h_flag) (void)hipHostFree(b->h_flag);
@@ -103,6 +117,10 @@ int class_row(const BatchClass& c, const PassCfg& cfg, int mode, RowArgs a, hipS
 int class_col(const BatchClass& c, const PassCfg& cfg, int mode, float2* xy, float scale, hipStream_t s) {
   ColArgs a;
   a.xy = xy;
+  a.sup_ptr = c.d_sup_ptr;
+  a.sup_ptr_stride = c.L1 + 1;
+  a.sup = c.d_sup;
+  a.sup_rhs = c.d_sup_rhs;
   a.omega = c.d_omega;
   a.omega_stride = c.L;
   a.coef = c.d_coef;
@@ -120,10 +138,10 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
     const float beta = static_cast<float>((alpha - 1.0) / alpha_next);
     alpha = alpha_next;
     for (BatchClass& c : b->cls) {
-      BCCB_TRY(class_col(c, c.cfg_col, COL_FILTER_AFFINE, c.d_xy, 1.f, s));
+      BCCB_TRY(class_col(c, c.cfg_col, c.sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, c.d_xy, 1.f, s));
       RowArgs a;
       a.xy = c.d_xy;
-      a.rhs = c.d_rhs;
+      a.rhs = c.sparse ? nullptr : c.d_rhs;
       a.state = c.d_c;
       a.out_c = c.d_c;
       a.kscale = c.d_kscale;
@@ -174,11 +192,42 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
     if (c.n > 65535) rc = BCCB_E_UNSUPPORTED;
     default_batch_cfg(c);
     const size_t pts = static_cast<size_t>(c.n) * c.L;
-    if (rc == BCCB_OK) rc = dalloc(&c.d_omega, pts);
+    c.sparse = true;
+    for (int k = 0; k < c.n; ++k) c.sparse = c.sparse && sparse_on(plans[c.scenes[k]]);
+    if (rc == BCCB_OK && !c.sparse) rc = dalloc(&c.d_omega, pts);  // sparse classes read Omega from the lists
     if (rc == BCCB_OK) rc = dalloc(&c.d_coef, c.n);
     if (rc == BCCB_OK) rc = dalloc(&c.d_kscale, c.n);
     if (rc == BCCB_OK) rc = dalloc(&c.d_xy, pts);
-    if (rc == BCCB_OK) rc = dalloc(&c.d_rhs, pts);
+    if (rc == BCCB_OK && !c.sparse) rc = dalloc(&c.d_rhs, pts);
+    if (rc == BCCB_OK && c.sparse) {
+      std::vector<int> sp, spp(1, 0), src;
+      std::vector<SupEntry> sup;
+      for (int k = 0; k < c.n; ++k) {
+        const bccb_plan_s* p = plans[c.scenes[k]];
+        const int eoff = static_cast<int>(sup.size());
+        const int soff = static_cast<int>(src.size());
+        c.entry_off.push_back(eoff);
+        c.max_entries = std::max(c.max_entries, p->nsup);
+        for (int v : p->h_sup_ptr) sp.push_back(v + eoff);
+        sup.insert(sup.end(), p->h_sup.begin(), p->h_sup.end());
+        for (size_t j = 1; j < p->h_src_ptr.size(); ++j) spp.push_back(p->h_src_ptr[j] + soff);
+        src.insert(src.end(), p->h_src.begin(), p->h_src.end());
+      }
+      rc = dalloc(&c.d_sup_ptr, sp.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sup, sup.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_src_ptr, spp.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_src, src.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sup_rhs, sup.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sdesc, c.n);
+      if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&c.h_sdesc), c.n * sizeof(SupRhsDesc)) != hipSuccess)
+        rc = BCCB_E_NOMEM;
+      if (rc == BCCB_OK &&
+          (hipMemcpy(c.d_sup_ptr, sp.data(), sp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(c.d_sup, sup.data(), sup.size() * sizeof(SupEntry), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(c.d_src_ptr, spp.data(), spp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(c.d_src, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
+        rc = BCCB_E_DEVICE;
+    }
     if (rc == BCCB_OK) rc = dalloc(&c.d_c, pts);
     if (rc == BCCB_OK) rc = dalloc(&c.d_desc, c.n);
     if (rc != BCCB_OK) break;
@@ -187,7 +236,7 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
       const bccb_plan_s* p = plans[c.scenes[k]];
       coef[k] = make_float2(static_cast<float>(1.0 / static_cast<double>(c.L)),
                             static_cast<float>(-p->mu / static_cast<double>(c.L)));
-      if (hipMemcpyAsync(c.d_omega + static_cast<size_t>(k) * c.L, p->d_omega, c.L * sizeof(float),
+      if (!c.sparse && hipMemcpyAsync(c.d_omega + static_cast<size_t>(k) * c.L, p->d_omega, c.L * sizeof(float),
                          hipMemcpyDeviceToDevice, b->stream) != hipSuccess) {
         rc = BCCB_E_DEVICE;
         break;
@@ -255,14 +304,31 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
     BCCB_HIP(hipMemcpyAsync(c.d_kscale, b->h_kscale + off, c.n * sizeof(float), hipMemcpyHostToDevice, s));
     off += c.n;
   }
-  // mu_s * b_s = mu_s * D_s^H y_s for every scene; c^(0) = 0, DFT_rows(z^(1)) = 0
+  // mu_s * b_s = mu_s * D_s^H y_s for every scene (spectral support bins, or a grid);
+  // c^(0) = 0, DFT_rows(z^(1)) = 0
+  off = 0;
   for (BatchClass& c : b->cls) {
-    BCCB_TRY(kern(launch_scatter_batch(c.d_desc, c.n, c.L1, c.L2, c.d_xy, b->d_flag, s)));
-    BCCB_TRY(class_col(c, c.cfg_col, COL_INV, c.d_xy, 1.f, s));
-    RowArgs a;
-    a.xy = c.d_xy;
-    a.dst = c.d_rhs;
-    BCCB_TRY(class_row(c, c.cfg_row, ROW_INV, a, s));
+    if (c.sparse) {
+      for (int k = 0; k < c.n; ++k) {
+        const bccb_plan_s* p = b->plans[c.scenes[k]];
+        SupRhsDesc& d = c.h_sdesc[k];
+        d.y = b->h_desc[off + k].y;
+        d.entry_off = c.entry_off[k];
+        d.nentries = p->nsup;
+        d.rhs_off = c.entry_off[k];
+        d.scale = static_cast<float>(p->mu);
+      }
+      BCCB_HIP(hipMemcpyAsync(c.d_sdesc, c.h_sdesc, c.n * sizeof(SupRhsDesc), hipMemcpyHostToDevice, s));
+      BCCB_TRY(kern(launch_sup_rhs(c.d_sdesc, c.n, c.max_entries, c.d_src_ptr, c.d_src, c.d_sup_rhs, b->d_flag, s)));
+    } else {
+      BCCB_TRY(kern(launch_scatter_batch(c.d_desc, c.n, c.L1, c.L2, c.d_xy, b->d_flag, s)));
+      BCCB_TRY(class_col(c, c.cfg_col, COL_INV, c.d_xy, 1.f, s));
+      RowArgs a;
+      a.xy = c.d_xy;
+      a.dst = c.d_rhs;
+      BCCB_TRY(class_row(c, c.cfg_row, ROW_INV, a, s));
+    }
+    off += c.n;
     BCCB_TRY(kern(launch_fill(c.d_c, static_cast<long>(c.n) * c.L, s)));
     BCCB_TRY(kern(launch_fill(c.d_xy, static_cast<long>(c.n) * c.L, s)));
   }
@@ -312,7 +378,7 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
         if (row_shape_ok(c.L1, r)) {
           RowArgs a;
           a.xy = c.d_xy;
-          a.rhs = c.d_rhs;
+          a.rhs = c.sparse ? nullptr : c.d_rhs;
           a.state = c.d_c;
           a.kscale = c.d_kscale;
           a.kappa = 1.f;
@@ -325,8 +391,8 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
         w.E = E;
         w.W = k;
         if (col_shape_ok(c.L1, c.L2, w)) {
-          const float ms = time_launches(b->stream, reps,
-                                         [&] { return class_col(c, w, COL_FILTER_AFFINE, c.d_xy, 1.f, b->stream); });
+          const int cm = c.sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
+          const float ms = time_launches(b->stream, reps, [&] { return class_col(c, w, cm, c.d_xy, 1.f, b->stream); });
           if (ms < 0.f) return BCCB_E_DEVICE;
           if (ms < best_c) { best_c = ms; bc = w; }
         }

@@ -46,6 +46,18 @@ enum ColMode {
   COL_FILTER_CPLX = 4,  // xy = IDFT_cols(mulc . DFT_cols(xy))
   COL_MULINV_AFFINE = 5,// xy = IDFT_cols((a + b*Omega) . xy)
   COL_MULINV_ADMM = 6,  // xy = IDFT_cols(scale/(Omega + rho) . xy)
+  // Sparse-support forms: Omega is nonzero only on a listed set of bins (the
+  // folded array elements), and the right-hand side of the iteration lives on
+  // the same bins in the spectral domain, so both are applied from a short
+  // per-column list instead of dense grids.
+  COL_SPARSE_AFFINE = 7,// xy = IDFT_cols(m . DFT_cols(xy) + r): m = a off the support, a + b Omega_j on it; r = rhs_j
+  COL_SPARSE_ADMM = 8,  // m = scale/rho off the support, scale/(Omega_j + rho) on it; r = rhs_j/(Omega_j + rho)
+};
+
+// One support bin of a column: spectral row k2 and its eigenvalue.
+struct SupEntry {
+  int k2;
+  float omega;
 };
 
 struct ColArgs {
@@ -60,7 +72,28 @@ struct ColArgs {
   int nscenes = 1;
   float rho = 0.f, scale = 1.f;
   const int* scene_map = nullptr;// logical scene -> physical scene (nullable = identity)
+  // sparse-support modes: entries of (scene s, column k1) are sup[sup_ptr[s*sup_ptr_stride + k1] ..
+  // sup_ptr[s*sup_ptr_stride + k1 + 1]); their right-hand sides are sup_rhs[s*sup_rhs_stride + j]
+  const int* sup_ptr = nullptr;
+  long sup_ptr_stride = 0;
+  const SupEntry* sup = nullptr;
+  const float2* sup_rhs = nullptr;
+  long sup_rhs_stride = 0;
 };
+
+// Spectral right-hand side on the support bins, per scene:
+// rhs[rhs_off + j] = scale * sum over sources q of entry (entry_off + j) of sign_q * y[idx_q].
+struct SupRhsDesc {
+  const float2* y = nullptr;
+  int entry_off = 0;
+  int nentries = 0;
+  long rhs_off = 0;
+  float scale = 1.f;
+  int pad = 0;
+};
+// src_ptr: [entries + 1] offsets into src; src[q] = (sensor index << 1) | (1 if (-1)^(m1+m2) = -1)
+int launch_sup_rhs(const SupRhsDesc* desc, int nscenes, int max_entries, const int* src_ptr, const int* src,
+                   float2* rhs, int* flag, hipStream_t s);
 
 // Launch shape of the passes for one transform length: E elements per thread
 // (T = N/E threads per transform), rows per block of the row pass, columns per

@@ -140,6 +140,25 @@ __global__ void k_gather_batch(const SceneDesc* __restrict__ desc, long L, const
     out[i] = src[scene * L + i];
 }
 
+__global__ void k_sup_rhs(const SupRhsDesc* __restrict__ desc, const int* __restrict__ src_ptr,
+                          const int* __restrict__ src, float2* __restrict__ rhs, int* flag) {
+  const SupRhsDesc d = desc[blockIdx.y];
+  const int jl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jl >= d.nentries) return;
+  const int j = d.entry_off + jl;
+  float2 acc = make_float2(0.f, 0.f);
+  bool ok = true;
+  for (int q = src_ptr[j]; q < src_ptr[j + 1]; ++q) {
+    const int code = src[q];
+    const float2 yv = d.y[code >> 1];
+    ok = ok && finite2(yv);
+    if (code & 1) acc = make_float2(acc.x - yv.x, acc.y - yv.y);
+    else acc = make_float2(acc.x + yv.x, acc.y + yv.y);
+  }
+  if (!ok && flag) *flag = 1;
+  rhs[d.rhs_off + jl] = make_float2(acc.x * d.scale, acc.y * d.scale);
+}
+
 __global__ void k_fill(float2* p, long n) {
   for (long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * blockDim.x)
     p[i] = make_float2(0.f, 0.f);
@@ -246,6 +265,14 @@ int launch_gather_batch(const SceneDesc* desc, int n, long L, const float2* src,
   if (bx > 64) bx = 64;
   const dim3 grid(static_cast<unsigned>(bx), static_cast<unsigned>(n));
   hipLaunchKernelGGL(k_gather_batch, grid, dim3(256), 0, s, desc, L, src);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_sup_rhs(const SupRhsDesc* desc, int nscenes, int max_entries, const int* src_ptr, const int* src,
+                   float2* rhs, int* flag, hipStream_t s) {
+  if (nscenes <= 0 || max_entries <= 0) return 0;
+  const dim3 grid(static_cast<unsigned>((max_entries + 255) / 256), static_cast<unsigned>(nscenes));
+  hipLaunchKernelGGL(k_sup_rhs, grid, dim3(256), 0, s, desc, src_ptr, src, rhs, flag);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

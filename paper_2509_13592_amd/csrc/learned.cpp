@@ -44,6 +44,10 @@ struct bccb_lista_s {
   int* h_flag = nullptr;
   int batch = 0;                                // batch of the last training forward
   bool have_acts = false;
+  // spectral right-hand sides of the fallback FISTA on the plan's support bins
+  float2* d_sup_rhs = nullptr;                  // [cap][nsup]
+  SupRhsDesc* d_sdesc = nullptr;                // [cap]
+  SupRhsDesc* h_sdesc = nullptr;                // pinned [cap]
 };
 
 namespace {
@@ -62,7 +66,7 @@ void lista_free(bccb_lista_s* n) {
   void* ptrs[] = {n->d_b, n->d_c, n->d_xy, n->d_A, n->d_Z, n->d_ring[0], n->d_ring[1], n->d_U, n->d_C,
                   n->d_mulc, n->d_omp, n->d_dscal, n->d_tau, n->d_coef_fista, n->d_coef_gram, n->d_rows,
                   n->d_gm_part, n->d_gm, n->d_lg, n->d_sum_part, n->d_sums, n->d_sums2, n->d_bnorm, n->d_rk,
-                  n->d_desc, n->d_map, n->d_flag};
+                  n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (n->h_desc) (void)hipHostFree(n->h_desc);
@@ -70,6 +74,7 @@ void lista_free(bccb_lista_s* n) {
   if (n->h_tau) (void)hipHostFree(n->h_tau);
   if (n->h_tmp) (void)hipHostFree(n->h_tmp);
   if (n->h_flag) (void)hipHostFree(n->h_flag);
+  if (n->h_sdesc) (void)hipHostFree(n->h_sdesc);
   delete n;
 }
 
@@ -83,6 +88,10 @@ int row(bccb_lista_s* n, int mode, RowArgs a, int nscenes) {
 int col(bccb_lista_s* n, int mode, float2* xy, int nscenes, const float2* coef, const float2* mulc, const int* map) {
   ColArgs a;
   a.xy = xy;
+  a.sup_ptr = n->plan->d_sup_ptr;
+  a.sup = n->plan->d_sup;
+  a.sup_rhs = n->d_sup_rhs;
+  a.sup_rhs_stride = n->plan->nsup;
   a.omega = n->plan->d_omega;
   a.omega_stride = 0;
   a.mulc = mulc;
@@ -245,6 +254,12 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
   if (rc == BCCB_OK) rc = dalloc(&n->d_desc, max_batch);
   if (rc == BCCB_OK) rc = dalloc(&n->d_map, max_batch);
   if (rc == BCCB_OK) rc = dalloc(&n->d_flag, 1);
+  if (rc == BCCB_OK && sparse_on(plan)) {
+    rc = dalloc(&n->d_sup_rhs, static_cast<size_t>(max_batch) * plan->nsup);
+    if (rc == BCCB_OK) rc = dalloc(&n->d_sdesc, max_batch);
+    if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&n->h_sdesc), max_batch * sizeof(SupRhsDesc)) != hipSuccess)
+      rc = BCCB_E_NOMEM;
+  }
   if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&n->h_desc), max_batch * sizeof(SceneDesc)) != hipSuccess ||
                         hipHostMalloc(reinterpret_cast<void**>(&n->h_map), max_batch * sizeof(int)) != hipSuccess ||
                         hipHostMalloc(reinterpret_cast<void**>(&n->h_tau), max_batch * sizeof(float)) != hipSuccess ||
@@ -420,6 +435,21 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
   }
   int done_iters = 0;
   double alpha = 1.0;
+  const bool sparse = n->d_sup_rhs != nullptr;
+  if (sparse && !act.empty() && max_iters > 0) {
+    // mu * D_s^H y of every scene on the support bins of its spectrum
+    bccb_plan_s* p = n->plan;
+    for (int i = 0; i < batch; ++i) {
+      SupRhsDesc& d = n->h_sdesc[i];
+      d.y = reinterpret_cast<const float2*>(y) + static_cast<size_t>(i) * p->M;
+      d.entry_off = 0;
+      d.nentries = p->nsup;
+      d.rhs_off = static_cast<long>(i) * p->nsup;
+      d.scale = static_cast<float>(p->mu);
+    }
+    BCCB_HIP(hipMemcpyAsync(n->d_sdesc, n->h_sdesc, batch * sizeof(SupRhsDesc), hipMemcpyHostToDevice, s));
+    BCCB_TRY(kern(launch_sup_rhs(n->d_sdesc, batch, p->nsup, p->d_src_ptr, p->d_src, n->d_sup_rhs, n->d_flag, s)));
+  }
   if (!act.empty() && max_iters > 0) {
     // warm start z^(1) = c^(0) = current c (network output or zeros)
     const int na = static_cast<int>(act.size());
@@ -435,10 +465,11 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     const int steps = std::min(check_every, max_iters - done_iters);
     for (int t = 0; t < steps; ++t) {
       const double an = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
-      BCCB_TRY(col(n, COL_FILTER_AFFINE, n->d_xy, na, n->d_coef_fista, nullptr, n->d_map));
+      BCCB_TRY(col(n, sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, n->d_xy, na, n->d_coef_fista, nullptr,
+                   n->d_map));
       RowArgs a;
       a.xy = n->d_xy;
-      a.rhs = n->d_b;
+      a.rhs = sparse ? nullptr : n->d_b;
       a.rhs_scale = static_cast<float>(n->plan->mu);
       a.state = n->d_c;
       a.kscale = n->d_tau;

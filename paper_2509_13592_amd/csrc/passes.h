@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   }
   if constexpr (kIter) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) rhs[e] = active ? a.rhs[base + F::in_index(t, e)] : zero;
+    for (int e = 0; e < E; ++e) rhs[e] = (active && a.rhs) ? a.rhs[base + F::in_index(t, e)] : zero;
   }
   if constexpr (kState) {
 #pragma unroll
@@ -171,10 +171,11 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   float2* g = a.xy + scene * plane + col;
   float2* sms = lds + c;
 
+  constexpr bool kSparse = (MODE == COL_SPARSE_AFFINE || MODE == COL_SPARSE_ADMM);
   constexpr bool kFwd = (MODE == COL_FWD || MODE == COL_FILTER_AFFINE || MODE == COL_FILTER_ADMM ||
-                         MODE == COL_FILTER_CPLX);
+                         MODE == COL_FILTER_CPLX || kSparse);
   constexpr bool kInv = (MODE != COL_FWD);
-  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV);
+  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV && !kSparse);
   constexpr bool kCplx = (MODE == COL_FILTER_CPLX);
 
   // all global loads first (iterate, spectral multiplier, twiddles)
@@ -212,6 +213,43 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   } else if constexpr (kMul) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cscale(v[e], a.scale / (om[e] + a.rho));
+  } else if constexpr (kSparse) {
+    // multiplier off the support; the few support bins of this column are then
+    // overwritten by the thread that holds them
+    float mdef;
+    float2 ab = make_float2(0.f, 0.f);
+    if constexpr (MODE == COL_SPARSE_AFFINE) {
+      ab = a.coef[scene];
+      mdef = ab.x;
+    } else {
+      mdef = a.scale / a.rho;
+    }
+    float2 src[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      src[e] = v[e];
+      v[e] = cscale(v[e], mdef);
+    }
+    const int* ptr = a.sup_ptr + scene * a.sup_ptr_stride + col;
+    const int j0 = ptr[0], j1 = ptr[1];
+    const float2* rhs = a.sup_rhs + scene * a.sup_rhs_stride;
+    for (int j = j0; j < j1; ++j) {
+      const SupEntry en = a.sup[j];
+      const float2 r = rhs[j];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (F::out_index(t, e) == en.k2) {
+          if constexpr (MODE == COL_SPARSE_AFFINE) {
+            const float m = ab.x + ab.y * en.omega;
+            v[e] = make_float2(src[e].x * m + r.x, src[e].y * m + r.y);
+          } else {
+            const float d = 1.f / (en.omega + a.rho);
+            const float m = a.scale * d;
+            v[e] = make_float2(src[e].x * m + r.x * d, src[e].y * m + r.y * d);
+          }
+        }
+      }
+    }
   }
 
   if constexpr (kInv) {
@@ -265,6 +303,8 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
     case COL_FILTER_CPLX: hipLaunchKernelGGL((k_col<N, E, COL_FILTER_CPLX>), grid, block, shm, s, a, W); break;
     case COL_MULINV_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_MULINV_AFFINE>), grid, block, shm, s, a, W); break;
     case COL_MULINV_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_MULINV_ADMM>), grid, block, shm, s, a, W); break;
+    case COL_SPARSE_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_AFFINE>), grid, block, shm, s, a, W); break;
+    case COL_SPARSE_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_ADMM>), grid, block, shm, s, a, W); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;

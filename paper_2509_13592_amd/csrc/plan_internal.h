@@ -33,6 +33,22 @@ struct bccb_plan_s {
   double* h_red = nullptr;         // pinned host copy of the partials
   int* h_flag = nullptr;           // pinned host copy of the flag
 
+  // sparse spectral support of Omega (the folded array elements): per column k1 the
+  // bins sup[sup_ptr[k1] .. sup_ptr[k1+1]), and for each bin the snapshot entries
+  // folding onto it, src[src_ptr[j] .. src_ptr[j+1]) = (sensor << 1) | sign bit
+  int nsup = 0;
+  bool has_support = false;
+  std::vector<int> h_sup_ptr, h_src_ptr, h_src;
+  std::vector<bccb::SupEntry> h_sup;
+  int* d_sup_ptr = nullptr;
+  bccb::SupEntry* d_sup = nullptr;
+  int* d_src_ptr = nullptr;
+  int* d_src = nullptr;
+  float2* d_sup_rhs = nullptr;     // [nsup] per solve
+  bccb::SupRhsDesc* d_sup_desc = nullptr;
+  bccb::SupRhsDesc* h_sup_desc = nullptr;  // pinned
+  int use_support = 1;
+
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
   int use_graph = 1;
@@ -60,6 +76,7 @@ inline int kern(int rc) { return rc == 0 ? BCCB_OK : (rc == -2 ? BCCB_E_UNSUPPOR
 
 bool elems_ok(int N, int E);
 int adjoint_into(bccb_plan_s* p, const float2* y, float scale, float2* dst);
+bool sparse_on(const bccb_plan_s* p);
 int begin_call(bccb_plan_s* p);
 int end_call(bccb_plan_s* p);
 bool row_shape_ok(int L1, const PassCfg& c);

@@ -120,3 +120,20 @@ def test_full_uneven_workload_sampled():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_batch_dense_grid_path():
+    """The batch with the spectral support switched off (dense Omega and mu*b grids)."""
+    scenes = [S.batched_scene(300 + i) for i in range(6)]
+    plans, ys, taus = _setup(scenes)
+    for p in plans:
+        p.set_config(spectral_support=0)
+    batch = B.Batch(plans)
+    outs = batch.fista(ys, taus, 80)
+    for i, sc in enumerate(scenes):
+        P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(80)
+        rel = abs(P.objective(_np(outs[i])) - P.objective(ref)) / P.objective(ref)
+        print(f"case dense-grid batch scene {i}: rel F={rel:.2e}", flush=True)
+        assert rel <= OBJ_TOL
+    batch.close()

@@ -236,10 +236,10 @@ def test_full_ura_one_step_exact():
 
 
 CONFIGS_256 = [
-    dict(row_elems=4, row_rows_per_block=1, col_elems=4, col_cols_per_block=1, use_graph=1),
-    dict(row_elems=8, row_rows_per_block=2, col_elems=8, col_cols_per_block=4, use_graph=0),
-    dict(row_elems=16, row_rows_per_block=16, col_elems=16, col_cols_per_block=16, use_graph=1),
-    dict(row_elems=32, row_rows_per_block=4, col_elems=32, col_cols_per_block=8, use_graph=0),
+    dict(row_elems=4, row_rows_per_block=1, col_elems=4, col_cols_per_block=1, use_graph=1, spectral_support=1),
+    dict(row_elems=8, row_rows_per_block=2, col_elems=8, col_cols_per_block=4, use_graph=0, spectral_support=0),
+    dict(row_elems=16, row_rows_per_block=16, col_elems=16, col_cols_per_block=16, use_graph=1, spectral_support=0),
+    dict(row_elems=32, row_rows_per_block=4, col_elems=32, col_cols_per_block=8, use_graph=0, spectral_support=1),
 ]
 
 
@@ -294,4 +294,34 @@ def test_small_and_rectangular_configs(L1, L2):
         print(f"case gram L1={L1} L2={L2} E={E}", flush=True)
         gx = _np(plan.gram_apply(B.to_device(x.reshape(L2, L1))))
         assert np.linalg.norm(gx - ref) <= MATVEC_TOL * np.linalg.norm(ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("geom", ["tiny", "ragged", "aliasing", "paper"])
+def test_sparse_support_path_matches_dense_path(geom):
+    """The spectral-support column pass (Omega and the right-hand side applied on the folded
+    bins only) and the dense-grid path solve the same problem: both within tolerance of the
+    oracle and of each other, for ISTA, FISTA and ADMM."""
+    sc = {"tiny": S.tiny_scene(5),
+          "ragged": S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(12, 1, 0)),
+          "aliasing": S.custom_scene(20, 6, 40, 32, 8, K=2, snr_db=20, seed=(13, 1, 0)),
+          "paper": S.paper_scale_scene(4)}[geom]
+    iters = 150
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    res = {}
+    for sup in (1, 0):
+        plan.set_config(spectral_support=sup)
+        res[sup] = (_np(plan.ista(y, P.tau, iters)), _np(plan.fista(y, P.tau, iters)),
+                    _np(plan.admm(y, P.tau, 4.0, iters)))
+    refs = (P.ista(iters), P.fista(iters), P.admm(4.0, iters)[0])
+    for k, name in enumerate(("ista", "fista", "admm")):
+        Fr = P.objective(refs[k])
+        for sup in (1, 0):
+            rel = abs(P.objective(res[sup][k]) - Fr) / Fr
+            print(f"case support={sup} {geom} {name}: rel F = {rel:.2e}", flush=True)
+            assert rel <= OBJ_TOL
+        a, b = res[1][k], res[0][k]
+        assert np.linalg.norm(a - b) <= 1e-3 * max(np.linalg.norm(b), 1e-30)
     plan.close()
