@@ -283,6 +283,10 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   side D_s^H y (whose 2D DFT is the scattered snapshot, nonzero on the same
  *   bins) from a per-column list inside the column pass, so the row pass reads
  *   no right-hand-side grid; 0 = dense Omega grid and a b grid.
+ *   row_spread, col_spread: 1, 2, 4 or 8 -- launch that many times the blocks
+ *   of a pass and let only every n-th work; on a GPU that deals consecutive
+ *   blocks to its dies round-robin this keeps a single scene's working set in
+ *   one die's L2 between passes.  Timing only.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -292,6 +296,8 @@ typedef struct {
   int col_cols_per_block;
   int use_graph;
   int spectral_support;
+  int row_spread;
+  int col_spread;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */

@@ -30,7 +30,8 @@ class Config(ctypes.Structure):
     """bccb_config: launch shape of a plan's row and column passes."""
     _fields_ = [("row_elems", ctypes.c_int), ("row_rows_per_block", ctypes.c_int),
                 ("col_elems", ctypes.c_int), ("col_cols_per_block", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("spectral_support", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("spectral_support", ctypes.c_int),
+                ("row_spread", ctypes.c_int), ("col_spread", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

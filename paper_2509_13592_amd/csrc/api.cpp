@@ -598,6 +598,8 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->col_cols_per_block = p->cfg_col.W;
   cfg->use_graph = p->use_graph;
   cfg->spectral_support = p->use_support;
+  cfg->row_spread = p->cfg_row.spread;
+  cfg->col_spread = p->cfg_col.spread;
   return BCCB_OK;
 }
 
@@ -606,9 +608,13 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   PassCfg r, c;
   r.E = cfg->row_elems;
   r.rpb = cfg->row_rows_per_block;
+  r.spread = cfg->row_spread;
   c.E = cfg->col_elems;
   c.W = cfg->col_cols_per_block;
-  if (!row_shape_ok(p->L1, r) || !col_shape_ok(p->L1, p->L2, c)) return BCCB_E_INVALID;
+  c.spread = cfg->col_spread;
+  auto spread_ok = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
+  if (!row_shape_ok(p->L1, r) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread))
+    return BCCB_E_INVALID;
   p->cfg_row = r;
   p->cfg_col = c;
   p->use_graph = cfg->use_graph ? 1 : 0;
@@ -632,11 +638,14 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   PassCfg br = p->cfg_row, bc = p->cfg_col;
   int rc = BCCB_OK;
   const int Es[4] = {4, 8, 16, 32};
-  for (int ei = 0; ei < 4 && rc == BCCB_OK; ++ei) {
+  for (int cand = 0; cand < 8 && rc == BCCB_OK; ++cand) {
+    const int ei = cand % 4;
+    const int spread = cand < 4 ? 1 : 8;
     for (int k = 1; k <= 256 && rc == BCCB_OK; k *= 2) {
       PassCfg c;
       c.E = Es[ei];
       c.rpb = k;
+      c.spread = spread;
       if (row_shape_ok(p->L1, c)) {
         rc = row_pass_on(p, c, ROW_FISTA, a, p->stream);  // warm
         if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
@@ -650,6 +659,7 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
       PassCfg d;
       d.E = Es[ei];
       d.W = k;
+      d.spread = spread;
       const int cmode = sparse_on(p) ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
       if (rc == BCCB_OK && col_shape_ok(p->L1, p->L2, d)) {
         rc = col_pass_on(p, d, cmode, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);

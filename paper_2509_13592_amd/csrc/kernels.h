@@ -35,6 +35,7 @@ struct RowArgs {
   float2* save_u = nullptr;      // FISTA: store u = IDFT_rows(xy) + rhs_scale*rhs (nullable)
   float2* save_c = nullptr;      // FISTA: store c_t (nullable)
   const int* scene_map = nullptr;// logical scene -> physical scene of the arenas (nullable = identity)
+  int spread = 1;                // see PassCfg::spread
 };
 
 // Column pass (transforms along l2, stride L1).
@@ -72,6 +73,7 @@ struct ColArgs {
   int nscenes = 1;
   float rho = 0.f, scale = 1.f;
   const int* scene_map = nullptr;// logical scene -> physical scene (nullable = identity)
+  int spread = 1;                // see PassCfg::spread
   // sparse-support modes: entries of (scene s, column k1) are sup[sup_ptr[s*sup_ptr_stride + k1] ..
   // sup_ptr[s*sup_ptr_stride + k1 + 1]); their right-hand sides are sup_rhs[s*sup_rhs_stride + j]
   const int* sup_ptr = nullptr;
@@ -102,6 +104,7 @@ struct PassCfg {
   int E = 16;
   int rpb = 1;
   int W = 1;
+  int spread = 1;  // launch spread x the blocks; only every spread-th does work (1 = off)
 };
 
 // Returns 0, -1 (shape not launchable), -2 (size not compiled), -4 (HIP error).

@@ -174,7 +174,9 @@ __global__ void k_copy(float2* dst, const float2* src, long n) {
 // ---------------------------------------------------------------------------
 }  // namespace
 
-int launch_row(int N, const PassCfg& c, int mode, const RowArgs& a, hipStream_t s) {
+int launch_row(int N, const PassCfg& c, int mode, const RowArgs& a0, hipStream_t s) {
+  RowArgs a = a0;
+  a.spread = c.spread;
   switch (N) {
     case 8: return row_launch_8(c.E, mode, a, c.rpb, s);
     case 16: return row_launch_16(c.E, mode, a, c.rpb, s);
@@ -188,7 +190,9 @@ int launch_row(int N, const PassCfg& c, int mode, const RowArgs& a, hipStream_t 
   }
 }
 
-int launch_col(int N, const PassCfg& c, int mode, const ColArgs& a, hipStream_t s) {
+int launch_col(int N, const PassCfg& c, int mode, const ColArgs& a0, hipStream_t s) {
+  ColArgs a = a0;
+  a.spread = c.spread;
   switch (N) {
     case 8: return col_launch_8(c.E, mode, a, c.W, s);
     case 16: return col_launch_16(c.E, mode, a, c.W, s);

@@ -52,23 +52,42 @@ __global__ __launch_bounds__(256) void k_lista_bwd_row(ListaBwdRowArgs a, int rp
   const size_t base = static_cast<size_t>(prow) * N;
   const float2 zero = make_float2(0.f, 0.f);
 
+  // unconditional loads from valid rows, zeroed afterwards (no flat address selects)
   float2 v[E], zb2[E], u[E], bb[E], c1[E], c2[E], lo[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const size_t ii = base + F::in_index(t, e);
-    v[e] = (active && a.A_in) ? a.A_in[base + F::out_index(t, e)] : zero;
-    zb2[e] = (active && a.zbar2) ? a.zbar2[ii] : zero;
-    u[e] = active ? a.U[ii] : zero;
-    bb[e] = active ? a.b[ii] : zero;
-    c1[e] = (active && a.Cm1) ? a.Cm1[ii] : zero;
-    c2[e] = (active && a.Cm2) ? a.Cm2[ii] : zero;
-    if (a.cout) {
-      const float2 co = active ? a.cout[ii] : zero;
-      const float2 la = active ? a.label[ii] : zero;
-      lo[e] = csub(co, la);
-    } else {
-      lo[e] = zero;
-    }
+    u[e] = a.U[ii];
+    bb[e] = a.b[ii];
+    v[e] = zero;
+    zb2[e] = zero;
+    c1[e] = zero;
+    c2[e] = zero;
+    lo[e] = zero;
+  }
+  if (a.A_in) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = a.A_in[base + F::out_index(t, e)];
+  }
+  if (a.zbar2) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) zb2[e] = a.zbar2[base + F::in_index(t, e)];
+  }
+  if (a.Cm1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c1[e] = a.Cm1[base + F::in_index(t, e)];
+  }
+  if (a.Cm2) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c2[e] = a.Cm2[base + F::in_index(t, e)];
+  }
+  if (a.cout) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) lo[e] = csub(a.cout[base + F::in_index(t, e)], a.label[base + F::in_index(t, e)]);
+  }
+  if (!active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = zb2[e] = u[e] = bb[e] = c1[e] = c2[e] = lo[e] = zero;
   }
   for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
   __syncthreads();
@@ -199,9 +218,13 @@ __global__ __launch_bounds__(256) void k_kkt_row(KktRowArgs a, int rpb) {
   float2 v[E], cc[E], bb[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    v[e] = active ? a.gc[base + F::out_index(t, e)] : zero;
-    cc[e] = active ? a.c[base + F::in_index(t, e)] : zero;
-    bb[e] = active ? a.b[base + F::in_index(t, e)] : zero;
+    v[e] = a.gc[base + F::out_index(t, e)];
+    cc[e] = a.c[base + F::in_index(t, e)];
+    bb[e] = a.b[base + F::in_index(t, e)];
+  }
+  if (!active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cc[e] = bb[e] = zero;
   }
   for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
   __syncthreads();

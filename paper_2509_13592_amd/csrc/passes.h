@@ -33,6 +33,17 @@ __device__ __forceinline__ float2 shrink(float2 z, float k) {
 // Row pass: a block owns `rpb` consecutive rows, T threads each.
 // Dynamic LDS: rpb * N float2 exchange slots + N twiddles.
 // ---------------------------------------------------------------------------
+// With spread > 1 the grid holds spread x the blocks and only every spread-th
+// does work: on a GPU that deals consecutive blocks round-robin to its XCDs
+// this keeps a small (single-scene) working set inside one XCD's L2.
+__device__ __forceinline__ bool spread_block(int spread, int& bid) {
+  bid = static_cast<int>(blockIdx.x);
+  if (spread <= 1) return true;
+  if (bid % spread != 0) return false;
+  bid /= spread;
+  return true;
+}
+
 template <int N, int E, int MODE>
 __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   using F = Stockham<N, E>;
@@ -41,11 +52,13 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   constexpr bool kState = (MODE == ROW_FISTA || MODE == ROW_ADMM);
   extern __shared__ float2 lds[];
   float2* stw = lds + rpb * N;
+  int bid;
+  if (!spread_block(a.spread, bid)) return;  // whole block exits together
 
   const int tid = threadIdx.x;
   const int nthreads = rpb * T;
   const int r = tid / T, t = tid - (tid / T) * T;
-  const int row = blockIdx.x * rpb + r;
+  const int row = bid * rpb + r;
   const bool active = row < a.nrows;
   float2* sm = lds + r * N;
   // logical row -> physical row of the arenas (scene compaction through scene_map)
@@ -62,23 +75,44 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   // Every global load of the pass is issued before the first barrier so the
   // latencies of the iterate, the right-hand side, the state and the twiddle
   // table overlap instead of adding up.
+  // Loads read a valid row (row 0 for inactive threads) and are zeroed afterwards:
+  // selecting between a global address and a local zero would turn them into
+  // flat loads through a stack slot.
   float2 v[E];
   float2 rhs[kIter ? E : 1];
   float2 st[kState ? E : 1];
   if constexpr (MODE == ROW_FWD) {
+    if (a.src) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = (active && a.src) ? a.src[base + F::in_index(t, e)] : zero;
+      for (int e = 0; e < E; ++e) v[e] = a.src[base + F::in_index(t, e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = zero;
+    }
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = active ? a.xy[base + F::out_index(t, e)] : zero;
+    for (int e = 0; e < E; ++e) v[e] = a.xy[base + F::out_index(t, e)];
   }
   if constexpr (kIter) {
+    if (a.rhs) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) rhs[e] = (active && a.rhs) ? a.rhs[base + F::in_index(t, e)] : zero;
+      for (int e = 0; e < E; ++e) rhs[e] = a.rhs[base + F::in_index(t, e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) rhs[e] = zero;
+    }
   }
   if constexpr (kState) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) st[e] = active ? a.state[base + F::in_index(t, e)] : zero;
+    for (int e = 0; e < E; ++e) st[e] = a.state[base + F::in_index(t, e)];
+  }
+  if (!active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = zero;
+      if constexpr (kIter) rhs[e] = zero;
+      if constexpr (kState) st[e] = zero;
+    }
   }
   for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
   __syncthreads();
@@ -159,13 +193,15 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   constexpr int T = F::T;
   extern __shared__ float2 lds[];
   float2* stw = lds + W * N;
+  int bid;
+  if (!spread_block(a.spread, bid)) return;  // whole block exits together
 
   const int tid = threadIdx.x;
   const int nthreads = W * T;
   const int c = tid % W, t = tid / W;
   const int strips = a.L1 / W;
-  const int lscene = blockIdx.x / strips;
-  const int col = (blockIdx.x - lscene * strips) * W + c;
+  const int lscene = bid / strips;
+  const int col = (bid - lscene * strips) * W + c;
   const int scene = a.scene_map ? a.scene_map[lscene] : lscene;
   const size_t plane = static_cast<size_t>(N) * a.L1;
   float2* g = a.xy + scene * plane + col;
@@ -274,7 +310,8 @@ int row_launch_e(int mode, const RowArgs& a, int rpb, hipStream_t s) {
   if (blocks <= 0) return 0;
   const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2);
   if (shm > 65536) return -1;
-  const dim3 grid(blocks), block(rpb * T);
+  const int spread = a.spread > 1 ? a.spread : 1;
+  const dim3 grid(blocks * spread), block(rpb * T);
   switch (mode) {
     case ROW_FWD: hipLaunchKernelGGL((k_row<N, E, ROW_FWD>), grid, block, shm, s, a, rpb); break;
     case ROW_INV: hipLaunchKernelGGL((k_row<N, E, ROW_INV>), grid, block, shm, s, a, rpb); break;
@@ -294,7 +331,8 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
   if (blocks <= 0) return 0;
   const size_t shm = static_cast<size_t>(W + 1) * N * sizeof(float2);
   if (shm > 65536) return -1;
-  const dim3 grid(blocks), block(W * T);
+  const int spread = a.spread > 1 ? a.spread : 1;
+  const dim3 grid(blocks * spread), block(W * T);
   switch (mode) {
     case COL_FWD: hipLaunchKernelGGL((k_col<N, E, COL_FWD>), grid, block, shm, s, a, W); break;
     case COL_INV: hipLaunchKernelGGL((k_col<N, E, COL_INV>), grid, block, shm, s, a, W); break;

@@ -236,10 +236,14 @@ def test_full_ura_one_step_exact():
 
 
 CONFIGS_256 = [
-    dict(row_elems=4, row_rows_per_block=1, col_elems=4, col_cols_per_block=1, use_graph=1, spectral_support=1),
-    dict(row_elems=8, row_rows_per_block=2, col_elems=8, col_cols_per_block=4, use_graph=0, spectral_support=0),
-    dict(row_elems=16, row_rows_per_block=16, col_elems=16, col_cols_per_block=16, use_graph=1, spectral_support=0),
-    dict(row_elems=32, row_rows_per_block=4, col_elems=32, col_cols_per_block=8, use_graph=0, spectral_support=1),
+    dict(row_elems=4, row_rows_per_block=1, col_elems=4, col_cols_per_block=1, use_graph=1, spectral_support=1,
+         row_spread=8, col_spread=8),
+    dict(row_elems=8, row_rows_per_block=2, col_elems=8, col_cols_per_block=4, use_graph=0, spectral_support=0,
+         row_spread=1, col_spread=2),
+    dict(row_elems=16, row_rows_per_block=16, col_elems=16, col_cols_per_block=16, use_graph=1, spectral_support=0,
+         row_spread=4, col_spread=1),
+    dict(row_elems=32, row_rows_per_block=4, col_elems=32, col_cols_per_block=8, use_graph=0, spectral_support=1,
+         row_spread=1, col_spread=1),
 ]
 
 
@@ -273,6 +277,8 @@ def test_results_invariant_to_launch_config():
         plan.set_config(row_elems=3)
     with pytest.raises(B.BCCBError):
         plan.set_config(col_elems=4, col_cols_per_block=3)
+    with pytest.raises(B.BCCBError):
+        plan.set_config(row_spread=3)
     plan.close()
 
 
