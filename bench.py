@@ -190,6 +190,7 @@ def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000):
                        f"SNR~U[10,30] dB; target r_KKT <= {target}, checked every {check_every} iterations")
     out["weights"] = {"train_scenes": rec["train_scenes"], "label_iters": rec["label_iters"],
                       "steps": rec["steps"], "final_val_loss": rec["val_loss_curve"][-1][1]}
+    out["fallback"] = "plain FISTA continuing the unrolled momentum (identity weights = plain FISTA)"
     net.close()
     plan.close()
     return out

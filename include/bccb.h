@@ -233,11 +233,16 @@ int lista_adam(float* params, const float* grad, float* m, float* v, int n, int 
 
 /*
  * lista_solve -- KKT-gated solve.  params != NULL: learned forward, then
- *   plain FISTA (warm start from the network output, momentum restarted)
- *   on the scenes whose KKT residual r = ||e||/||D_s^H y|| (as in
- *   bccb_objective_kkt) exceeds kkt_target, checked every check_every
- *   iterations; converged scenes drop out of the passes.  params == NULL:
- *   the same plain FISTA from zero with the same checks.  Stops when every
+ *   plain FISTA from the network output on the scenes whose KKT residual
+ *   r = ||e||/||D_s^H y|| (as in bccb_objective_kkt) exceeds kkt_target,
+ *   checked every check_every iterations; converged scenes drop out of the
+ *   passes.  restart != 0: the fallback restarts the momentum (z = output,
+ *   alpha = 1); restart == 0: it continues the unrolled FISTA (z from the last
+ *   two layer outputs with the last layer's momentum weight, alpha resumed
+ *   after the layers), so identity weights give exactly plain FISTA.  An output
+ *   that is non-finite or farther from stationarity than zero is replaced by
+ *   zero (and the momentum restarts).  params == NULL: plain FISTA from zero
+ *   with the same checks.  Stops when every
  *   scene meets the target or after max_iters fallback iterations.
  *   c_out: device [batch][L2][L1]; iters_out (host int [batch], nullable):
  *   fallback iterations per scene; rkkt_out (host double [batch], nullable):
@@ -245,7 +250,7 @@ int lista_adam(float* params, const float* grad, float* m, float* v, int n, int 
  *   the target.
  */
 int lista_solve(bccb_lista_t net, const float* params, const bccb_c32* y, const float* tau, int batch,
-                double kkt_target, int check_every, int max_iters, bccb_c32* c_out, int* iters_out,
+                double kkt_target, int check_every, int max_iters, int restart, bccb_c32* c_out, int* iters_out,
                 double* rkkt_out);
 
 /*

@@ -91,7 +91,7 @@ _SIGS = {
     "lista_forward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "lista_backward": (_i, [_vp, _vp, _vp, _vp, _pd]),
     "lista_adam": (_i, [_vp, _vp, _vp, _vp, _i, _i, _f, _f, _f, _f, _vp, _vp]),
-    "lista_solve": (_i, [_vp, _vp, _vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp]),
+    "lista_solve": (_i, [_vp, _vp, _vp, _vp, _i, _d, _i, _i, _i, _vp, _vp, _vp]),
     "bccb_dense_create": (_i, [_vp, _i, _f, ctypes.POINTER(_vp)]),
     "bccb_dense_destroy": (_i, [_vp]),
     "bccb_dense_apply": (_i, [_vp, _vp, _vp]),
@@ -369,8 +369,9 @@ class Lista:
               "lista_backward")
         return grad, loss.value
 
-    def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None):
-        """KKT-gated solve (params=None: plain FISTA from zero).  Returns (c, iters, rkkt, status)."""
+    def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None, restart=False):
+        """KKT-gated solve (params=None: plain FISTA from zero); restart=True restarts the
+        fallback momentum instead of continuing the unrolled FISTA.  Returns (c, iters, rkkt, status)."""
         B = ys.shape[0]
         if out is None:
             out = torch.empty((B, self.plan.L2, self.plan.L1), dtype=torch.complex64, device=ys.device)
@@ -378,7 +379,8 @@ class Lista:
         iters = np.zeros(B, dtype=np.int32)
         rk = np.zeros(B, dtype=np.float64)
         rc = check(lib.lista_solve(self._h, _fptr(params) if params is not None else None, _ptr(ys), tp, B,
-                                   float(kkt_target), int(check_every), int(max_iters), _ptr(out),
+                                   float(kkt_target), int(check_every), int(max_iters), 1 if restart else 0,
+                                   _ptr(out),
                                    iters.ctypes.data, rk.ctypes.data), "lista_solve")
         return out, iters, rk, rc
 

@@ -34,6 +34,7 @@ struct RowArgs {
   const float* dscal = nullptr;  // device {kappa, rhs_scale} overriding the two scalars (nullable)
   float2* save_u = nullptr;      // FISTA: store u = IDFT_rows(xy) + rhs_scale*rhs (nullable)
   float2* save_c = nullptr;      // FISTA: store c_t (nullable)
+  float2* out_prev = nullptr;    // FISTA: store c_{t-1} (the state before the update) (nullable)
   const int* scene_map = nullptr;// logical scene -> physical scene of the arenas (nullable = identity)
   int spread = 1;                // see PassCfg::spread
 };
@@ -198,6 +199,9 @@ int launch_kkt(const float2* c, const float2* b, const float2* gc, float tau, lo
                double* partial, int* nblocks, hipStream_t s);
 int launch_absmax(const float2* b, long L, double* partial, int* nblocks, hipStream_t s);
 int launch_fill(float2* p, long n, hipStream_t s);   // zero fill (graph-safe, no memset node)
+// out = (1 + beta) a - beta b over n scenes of L points selected by map (nullable = identity)
+int launch_momentum(float2* out, const float2* a, const float2* b, float beta, long L, int n, const int* map,
+                    hipStream_t s);
 int launch_copy(float2* dst, const float2* src, long n, hipStream_t s);
 
 constexpr int kReduceBlocks = 512;

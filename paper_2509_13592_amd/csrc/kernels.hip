@@ -164,6 +164,16 @@ __global__ void k_fill(float2* p, long n) {
     p[i] = make_float2(0.f, 0.f);
 }
 
+__global__ void k_momentum(float2* __restrict__ out, const float2* __restrict__ a, const float2* __restrict__ b,
+                           float beta, long L, const int* __restrict__ map) {
+  const int s = map ? map[blockIdx.y] : static_cast<int>(blockIdx.y);
+  const size_t off = static_cast<size_t>(s) * L;
+  for (long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; i < L; i += static_cast<long>(gridDim.x) * blockDim.x) {
+    const float2 x = a[off + i], y = b[off + i];
+    out[off + i] = make_float2(x.x + beta * (x.x - y.x), x.y + beta * (x.y - y.y));
+  }
+}
+
 __global__ void k_copy(float2* dst, const float2* src, long n) {
   for (long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * blockDim.x)
     dst[i] = src[i];
@@ -285,6 +295,16 @@ int launch_fill(float2* p, long n, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) return 0;
   hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_momentum(float2* out, const float2* a, const float2* b, float beta, long L, int n, const int* map,
+                    hipStream_t s) {
+  if (n <= 0) return 0;
+  long bx = (L + 255) / 256;
+  if (bx > 64) bx = 64;
+  hipLaunchKernelGGL(k_momentum, dim3(static_cast<unsigned>(bx), static_cast<unsigned>(n)), dim3(256), 0, s, out, a, b,
+                     beta, L, map);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

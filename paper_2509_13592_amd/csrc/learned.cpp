@@ -19,10 +19,12 @@ struct bccb_lista_s {
   long L = 0;
   hipStream_t stream = nullptr;
   std::vector<double> beta;        // FISTA momentum weights of the layers
+  double alpha_end = 1.0;          // FISTA alpha after the layers (continuation of the schedule)
   PassCfg rcfg, ccfg;              // forward / FISTA pass shapes
   int bwdE = 16, bwd_rpb = 1, bwd_W = 1, groups = 16;
 
   float2 *d_b = nullptr, *d_c = nullptr, *d_xy = nullptr, *d_A = nullptr, *d_Z = nullptr;
+  float2* d_cprev = nullptr;                    // c_{K-2} of the last forward (momentum continuation)
   float2* d_ring[2] = {nullptr, nullptr};
   float2 *d_U = nullptr, *d_C = nullptr;        // [K][cap][L] (training)
   float2 *d_mulc = nullptr, *d_omp = nullptr;   // [K][L]
@@ -63,7 +65,7 @@ int dalloc(T** p, size_t n) {
 
 void lista_free(bccb_lista_s* n) {
   if (!n) return;
-  void* ptrs[] = {n->d_b, n->d_c, n->d_xy, n->d_A, n->d_Z, n->d_ring[0], n->d_ring[1], n->d_U, n->d_C,
+  void* ptrs[] = {n->d_b, n->d_c, n->d_cprev, n->d_xy, n->d_A, n->d_Z, n->d_ring[0], n->d_ring[1], n->d_U, n->d_C,
                   n->d_mulc, n->d_omp, n->d_dscal, n->d_tau, n->d_coef_fista, n->d_coef_gram, n->d_rows,
                   n->d_gm_part, n->d_gm, n->d_lg, n->d_sum_part, n->d_sums, n->d_sums2, n->d_bnorm, n->d_rk,
                   n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
@@ -152,6 +154,7 @@ int run_layers(bccb_lista_s* n, const float* params, int batch, bool save) {
     a.dscal = n->d_dscal + 2 * k;
     a.beta = static_cast<float>(n->beta[k]);
     a.last = (k == n->K - 1);
+    if (a.last) a.out_prev = n->d_cprev;
     if (save) {
       a.save_u = n->d_U + k * lay;
       a.save_c = n->d_C + k * lay;
@@ -206,6 +209,7 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
     n->beta.push_back((al - 1.0) / an);
     al = an;
   }
+  n->alpha_end = al;
   // throughput shapes: 16 elements per thread, 256-thread blocks
   n->rcfg.E = n->L1 >= 16 ? 16 : 8;
   n->rcfg.rpb = std::max(1, 256 / (n->L1 / n->rcfg.E));
@@ -229,6 +233,7 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
   int rc = BCCB_OK;
   if (rc == BCCB_OK) rc = dalloc(&n->d_b, pts);
   if (rc == BCCB_OK) rc = dalloc(&n->d_c, pts);
+  if (rc == BCCB_OK) rc = dalloc(&n->d_cprev, pts);
   if (rc == BCCB_OK) rc = dalloc(&n->d_xy, pts);
   if (rc == BCCB_OK) rc = dalloc(&n->d_A, pts);
   if (rc == BCCB_OK && train) rc = dalloc(&n->d_Z, pts);
@@ -377,7 +382,7 @@ int lista_adam(float* params, const float* grad, float* m, float* v, int cnt, in
 }
 
 int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const float* tau, int batch,
-                double kkt_target, int check_every, int max_iters, bccb_c32* c_out, int* iters_out,
+                double kkt_target, int check_every, int max_iters, int restart, bccb_c32* c_out, int* iters_out,
                 double* rkkt_out) {
   if (!n || !y || !tau || !c_out || batch < 1 || batch > n->cap || check_every < 1 || max_iters < 0 ||
       !(kkt_target > 0.0))
@@ -428,13 +433,17 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
       if (!std::isfinite(rk[i]) || rk[i] > r0[i]) {
         BCCB_TRY(kern(launch_fill(n->d_c + static_cast<size_t>(i) * n->L, n->L, s)));
         rk[i] = r0[i];
+        restart = 1;  // the discarded scene starts over, so the shared momentum does too
       }
       if (!(rk[i] <= kkt_target)) keep.push_back(i);
     }
     act.swap(keep);
   }
+  // Continuing the unrolled FISTA: z = c_{K-1} + beta_{K-1} (c_{K-1} - c_{K-2}) and the
+  // alpha schedule resumes after the K layers; restarting: z = c_{K-1}, alpha = 1.
+  const bool carry = params && !restart;
   int done_iters = 0;
-  double alpha = 1.0;
+  double alpha = carry ? n->alpha_end : 1.0;
   const bool sparse = n->d_sup_rhs != nullptr;
   if (sparse && !act.empty() && max_iters > 0) {
     // mu * D_s^H y of every scene on the support bins of its spectrum
@@ -451,13 +460,18 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     BCCB_TRY(kern(launch_sup_rhs(n->d_sdesc, batch, p->nsup, p->d_src_ptr, p->d_src, n->d_sup_rhs, n->d_flag, s)));
   }
   if (!act.empty() && max_iters > 0) {
-    // warm start z^(1) = c^(0) = current c (network output or zeros)
+    // warm start: z = current c (network output or zeros) or its momentum continuation
     const int na = static_cast<int>(act.size());
     BCCB_TRY(upload(act));
     RowArgs f;
     f.xy = n->d_xy;
     f.src = n->d_c;
     f.scene_map = n->d_map;
+    if (carry) {
+      BCCB_TRY(kern(launch_momentum(n->d_A, n->d_c, n->d_cprev, static_cast<float>(n->beta[n->K - 1]), n->L, na,
+                                    n->d_map, s)));
+      f.src = n->d_A;
+    }
     BCCB_TRY(row(n, ROW_FWD, f, na));
   }
   while (!act.empty() && done_iters < max_iters) {

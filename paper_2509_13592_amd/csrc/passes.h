@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
           a.state[idx] = c;
           if (a.save_u) a.save_u[idx] = u;
           if (a.save_c) a.save_c[idx] = c;
+          if (a.out_prev) a.out_prev[idx] = cp;
         }
         v[e] = make_float2(c.x + a.beta * (c.x - cp.x), c.y + a.beta * (c.y - cp.y));
       } else {  // ROW_ADMM

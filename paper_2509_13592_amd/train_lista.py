@@ -4,7 +4,10 @@ python -m paper_2509_13592_amd.train_lista [--train-scenes N] [--steps S] [--out
 
 Scenes: the fixed 16x16-URA mask with 64 elements, L1 = L2 = 256, K ~ U{1..8}
 targets, SNR ~ U[10, 30] dB (training split 0).  Labels: plain FISTA with
-`--label-iters` iterations from zero (batched solver on the GPU).  The network,
+`--label-iters` iterations from zero (batched solver on the GPU).  The default
+target is 200 iterations: 16 layers can learn to reproduce it (relative error
+~0.27), while 2000-iteration labels are out of their reach (~0.9) and only pull
+the network towards near-zero outputs.  The network,
 its backward and Adam all run in the HIP library; this script only drives them.
 The result is a JSON file with the 16 x 52 parameters and the training record.
 """
@@ -124,11 +127,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-scenes", type=int, default=8192)
     ap.add_argument("--val-scenes", type=int, default=256)
-    ap.add_argument("--label-iters", type=int, default=2000)
+    ap.add_argument("--label-iters", type=int, default=200)
     ap.add_argument("--layers", type=int, default=16)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--steps", type=int, default=1500)
-    ap.add_argument("--lr", type=float, default=0.15)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--lr", type=float, default=0.005)
     ap.add_argument("--delta-lr-scale", type=float, default=0.01)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--log-every", type=int, default=50)

@@ -169,9 +169,17 @@ def test_kkt_gated_solve():
     boom = B.lista_init_params(K)
     boom[:, 0] = 40.0
     cases["diverging steps"] = boom
-    for name, params in cases.items():
-        c, iters, rk, rc = net.solve(params, ys, taus, kkt_target=target, check_every=10, max_iters=4000)
+    runs = [(name, params, False) for name, params in cases.items()] + [("identity, restarted", cases["identity"], True)]
+    plain_iters = None
+    for name, params, restart in runs:
+        c, iters, rk, rc = net.solve(params, ys, taus, kkt_target=target, check_every=10, max_iters=4000,
+                                     restart=restart)
         assert rc == 0, name
+        if name == "plain":
+            plain_iters = iters.copy()
+        if name == "identity":
+            # continuing the unrolled FISTA: 16 layers + fallback = the plain trajectory
+            assert np.all(np.abs(iters + K - plain_iters) <= 20), (iters, plain_iters)
         for i, sc in enumerate(scenes):
             P = O.Problem(mask, L1, L2, sc.y, tau=taus[i], dense=False)
             r_ref, _ = P.kkt(c[i].cpu().numpy().reshape(-1).astype(np.complex128))
