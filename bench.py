@@ -208,9 +208,9 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
-    ap.add_argument("--only", choices=["all", "single", "batch256", "calib"], default="all",
-                    help="profiling subsets: the single-scene solve only, a uniform 256^2 batch only, "
-                         "or a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib"], default="all",
+                    help="subsets: the single-scene solve only, the batched workloads only, a uniform "
+                         "256^2 batch only (profiling), or a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -233,6 +233,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n * 8, "dispatches": 3}))
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": batched_runs(args)}))
         return
     if args.only == "batch256":
         dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], 20, reps=2, tune=False)

@@ -184,6 +184,15 @@ int lasso_solve_batch_fista(bccb_batch_t batch, const bccb_c32* const* y, const 
 int bccb_batch_autotune(bccb_batch_t batch, int reps);
 
 /*
+ * bccb_batch_set_sparse_iterate -- 1 (the default for classes with L1 >= 8):
+ *   keep every scene's FISTA iterate per row in (index, value) slots while the
+ *   row is sparse, as bccb_config.sparse_iterate does for one plan; 0: dense
+ *   iterates.  Same results either way (the stored values are exact).
+ *   BCCB_E_INVALID for a null batch or a value other than 0 or 1.
+ */
+int bccb_batch_set_sparse_iterate(bccb_batch_t batch, int on);
+
+/*
  * Learned unrolled FISTA with a KKT-gated plain-FISTA fallback.
  *
  * Network (all scenes share one plan, i.e. one array mask and grid): layer k,
@@ -292,6 +301,12 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   of a pass and let only every n-th work; on a GPU that deals consecutive
  *   blocks to its dies round-robin this keeps a single scene's working set in
  *   one die's L2 between passes.  Timing only.
+ *   sparse_iterate: 1 = FISTA keeps c^(t) (eq. (11)) per row as up to L1/8
+ *   (column index, value) pairs while the row has that few nonzeros -- after
+ *   the soft threshold (eq. (9)) most rows do -- and as the dense row
+ *   otherwise, so the row pass moves a few bytes per row instead of 16 B per
+ *   grid point for c^(t-1) and c^(t); the values are stored exactly, so the
+ *   iterates are those of the dense form.  Needs L1 >= 8.  0 = dense c^(t).
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -303,6 +318,7 @@ typedef struct {
   int spectral_support;
   int row_spread;
   int col_spread;
+  int sparse_iterate;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */

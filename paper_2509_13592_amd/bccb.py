@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
     _fields_ = [("row_elems", ctypes.c_int), ("row_rows_per_block", ctypes.c_int),
                 ("col_elems", ctypes.c_int), ("col_cols_per_block", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("spectral_support", ctypes.c_int),
-                ("row_spread", ctypes.c_int), ("col_spread", ctypes.c_int)]
+                ("row_spread", ctypes.c_int), ("col_spread", ctypes.c_int),
+                ("sparse_iterate", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -294,6 +295,9 @@ class Batch:
 
     def autotune(self, reps: int = 10):
         check(lib.bccb_batch_autotune(self._h, int(reps)), "bccb_batch_autotune")
+
+    def set_sparse_iterate(self, on: bool):
+        check(lib.bccb_batch_set_sparse_iterate(self._h, 1 if on else 0), "bccb_batch_set_sparse_iterate")
 
     def fista(self, ys, taus, iters: int, outs=None):
         n = self.n

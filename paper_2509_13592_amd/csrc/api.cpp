@@ -58,6 +58,9 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_xy);
   dfree(p->d_rhs);
   dfree(p->d_state);
+  dfree(p->d_cnt);
+  dfree(p->d_sidx);
+  dfree(p->d_sval);
   dfree(p->d_tmp);
   dfree(p->d_coef);
   dfree(p->d_red);
@@ -114,10 +117,11 @@ bool elems_ok(int N, int E) {
   return true;
 }
 
-bool row_shape_ok(int L1, const PassCfg& c) {
+bool row_shape_ok(int L1, const PassCfg& c, bool sparse_iterate) {
   if (!elems_ok(L1, c.E) || c.rpb < 1) return false;
   const int T = L1 / c.E;
-  return c.rpb * T <= 256 && static_cast<long>(c.rpb + 1) * L1 * 8 <= 65536;
+  const long counts = sparse_iterate ? static_cast<long>(c.rpb) * T * 4 : 0;  // per-thread nonzero counts
+  return c.rpb * T <= 256 && static_cast<long>(c.rpb + 1) * L1 * 8 + counts <= 65536;
 }
 
 bool col_shape_ok(int L1, int L2, const PassCfg& c) {
@@ -328,6 +332,11 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   if (rc == BCCB_OK) rc = dmalloc(&p->d_xy, p->L);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_rhs, p->L);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_state, p->L);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_cnt, L2);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sidx, static_cast<size_t>(L2) * (L1 / 8 > 0 ? L1 / 8 : 1));
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sval, static_cast<size_t>(L2) * (L1 / 8 > 0 ? L1 / 8 : 1));
+  // every row starts out dense: no slot is read before the kernel has written it
+  if (rc == BCCB_OK && hipMemset(p->d_cnt, 0x7f, L2 * sizeof(int)) != hipSuccess) rc = BCCB_E_DEVICE;
   if (rc == BCCB_OK) rc = dmalloc(&p->d_tmp, p->L);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_red, static_cast<size_t>(kReduceBlocks) * 8);
@@ -455,8 +464,11 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
     else if (!init) BCCB_TRY(kern(launch_fill(out, p->L, p->stream)));
   }
   const float kappa = static_cast<float>(p->mu * tau);
+  // FISTA with the iterate in per-row slots: c^(0) is read densely (all counts "dense")
+  const int rmode = (mode == ROW_FISTA && p->sparse_iterate) ? ROW_FISTA_SP : mode;
+  if (rmode == ROW_FISTA_SP) BCCB_TRY(kern(launch_fill_int(p->d_cnt, p->L2, p->L1 + 1, p->stream)));
   if (iters > 0) {
-    const unsigned long long key[8] = {static_cast<unsigned long long>(mode), static_cast<unsigned long long>(iters),
+    const unsigned long long key[8] = {static_cast<unsigned long long>(rmode), static_cast<unsigned long long>(iters),
                                        reinterpret_cast<unsigned long long>(out), fbits(kappa), 0, 0,
                                        sparse ? 1ull : 0ull, 1};
     BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
@@ -470,11 +482,14 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
         a.rhs = sparse ? nullptr : p->d_rhs;
         a.state = out;
         a.out_c = out;
+        a.cnt = p->d_cnt;
+        a.sidx = p->d_sidx;
+        a.sval = p->d_sval;
         a.kappa = kappa;
         a.beta = static_cast<float>((alpha - 1.0) / alpha_next);
         a.last = (t == iters);
         alpha = alpha_next;
-        BCCB_TRY(row_pass_on(p, p->cfg_row, mode, a, s));
+        BCCB_TRY(row_pass_on(p, p->cfg_row, rmode, a, s));
       }
       return BCCB_OK;
     }));
@@ -600,6 +615,7 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->spectral_support = p->use_support;
   cfg->row_spread = p->cfg_row.spread;
   cfg->col_spread = p->cfg_col.spread;
+  cfg->sparse_iterate = p->sparse_iterate;
   return BCCB_OK;
 }
 
@@ -613,12 +629,15 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   c.W = cfg->col_cols_per_block;
   c.spread = cfg->col_spread;
   auto spread_ok = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
-  if (!row_shape_ok(p->L1, r) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread))
+  const bool spi = cfg->sparse_iterate != 0;
+  if (!row_shape_ok(p->L1, r, spi) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread) ||
+      (spi && p->L1 < 8))
     return BCCB_E_INVALID;
   p->cfg_row = r;
   p->cfg_col = c;
   p->use_graph = cfg->use_graph ? 1 : 0;
   p->use_support = cfg->spectral_support ? 1 : 0;
+  p->sparse_iterate = spi ? 1 : 0;
   drop_graph(p);
   return BCCB_OK;
 }
@@ -630,10 +649,15 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   BCCB_HIP(hipEventCreate(&e1));
   RowArgs a;
   a.xy = p->d_xy;
-  a.rhs = p->d_rhs;
+  a.rhs = sparse_on(p) ? nullptr : p->d_rhs;
   a.state = p->d_state;
+  a.cnt = p->d_cnt;
+  a.sidx = p->d_sidx;
+  a.sval = p->d_sval;
   a.kappa = 1.f;
   a.beta = 0.5f;
+  const bool spi = p->sparse_iterate != 0;
+  const int rmode = spi ? ROW_FISTA_SP : ROW_FISTA;
   float best_r = 1e30f, best_c = 1e30f;
   PassCfg br = p->cfg_row, bc = p->cfg_col;
   int rc = BCCB_OK;
@@ -646,10 +670,10 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
       c.E = Es[ei];
       c.rpb = k;
       c.spread = spread;
-      if (row_shape_ok(p->L1, c)) {
-        rc = row_pass_on(p, c, ROW_FISTA, a, p->stream);  // warm
+      if (row_shape_ok(p->L1, c, spi)) {
+        rc = row_pass_on(p, c, rmode, a, p->stream);  // warm
         if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
-        for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass_on(p, c, ROW_FISTA, a, p->stream);
+        for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass_on(p, c, rmode, a, p->stream);
         float ms = 0.f;
         if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -697,9 +721,13 @@ int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, dou
   a.state = p->d_state;
   a.out_z = p->d_tmp;
   a.out_c = p->d_tmp;
+  a.cnt = p->d_cnt;
+  a.sidx = p->d_sidx;
+  a.sval = p->d_sval;
   a.kappa = 1.f;
   a.beta = 0.5f;
-  const int row_mode = solver == 0 ? ROW_ISTA : (solver == 1 ? ROW_FISTA : ROW_ADMM);
+  const int row_mode = solver == 0 ? ROW_ISTA
+                                   : (solver == 1 ? (p->sparse_iterate ? ROW_FISTA_SP : ROW_FISTA) : ROW_ADMM);
   const bool sparse = sparse_on(p);
   const int col_mode = solver == 2 ? (sparse ? COL_SPARSE_ADMM : COL_FILTER_ADMM)
                                    : (sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE);

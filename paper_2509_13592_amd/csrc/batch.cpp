@@ -34,6 +34,11 @@ struct BatchClass {
   float2* d_xy = nullptr;         // [n][L]
   float2* d_rhs = nullptr;        // [n][L] mu_s * b_s
   float2* d_c = nullptr;          // [n][L] FISTA c^(t-1) -> c^(t)
+  // FISTA iterate in per-row slots while the row is sparse (ROW_FISTA_SP)
+  bool sp_iter = false;
+  int* d_cnt = nullptr;           // [n][L2]
+  unsigned short* d_sidx = nullptr;  // [n][L2][L1/8]
+  float2* d_sval = nullptr;       // [n][L2][L1/8]
   SceneDesc* d_desc = nullptr;    // [n]
   // sparse spectral support of every scene, concatenated (see bccb_plan_s)
   bool sparse = false;
@@ -75,7 +80,8 @@ void batch_free(bccb_batch_s* b) {
                     static_cast<void*>(c.d_xy), static_cast<void*>(c.d_rhs), static_cast<void*>(c.d_c),
                     static_cast<void*>(c.d_desc), static_cast<void*>(c.d_sup_ptr), static_cast<void*>(c.d_sup),
                     static_cast<void*>(c.d_src_ptr), static_cast<void*>(c.d_src), static_cast<void*>(c.d_sup_rhs),
-                    static_cast<void*>(c.d_sdesc)})
+                    static_cast<void*>(c.d_sdesc), static_cast<void*>(c.d_cnt), static_cast<void*>(c.d_sidx),
+                    static_cast<void*>(c.d_sval)})
       if (p) (void)hipFree(p);
     if (c.h_sdesc) (void)hipHostFree(c.h_sdesc);
   }
@@ -144,11 +150,14 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
       a.rhs = c.sparse ? nullptr : c.d_rhs;
       a.state = c.d_c;
       a.out_c = c.d_c;
+      a.cnt = c.d_cnt;
+      a.sidx = c.d_sidx;
+      a.sval = c.d_sval;
       a.kscale = c.d_kscale;
       a.kappa = 1.f;
       a.beta = beta;
       a.last = (t == iters);
-      BCCB_TRY(class_row(c, c.cfg_row, ROW_FISTA, a, s));
+      BCCB_TRY(class_row(c, c.cfg_row, c.sp_iter ? ROW_FISTA_SP : ROW_FISTA, a, s));
     }
   }
   return BCCB_OK;
@@ -230,6 +239,16 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
     }
     if (rc == BCCB_OK) rc = dalloc(&c.d_c, pts);
     if (rc == BCCB_OK) rc = dalloc(&c.d_desc, c.n);
+    if (c.L1 >= 8) {
+      const size_t rows = static_cast<size_t>(c.n) * c.L2;
+      if (rc == BCCB_OK) rc = dalloc(&c.d_cnt, rows);
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sidx, rows * (c.L1 / 8));
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sval, rows * (c.L1 / 8));
+      // every row starts out dense: no slot is read before the kernel has written it
+      if (rc == BCCB_OK && hipMemset(c.d_cnt, 0x7f, rows * sizeof(int)) != hipSuccess) rc = BCCB_E_DEVICE;
+      c.sp_iter = true;
+      while (!row_shape_ok(c.L1, c.cfg_row, true) && c.cfg_row.rpb > 1) c.cfg_row.rpb /= 2;
+    }
     if (rc != BCCB_OK) break;
     std::vector<float2> coef(c.n);
     for (int k = 0; k < c.n; ++k) {
@@ -331,6 +350,7 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
     off += c.n;
     BCCB_TRY(kern(launch_fill(c.d_c, static_cast<long>(c.n) * c.L, s)));
     BCCB_TRY(kern(launch_fill(c.d_xy, static_cast<long>(c.n) * c.L, s)));
+    if (c.sp_iter) BCCB_TRY(kern(launch_fill_int(c.d_cnt, static_cast<long>(c.n) * c.L2, c.L1 + 1, s)));
   }
   if (iters > 0) {
     if (!b->exec || b->graph_iters != iters) {
@@ -375,15 +395,19 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
         PassCfg r;
         r.E = E;
         r.rpb = k;
-        if (row_shape_ok(c.L1, r)) {
+        if (row_shape_ok(c.L1, r, c.sp_iter)) {
           RowArgs a;
           a.xy = c.d_xy;
           a.rhs = c.sparse ? nullptr : c.d_rhs;
           a.state = c.d_c;
+          a.cnt = c.d_cnt;
+          a.sidx = c.d_sidx;
+          a.sval = c.d_sval;
           a.kscale = c.d_kscale;
           a.kappa = 1.f;
           a.beta = 0.5f;
-          const float ms = time_launches(b->stream, reps, [&] { return class_row(c, r, ROW_FISTA, a, b->stream); });
+          const int mode = c.sp_iter ? ROW_FISTA_SP : ROW_FISTA;
+          const float ms = time_launches(b->stream, reps, [&] { return class_row(c, r, mode, a, b->stream); });
           if (ms < 0.f) return BCCB_E_DEVICE;
           if (ms < best_r) { best_r = ms; br = r; }
         }
@@ -400,6 +424,19 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
     }
     c.cfg_row = br;
     c.cfg_col = bc;
+  }
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->graph_iters = -1;
+  return BCCB_OK;
+}
+
+int bccb_batch_set_sparse_iterate(bccb_batch_t b, int on) {
+  if (!b || (on != 0 && on != 1)) return BCCB_E_INVALID;
+  for (BatchClass& c : b->cls) {
+    const bool want = on == 1 && c.d_cnt != nullptr;
+    while (want && !row_shape_ok(c.L1, c.cfg_row, true) && c.cfg_row.rpb > 1) c.cfg_row.rpb /= 2;
+    c.sp_iter = want;
   }
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;

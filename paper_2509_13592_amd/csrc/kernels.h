@@ -13,6 +13,8 @@ enum RowMode {
   ROW_ISTA = 2,   // u = IDFT_rows(xy); c = S_k(u + rhs); xy = DFT_rows(c)
   ROW_FISTA = 3,  // u = IDFT_rows(xy); c = S_k(u + rhs); z = c + beta (c - state); state = c; xy = DFT_rows(z)
   ROW_ADMM = 4,   // u = IDFT_rows(xy); c = rhs + u; z = S_k(c + v); v += c - z; xy = DFT_rows(z - v)
+  ROW_FISTA_SP = 5,  // ROW_FISTA with c_{t-1} / c_t kept per row as (index, value) slots while the row
+                     // has at most N/8 nonzeros (dense row in `state` otherwise; always dense at the last iteration)
 };
 
 struct RowArgs {
@@ -37,6 +39,11 @@ struct RowArgs {
   float2* out_prev = nullptr;    // FISTA: store c_{t-1} (the state before the update) (nullable)
   const int* scene_map = nullptr;// logical scene -> physical scene of the arenas (nullable = identity)
   int spread = 1;                // see PassCfg::spread
+  // ROW_FISTA_SP storage: per physical row, cnt = number of nonzeros (> N/8: the row is dense in
+  // `state`), slot j < cnt holds element sidx[row * (N/8) + j] with value sval[row * (N/8) + j]
+  int* cnt = nullptr;
+  unsigned short* sidx = nullptr;
+  float2* sval = nullptr;
 };
 
 // Column pass (transforms along l2, stride L1).
@@ -199,6 +206,7 @@ int launch_kkt(const float2* c, const float2* b, const float2* gc, float tau, lo
                double* partial, int* nblocks, hipStream_t s);
 int launch_absmax(const float2* b, long L, double* partial, int* nblocks, hipStream_t s);
 int launch_fill(float2* p, long n, hipStream_t s);   // zero fill (graph-safe, no memset node)
+int launch_fill_int(int* p, long n, int value, hipStream_t s);
 // out = (1 + beta) a - beta b over n scenes of L points selected by map (nullable = identity)
 int launch_momentum(float2* out, const float2* a, const float2* b, float beta, long L, int n, const int* map,
                     hipStream_t s);

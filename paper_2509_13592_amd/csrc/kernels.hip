@@ -164,6 +164,11 @@ __global__ void k_fill(float2* p, long n) {
     p[i] = make_float2(0.f, 0.f);
 }
 
+__global__ void k_fill_int(int* p, long n, int value) {
+  for (long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += static_cast<long>(gridDim.x) * blockDim.x)
+    p[i] = value;
+}
+
 __global__ void k_momentum(float2* __restrict__ out, const float2* __restrict__ a, const float2* __restrict__ b,
                            float beta, long L, const int* __restrict__ map) {
   const int s = map ? map[blockIdx.y] : static_cast<int>(blockIdx.y);
@@ -295,6 +300,14 @@ int launch_fill(float2* p, long n, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) return 0;
   hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_fill_int(int* p, long n, int value, hipStream_t s) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) return 0;
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks), dim3(256), 0, s, p, n, value);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

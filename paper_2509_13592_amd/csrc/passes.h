@@ -44,14 +44,23 @@ __device__ __forceinline__ bool spread_block(int spread, int& bid) {
   return true;
 }
 
+template <int N>
+struct SparseRow {
+  static constexpr int CAP = N / 8;   // slots per row
+};
+
 template <int N, int E, int MODE>
 __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   using F = Stockham<N, E>;
   constexpr int T = F::T;
-  constexpr bool kIter = (MODE == ROW_ISTA || MODE == ROW_FISTA || MODE == ROW_ADMM);
+  constexpr bool kSp = (MODE == ROW_FISTA_SP);
+  constexpr bool kIter = (MODE == ROW_ISTA || MODE == ROW_FISTA || MODE == ROW_ADMM || kSp);
   constexpr bool kState = (MODE == ROW_FISTA || MODE == ROW_ADMM);
+  constexpr int CAP = SparseRow<N>::CAP;
+  constexpr int SPT = (CAP + T - 1) / T;   // slots read per thread
   extern __shared__ float2 lds[];
   float2* stw = lds + rpb * N;
+  int* rowcnt = reinterpret_cast<int*>(stw + N);   // kSp: rpb * T ints
   int bid;
   if (!spread_block(a.spread, bid)) return;  // whole block exits together
 
@@ -106,6 +115,21 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
 #pragma unroll
     for (int e = 0; e < E; ++e) st[e] = a.state[base + F::in_index(t, e)];
   }
+  // sparse storage of c_{t-1}: the row's count and all of its slots are read up
+  // front (one round trip); a dense row is read after the count is known
+  int rcount = 0;
+  unsigned short sl_i[kSp ? SPT : 1];
+  float2 sl_v[kSp ? SPT : 1];
+  if constexpr (kSp) {
+    rcount = a.cnt[prow];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int j = t + T * q;
+      const int jj = j < CAP ? j : 0;
+      sl_i[q] = a.sidx[static_cast<size_t>(prow) * CAP + jj];
+      sl_v[q] = a.sval[static_cast<size_t>(prow) * CAP + jj];
+    }
+  }
   if (!active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -113,8 +137,31 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
       if constexpr (kIter) rhs[e] = zero;
       if constexpr (kState) st[e] = zero;
     }
+    rcount = 0;
   }
   for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+  float2 sp[kSp ? E : 1];   // c_{t-1} at the thread's elements (sparse storage)
+  if constexpr (kSp) {
+    // expand the slots into the row's LDS area, then read the thread's elements
+#pragma unroll
+    for (int e = 0; e < E; ++e) sm[F::in_index(t, e)] = zero;
+    __syncthreads();
+    if (rcount <= CAP) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int j = t + T * q;
+        if (j < rcount) sm[sl_i[q] < N ? sl_i[q] : N - 1] = sl_v[q];
+      }
+    }
+    __syncthreads();
+    if (rcount <= CAP) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sp[e] = sm[F::in_index(t, e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sp[e] = a.state[base + F::in_index(t, e)];
+    }
+  }
   __syncthreads();
 
   if constexpr (MODE == ROW_FWD) {
@@ -148,6 +195,10 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         const float2 c = shrink(make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y), kappa);
         if (a.last && active) a.out_c[idx] = c;
         v[e] = c;
+      } else if constexpr (kSp) {
+        // c_t stays in v[e] until the row's storage form is decided below
+        const float2 u = make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y);
+        v[e] = shrink(u, kappa);
       } else if constexpr (MODE == ROW_FISTA) {
         const float2 u = make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y);
         const float2 c = shrink(u, kappa);
@@ -173,6 +224,43 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         }
         v[e] = csub(z, vn);
       }
+    }
+    if constexpr (kSp) {
+      // store c_t: slots if the row has at most CAP nonzeros (not at the last
+      // iteration, whose output is read densely), the dense row otherwise
+      int mine = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
+      rowcnt[r * T + t] = mine;
+      __syncthreads();
+      int total = 0, before = 0;
+      for (int i = 0; i < T; ++i) {
+        const int ci = rowcnt[r * T + i];
+        total += ci;
+        before += (i < t) ? ci : 0;
+      }
+      const bool dense = a.last || total > CAP;
+      if (active) {
+        if (dense) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) a.state[base + F::in_index(t, e)] = v[e];
+        } else {
+          int o = before;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (v[e].x != 0.f || v[e].y != 0.f) {
+              a.sidx[static_cast<size_t>(prow) * CAP + o] = static_cast<unsigned short>(F::in_index(t, e));
+              a.sval[static_cast<size_t>(prow) * CAP + o] = v[e];
+              ++o;
+            }
+          }
+        }
+        if (t == 0) a.cnt[prow] = dense ? CAP + 1 + total : total;
+      }
+      // momentum z = c_t + beta (c_t - c_{t-1})
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        v[e] = make_float2(v[e].x + a.beta * (v[e].x - sp[e].x), v[e].y + a.beta * (v[e].y - sp[e].y));
     }
     if (!a.last) {
       F::forward(v, t, stw, sm, 1);
@@ -309,11 +397,14 @@ int row_launch_e(int mode, const RowArgs& a, int rpb, hipStream_t s) {
   if (rpb < 1 || rpb * T > 256) return -1;
   const int blocks = (a.nrows + rpb - 1) / rpb;
   if (blocks <= 0) return 0;
-  const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2);
+  const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2) +
+                     (mode == ROW_FISTA_SP ? static_cast<size_t>(rpb) * T * sizeof(int) : 0);
   if (shm > 65536) return -1;
+  if (mode == ROW_FISTA_SP && (!a.cnt || !a.sidx || !a.sval || !a.state)) return -1;
   const int spread = a.spread > 1 ? a.spread : 1;
   const dim3 grid(blocks * spread), block(rpb * T);
   switch (mode) {
+    case ROW_FISTA_SP: hipLaunchKernelGGL((k_row<N, E, ROW_FISTA_SP>), grid, block, shm, s, a, rpb); break;
     case ROW_FWD: hipLaunchKernelGGL((k_row<N, E, ROW_FWD>), grid, block, shm, s, a, rpb); break;
     case ROW_INV: hipLaunchKernelGGL((k_row<N, E, ROW_INV>), grid, block, shm, s, a, rpb); break;
     case ROW_ISTA: hipLaunchKernelGGL((k_row<N, E, ROW_ISTA>), grid, block, shm, s, a, rpb); break;

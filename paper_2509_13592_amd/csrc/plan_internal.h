@@ -49,6 +49,13 @@ struct bccb_plan_s {
   bccb::SupRhsDesc* h_sup_desc = nullptr;  // pinned
   int use_support = 1;
 
+  // FISTA iterate kept per row as (index, value) slots while the row is sparse
+  // (ROW_FISTA_SP): count [L2], slots [L2][L1/8]
+  int sparse_iterate = 0;
+  int* d_cnt = nullptr;
+  unsigned short* d_sidx = nullptr;
+  float2* d_sval = nullptr;
+
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
   int use_graph = 1;
@@ -79,7 +86,7 @@ int adjoint_into(bccb_plan_s* p, const float2* y, float scale, float2* dst);
 bool sparse_on(const bccb_plan_s* p);
 int begin_call(bccb_plan_s* p);
 int end_call(bccb_plan_s* p);
-bool row_shape_ok(int L1, const PassCfg& c);
+bool row_shape_ok(int L1, const PassCfg& c, bool sparse_iterate = false);
 bool col_shape_ok(int L1, int L2, const PassCfg& c);
 
 // Time `reps` launches of `launch()` on stream s with hipEvents; ms per launch, or < 0 on error.

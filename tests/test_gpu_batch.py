@@ -73,6 +73,33 @@ def test_batch_invariant_to_scene_order_and_autotune():
     b2.close()
 
 
+def test_batch_sparse_iterate_matches_dense_iterate():
+    """Per-row slot storage of the batched FISTA iterates (the default) and dense iterates
+    give the same bits, for iteration counts on both sides of the rows turning sparse."""
+    scenes = [S.batched_scene(300 + i) for i in range(10)]
+    scenes.append(S.custom_scene(20, 6, 40, 16, 8, K=2, snr_db=20, seed=(16, 0, 0)))
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    for iters in (1, 3, 40, 250):
+        res = {}
+        for on in (True, False):
+            batch.set_sparse_iterate(on)
+            res[on] = [o.clone() for o in batch.fista(ys, taus, iters)]
+        same = all(torch.equal(a, b) for a, b in zip(res[True], res[False]))
+        print(f"case batch sparse iterate iters={iters}: bitwise={same}", flush=True)
+        assert same
+    # a tuned launch shape changes the transforms' radix order, hence FP32 rounding: after
+    # 250 iterations the trajectories agree to about 1e-4 (the launch-shape test's 1e-3 bound)
+    batch.set_sparse_iterate(True)
+    batch.autotune(reps=3)
+    o = batch.fista(ys, taus, 250)
+    for a, b in zip(o, res[False]):
+        x, r = _np(a), _np(b)
+        assert np.linalg.norm(x - r) <= 1e-3 * max(np.linalg.norm(r), 1e-30)
+    assert B.lib.bccb_batch_set_sparse_iterate(batch._h, 2) == B.BCCB_E_INVALID
+    batch.close()
+
+
 def test_batch_edge_cases():
     scenes = [S.batched_scene(200 + i) for i in range(3)]
     plans, ys, taus = _setup(scenes)

@@ -237,13 +237,13 @@ def test_full_ura_one_step_exact():
 
 CONFIGS_256 = [
     dict(row_elems=4, row_rows_per_block=1, col_elems=4, col_cols_per_block=1, use_graph=1, spectral_support=1,
-         row_spread=8, col_spread=8),
+         row_spread=8, col_spread=8, sparse_iterate=1),
     dict(row_elems=8, row_rows_per_block=2, col_elems=8, col_cols_per_block=4, use_graph=0, spectral_support=0,
-         row_spread=1, col_spread=2),
+         row_spread=1, col_spread=2, sparse_iterate=0),
     dict(row_elems=16, row_rows_per_block=16, col_elems=16, col_cols_per_block=16, use_graph=1, spectral_support=0,
-         row_spread=4, col_spread=1),
+         row_spread=4, col_spread=1, sparse_iterate=1),
     dict(row_elems=32, row_rows_per_block=4, col_elems=32, col_cols_per_block=8, use_graph=0, spectral_support=1,
-         row_spread=1, col_spread=1),
+         row_spread=1, col_spread=1, sparse_iterate=0),
 ]
 
 
@@ -300,6 +300,44 @@ def test_small_and_rectangular_configs(L1, L2):
         print(f"case gram L1={L1} L2={L2} E={E}", flush=True)
         gx = _np(plan.gram_apply(B.to_device(x.reshape(L2, L1))))
         assert np.linalg.norm(gx - ref) <= MATVEC_TOL * np.linalg.norm(ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("geom", ["tiny", "ragged", "aliasing", "paper"])
+def test_sparse_iterate_matches_dense_iterate(geom):
+    """FISTA with c^(t) kept in per-row (index, value) slots while rows are sparse follows
+    the dense-iterate trajectory: same bits, from zero and from a warm start, at iteration
+    counts that end while rows are still dense, while they change form, and after they
+    have all turned sparse; ISTA and ADMM are unaffected by the option."""
+    sc = {"tiny": S.tiny_scene(6),
+          "ragged": S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(14, 1, 0)),
+          "aliasing": S.custom_scene(20, 6, 40, 32, 8, K=2, snr_db=20, seed=(15, 1, 0)),
+          "paper": S.paper_scale_scene(5)}[geom]
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    y = B.to_device(sc.y)
+    rng = np.random.default_rng(3)
+    warm = (rng.standard_normal((sc.L2, sc.L1)) + 1j * rng.standard_normal((sc.L2, sc.L1))).astype(np.complex64)
+    warm[np.abs(warm) < 1.5] = 0
+    warm_d = B.to_device(warm)
+    for iters in (0, 1, 2, 7, 60, 300):
+        for c0 in (None, warm_d):
+            outs = {}
+            for spi in (1, 0):
+                plan.set_config(sparse_iterate=spi)
+                outs[spi] = _np(plan.fista(y, P.tau, iters, c0=c0))
+            print(f"case {geom} iters={iters} warm={c0 is not None}: "
+                  f"bitwise={np.array_equal(outs[0], outs[1])}", flush=True)
+            assert np.array_equal(outs[0], outs[1])
+    others = {}
+    for spi in (1, 0):
+        plan.set_config(sparse_iterate=spi)
+        others[spi] = (_np(plan.ista(y, P.tau, 60)), _np(plan.admm(y, P.tau, 4.0, 60)))
+    assert all(np.array_equal(a, b) for a, b in zip(others[0], others[1]))
+    ref = P.fista(300)
+    plan.set_config(sparse_iterate=1)
+    g = _np(plan.fista(y, P.tau, 300))
+    assert abs(P.objective(g) - P.objective(ref)) / P.objective(ref) <= OBJ_TOL
     plan.close()
 
 
