@@ -79,7 +79,10 @@ def _batch_rate(B, scenes, iters, reps, tune=True):
         batch.fista(ys, taus, iters, outs=outs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    classes = batch.classes()
+    classes = [{"L1": L1, "L2": L2, "scenes": n,
+                "launch": dict(zip(("row_E", "rows_per_block", "col_E", "cols_per_block", "pruned",
+                                    "columns_transformed"), cfg))}
+               for (L1, L2, n), cfg in zip(batch.classes(), batch.class_configs())]
     batch.close()
     for p in plans:
         p.close()
@@ -238,7 +241,7 @@ def main():
         print(json.dumps({"batched": batched_runs(args)}))
         return
     if args.only == "batch256":
-        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], 20, reps=2, tune=False)
+        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], 20, reps=2)
         print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": 20, "classes": classes}))
         return
     sc = S.paper_scale_scene(0)

@@ -184,6 +184,14 @@ int lasso_solve_batch_fista(bccb_batch_t batch, const bccb_c32* const* y, const 
 int bccb_batch_autotune(bccb_batch_t batch, int reps);
 
 /*
+ * bccb_batch_class_config -- launch shape class `cls` (< nclasses of
+ *   bccb_batch_info) runs with: cfg[0..5] = row-pass E, rows per block,
+ *   column-pass E, columns per block, 1 if the class takes the pruned passes,
+ *   and the columns its column pass transforms per scene.  cfg: host int[6].
+ */
+int bccb_batch_class_config(bccb_batch_t batch, int cls, int* cfg);
+
+/*
  * bccb_batch_set_sparse_iterate -- 1 (the default for classes with L1 >= 8):
  *   keep every scene's FISTA iterate per row in (index, value) slots while the
  *   row is sparse, as bccb_config.sparse_iterate does for one plan; 0: dense
@@ -191,6 +199,15 @@ int bccb_batch_autotune(bccb_batch_t batch, int reps);
  *   BCCB_E_INVALID for a null batch or a value other than 0 or 1.
  */
 int bccb_batch_set_sparse_iterate(bccb_batch_t batch, int on);
+
+/*
+ * bccb_batch_set_support_columns -- 1 (the default): size classes whose every
+ *   scene has a kept-column set (see bccb_config.support_columns) run the
+ *   pruned passes; 0: the full passes (with sparse_iterate as set).  Results
+ *   agree to FP32 rounding.  BCCB_E_INVALID for a null batch or a value other
+ *   than 0 or 1.
+ */
+int bccb_batch_set_support_columns(bccb_batch_t batch, int on);
 
 /*
  * Learned unrolled FISTA with a KKT-gated plain-FISTA fallback.
@@ -307,6 +324,19 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   otherwise, so the row pass moves a few bytes per row instead of 16 B per
  *   grid point for c^(t-1) and c^(t); the values are stored exactly, so the
  *   iterates are those of the dense form.  Needs L1 >= 8.  0 = dense c^(t).
+ *   support_columns: 1 = with spectral_support in effect, ISTA and FISTA split
+ *   (I - mu G) z + mu b into z plus IDFT2 of a spectrum that lives on the
+ *   support bins (Omega and DFT2(b) vanish elsewhere, eq. (21)): the column pass
+ *   transforms only the spectral columns holding support bins, the row pass
+ *   exchanges only those columns with it and rebuilds z in the spatial domain
+ *   from c^(t-1), c^(t-2) (kept per row as above).  Taken when those columns
+ *   are at most L1/2 (after padding to a multiple of 4) and L1 >= 8; otherwise
+ *   the full passes run.  0 = always the full passes.
+ *   prow_elems, prow_rows_per_block: the pruned row pass's shape (as the row
+ *   pass; rows * (2 L1 + ...) must fit the 64 KB of LDS a workgroup can hold);
+ *   pcol_elems, pcol_cols_per_block: the pruned column pass's shape (columns
+ *   per block must divide the padded kept-column count).  Ignored (and
+ *   returned as set internally) when the plan has no such column set.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -319,10 +349,24 @@ typedef struct {
   int row_spread;
   int col_spread;
   int sparse_iterate;
+  int support_columns;
+  int prow_elems;
+  int prow_rows_per_block;
+  int pcol_elems;
+  int pcol_cols_per_block;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */
 int bccb_plan_get_config(bccb_plan_t plan, bccb_config* cfg);
+
+/*
+ * bccb_plan_support_columns -- *ncols (nullable): number of spectral columns k1
+ *   holding support bins of Omega (Sec. III-A, eq. (21)); *pruned (nullable):
+ *   1 if ISTA / FISTA solves on this plan take the pruned passes under the
+ *   current configuration (support_columns and spectral_support set, the
+ *   columns few enough), else 0.
+ */
+int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned);
 
 /* Set a configuration; BCCB_E_INVALID if a pass shape cannot be launched. */
 int bccb_plan_set_config(bccb_plan_t plan, const bccb_config* cfg);
@@ -331,7 +375,10 @@ int bccb_plan_set_config(bccb_plan_t plan, const bccb_config* cfg);
  * bccb_plan_autotune -- time every launchable (E, rows per block) of the FISTA
  *   row pass and every (E, columns per block) of the column pass on the plan's
  *   workspace (`reps` launches each, hipEvents), keep the fastest, and return
- *   it in *chosen (nullable).  use_graph is left as it was.
+ *   it in *chosen (nullable).  Where the plan has a kept-column set (see
+ *   support_columns) the pruned passes are tuned too, and support_columns is
+ *   set to whichever pair is faster per iteration (when spectral_support is on).
+ *   use_graph is left as it was.
  */
 int bccb_plan_autotune(bccb_plan_t plan, int reps, bccb_config* chosen);
 

@@ -32,7 +32,9 @@ class Config(ctypes.Structure):
                 ("col_elems", ctypes.c_int), ("col_cols_per_block", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("spectral_support", ctypes.c_int),
                 ("row_spread", ctypes.c_int), ("col_spread", ctypes.c_int),
-                ("sparse_iterate", ctypes.c_int)]
+                ("sparse_iterate", ctypes.c_int), ("support_columns", ctypes.c_int),
+                ("prow_elems", ctypes.c_int), ("prow_rows_per_block", ctypes.c_int),
+                ("pcol_elems", ctypes.c_int), ("pcol_cols_per_block", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -242,6 +244,12 @@ class Plan:
         check(lib.bccb_plan_set_config(self._h, ctypes.byref(c)), "bccb_plan_set_config")
         return self.get_config()
 
+    def support_columns(self) -> tuple[int, bool]:
+        """(spectral columns holding support bins, whether ISTA/FISTA take the pruned passes)."""
+        n, pr = ctypes.c_int(), ctypes.c_int()
+        check(lib.bccb_plan_support_columns(self._h, ctypes.byref(n), ctypes.byref(pr)), "bccb_plan_support_columns")
+        return n.value, bool(pr.value)
+
     def autotune(self, reps: int = 50) -> dict:
         c = Config()
         check(lib.bccb_plan_autotune(self._h, int(reps), ctypes.byref(c)), "bccb_plan_autotune")
@@ -295,6 +303,18 @@ class Batch:
 
     def autotune(self, reps: int = 10):
         check(lib.bccb_batch_autotune(self._h, int(reps)), "bccb_batch_autotune")
+
+    def class_configs(self):
+        """Per size class: (row E, rows/block, column E, columns/block, pruned, columns transformed)."""
+        out = []
+        for i in range(len(self.classes())):
+            cfg = (ctypes.c_int * 6)()
+            check(lib.bccb_batch_class_config(self._h, i, cfg), "bccb_batch_class_config")
+            out.append(tuple(cfg))
+        return out
+
+    def set_support_columns(self, on: bool):
+        check(lib.bccb_batch_set_support_columns(self._h, 1 if on else 0), "bccb_batch_set_support_columns")
 
     def set_sparse_iterate(self, on: bool):
         check(lib.bccb_batch_set_sparse_iterate(self._h, 1 if on else 0), "bccb_batch_set_sparse_iterate")

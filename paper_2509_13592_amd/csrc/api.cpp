@@ -61,6 +61,15 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_cnt);
   dfree(p->d_sidx);
   dfree(p->d_sval);
+  dfree(p->d_scol);
+  dfree(p->d_colslot);
+  dfree(p->d_xyc);
+  for (int i = 0; i < 3; ++i) {
+    dfree(p->d_pcnt[i]);
+    dfree(p->d_psidx[i]);
+    dfree(p->d_psval[i]);
+    dfree(p->d_pdense[i]);
+  }
   dfree(p->d_tmp);
   dfree(p->d_coef);
   dfree(p->d_red);
@@ -121,14 +130,24 @@ bool row_shape_ok(int L1, const PassCfg& c, bool sparse_iterate) {
   if (!elems_ok(L1, c.E) || c.rpb < 1) return false;
   const int T = L1 / c.E;
   const long counts = sparse_iterate ? static_cast<long>(c.rpb) * T * 4 : 0;  // per-thread nonzero counts
-  return c.rpb * T <= 256 && static_cast<long>(c.rpb + 1) * L1 * 8 + counts <= 65536;
+  return c.rpb * T <= 256 && (static_cast<long>(fft_areas(L1, c.E)) * c.rpb * fft_area(L1) + L1) * 8 + counts <= 65536;
 }
 
 bool col_shape_ok(int L1, int L2, const PassCfg& c) {
   if (!elems_ok(L2, c.E) || c.W < 1 || L1 % c.W != 0) return false;
   const int T = L2 / c.E;
-  return c.W * T <= 256 && static_cast<long>(c.W + 1) * L2 * 8 <= 65536;
+  return c.W * T <= 256 && (static_cast<long>(fft_areas(L2, c.E)) * c.W * fft_area(L2) + L2) * 8 <= 65536;
 }
+
+bool rowp_shape_ok(int L1, const PassCfg& c, int ncs) {
+  if (!elems_ok(L1, c.E) || c.rpb < 1 || ncs < 1 || ncs > L1 / 2) return false;
+  const int T = L1 / c.E;
+  return c.rpb * T <= 256 && rowp_lds_floats(L1, c.E, c.rpb, ncs) * 8 <= 65536;
+}
+
+bool colp_shape_ok(int ncs, int L2, const PassCfg& c) { return ncs >= 1 && col_shape_ok(ncs, L2, c); }
+
+bool pruned_on(const bccb_plan_s* p) { return p->prune_ok && p->use_prune && p->has_support && p->use_support; }
 
 // Latency-oriented default: E = 4, about one wave per workgroup.
 void default_config(bccb_plan_s* p) {
@@ -140,6 +159,10 @@ void default_config(bccb_plan_s* p) {
   int W = Tc >= 64 ? 1 : 64 / Tc;
   if (W > p->L1) W = p->L1;
   p->cfg_col.W = W;
+  p->cfg_rowp = p->cfg_row;
+  while (!rowp_shape_ok(p->L1, p->cfg_rowp, p->ncs) && p->cfg_rowp.rpb > 1) p->cfg_rowp.rpb /= 2;
+  p->cfg_colp.E = 4;
+  p->cfg_colp.W = 1;   // one kept column per workgroup: the most workgroups for a single scene
 }
 
 void drop_graph(bccb_plan_s* p) {
@@ -311,6 +334,13 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
     p->h_sup_ptr[L1] = static_cast<int>(p->h_sup.size());
     p->nsup = static_cast<int>(p->h_sup.size());
     p->has_support = p->nsup <= p->L / 4;
+    // spectral columns holding support bins (the pruned iteration transforms only these)
+    for (int k1 = 0; k1 < L1; ++k1)
+      if (p->h_sup_ptr[k1 + 1] > p->h_sup_ptr[k1]) p->h_scol.push_back(k1);
+    p->nscol = static_cast<int>(p->h_scol.size());
+    p->ncs = (p->nscol + 3) / 4 * 4;
+    p->prune_ok = p->has_support && L1 >= 8 && p->nscol >= 1 && p->ncs <= L1 / 2;
+    p->h_scol.resize(p->ncs, -1);
   }
 
   std::vector<float2> tw1(L1), tw2(L2);
@@ -338,6 +368,28 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   // every row starts out dense: no slot is read before the kernel has written it
   if (rc == BCCB_OK && hipMemset(p->d_cnt, 0x7f, L2 * sizeof(int)) != hipSuccess) rc = BCCB_E_DEVICE;
   if (rc == BCCB_OK) rc = dmalloc(&p->d_tmp, p->L);
+  if (rc == BCCB_OK && p->prune_ok) {
+    const size_t cap = static_cast<size_t>(L2) * (L1 / 8);
+    std::vector<int> colslot(L1, -1);
+    for (int j = 0; j < p->nscol; ++j) colslot[p->h_scol[j]] = j;
+    rc = dmalloc(&p->d_scol, p->ncs);
+    if (rc == BCCB_OK) rc = dmalloc(&p->d_colslot, L1);
+    if (rc == BCCB_OK) rc = dmalloc(&p->d_xyc, static_cast<size_t>(L2) * p->ncs);
+    for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
+      rc = dmalloc(&p->d_pcnt[i], L2);
+      if (rc == BCCB_OK) rc = dmalloc(&p->d_psidx[i], cap);
+      if (rc == BCCB_OK) rc = dmalloc(&p->d_psval[i], cap);
+      if (rc == BCCB_OK) rc = dmalloc(&p->d_pdense[i], p->L);
+      // rows start out dense over a zeroed grid: nothing unwritten is ever read
+      if (rc == BCCB_OK && (hipMemset(p->d_pcnt[i], 0x7f, L2 * sizeof(int)) != hipSuccess ||
+                            hipMemset(p->d_pdense[i], 0, p->L * sizeof(float2)) != hipSuccess))
+        rc = BCCB_E_DEVICE;
+    }
+    if (rc == BCCB_OK && (hipMemcpy(p->d_scol, p->h_scol.data(), p->ncs * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+                          hipMemcpy(p->d_colslot, colslot.data(), L1 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+                          hipMemset(p->d_xyc, 0, static_cast<size_t>(L2) * p->ncs * sizeof(float2)) != hipSuccess))
+      rc = BCCB_E_DEVICE;
+  }
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_red, static_cast<size_t>(kReduceBlocks) * 8);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_flag, 1);
@@ -400,6 +452,13 @@ int bccb_plan_info(bccb_plan_t plan, int* M, double* mu, float* omega_host) {
   return BCCB_OK;
 }
 
+int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned) {
+  if (!plan) return BCCB_E_INVALID;
+  if (ncols) *ncols = plan->nscol;
+  if (pruned) *pruned = pruned_on(plan) ? 1 : 0;
+  return BCCB_OK;
+}
+
 int bccb_adjoint(bccb_plan_t p, const bccb_c32* y, bccb_c32* b) {
   if (!p || !y || !b) return BCCB_E_INVALID;
   BCCB_TRY(begin_call(p));
@@ -442,6 +501,74 @@ static int check_solve(bccb_plan_t p, const bccb_c32* y, float tau, int iters, c
   return BCCB_OK;
 }
 
+// Pruned ISTA / FISTA (sparse support, kept columns only).  c_t lives in SlotBuf
+// t mod 3; buffer 0's dense rows are the output grid, which holds c_0 at the start.
+static SlotBuf pruned_buf(bccb_plan_s* p, int i, float2* out) {
+  SlotBuf b;
+  b.cnt = p->d_pcnt[i];
+  b.sidx = p->d_psidx[i];
+  b.sval = p->d_psval[i];
+  b.dense = i == 0 ? out : p->d_pdense[i];
+  return b;
+}
+
+static int solve_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const float2* init, float2* out) {
+  hipStream_t st = p->stream;
+  const bool fista = (mode == ROW_FISTA);
+  if (init && init != out) BCCB_TRY(kern(launch_copy(out, init, p->L, st)));
+  else if (!init) BCCB_TRY(kern(launch_fill(out, p->L, st)));
+  // c_0 dense in buffer 0, c_{-1} = 0 in buffer 2
+  BCCB_TRY(kern(launch_fill_int(p->d_pcnt[0], p->L2, p->L1 + 1, st)));
+  BCCB_TRY(kern(launch_fill_int(p->d_pcnt[2], p->L2, 0, st)));
+  RowArgs f;
+  f.xy = p->d_xyc;
+  f.src = out;
+  f.flag = p->d_flag;
+  f.colslot = p->d_colslot;
+  f.ncs = p->ncs;
+  BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED_FWD, f, st));   // kept columns of DFT_rows(z_1 = c_0)
+  if (iters == 0) return end_call(p);
+  const unsigned long long key[8] = {static_cast<unsigned long long>(mode), static_cast<unsigned long long>(iters),
+                                     reinterpret_cast<unsigned long long>(out), fbits(kappa), 1, 0, 1, 2};
+  BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
+    double alpha = 1.0;
+    float beta_prev = 0.f;
+    for (int t = 1; t <= iters; ++t) {
+      ColArgs c;
+      c.xy = p->d_xyc;
+      c.sup_ptr = p->d_sup_ptr;
+      c.sup = p->d_sup;
+      c.sup_rhs = p->d_sup_rhs;
+      c.coef = p->d_coef;
+      c.tw = p->d_tw2;
+      c.L1 = p->L1;
+      c.ncols = p->ncs;
+      c.ldx = p->ncs;
+      c.scol = p->d_scol;
+      BCCB_TRY(kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_AFFINE, c, s)));
+      const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+      const float beta = fista ? static_cast<float>((alpha - 1.0) / alpha_next) : 0.f;
+      alpha = alpha_next;
+      RowArgs a;
+      a.xy = p->d_xyc;
+      a.colslot = p->d_colslot;
+      a.ncs = p->ncs;
+      a.b1 = pruned_buf(p, (t - 1) % 3, out);
+      if (fista) a.b2 = pruned_buf(p, (t + 1) % 3, out);   // (t - 2) mod 3
+      a.b0 = pruned_buf(p, t % 3, out);
+      a.out_c = out;
+      a.kappa = kappa;
+      a.beta = beta;
+      a.beta_prev = beta_prev;
+      a.last = (t == iters);
+      beta_prev = beta;
+      BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED, a, s));
+    }
+    return BCCB_OK;
+  }));
+  return end_call(p);
+}
+
 // ISTA (mode ROW_ISTA) and FISTA (ROW_FISTA) share one driver.
 static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau, int iters, const bccb_c32* c0,
                            bccb_c32* c_out) {
@@ -453,6 +580,7 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
   // mu * D_s^H y: on the support bins of the spectrum (sparse) or as a grid
   if (sparse) BCCB_TRY(fill_sup_rhs(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu)));
   else BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
+  if (pruned_on(p)) return solve_pruned(p, mode, iters, static_cast<float>(p->mu * tau), init, out);
   // z^(1) = c^(0): its row DFT starts the first column pass; FISTA keeps c^(t-1) in c_out
   RowArgs f;
   f.xy = p->d_xy;
@@ -616,6 +744,11 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->row_spread = p->cfg_row.spread;
   cfg->col_spread = p->cfg_col.spread;
   cfg->sparse_iterate = p->sparse_iterate;
+  cfg->support_columns = p->use_prune;
+  cfg->prow_elems = p->cfg_rowp.E;
+  cfg->prow_rows_per_block = p->cfg_rowp.rpb;
+  cfg->pcol_elems = p->cfg_colp.E;
+  cfg->pcol_cols_per_block = p->cfg_colp.W;
   return BCCB_OK;
 }
 
@@ -633,6 +766,19 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   if (!row_shape_ok(p->L1, r, spi) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread) ||
       (spi && p->L1 < 8))
     return BCCB_E_INVALID;
+  PassCfg rp = p->cfg_rowp, cp = p->cfg_colp;
+  if (p->prune_ok) {
+    rp.E = cfg->prow_elems;
+    rp.rpb = cfg->prow_rows_per_block;
+    rp.spread = r.spread;
+    cp.E = cfg->pcol_elems;
+    cp.W = cfg->pcol_cols_per_block;
+    cp.spread = c.spread;
+    if (!rowp_shape_ok(p->L1, rp, p->ncs) || !colp_shape_ok(p->ncs, p->L2, cp)) return BCCB_E_INVALID;
+  }
+  p->cfg_rowp = rp;
+  p->cfg_colp = cp;
+  p->use_prune = cfg->support_columns ? 1 : 0;
   p->cfg_row = r;
   p->cfg_col = c;
   p->use_graph = cfg->use_graph ? 1 : 0;
@@ -642,11 +788,42 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   return BCCB_OK;
 }
 
+// Arguments of the pruned passes over the plan's own buffers (autotuning, profiling):
+// c_{t-1}, c_{t-2} from buffers 1 and 2, c_t into buffer 0's private grid.
+static RowArgs pruned_work_args(bccb_plan_s* p) {
+  RowArgs a;
+  a.xy = p->d_xyc;
+  a.colslot = p->d_colslot;
+  a.ncs = p->ncs;
+  a.b1 = pruned_buf(p, 1, nullptr);
+  a.b2 = pruned_buf(p, 2, nullptr);
+  a.b0 = pruned_buf(p, 0, nullptr);
+  a.b0.dense = p->d_pdense[0];
+  a.out_c = p->d_tmp;
+  a.kappa = 1.f;
+  a.beta = 0.5f;
+  a.beta_prev = 0.5f;
+  return a;
+}
+
+static ColArgs pruned_col_args(bccb_plan_s* p) {
+  ColArgs c;
+  c.xy = p->d_xyc;
+  c.sup_ptr = p->d_sup_ptr;
+  c.sup = p->d_sup;
+  c.sup_rhs = p->d_sup_rhs;
+  c.coef = p->d_coef;
+  c.tw = p->d_tw2;
+  c.L1 = p->L1;
+  c.ncols = p->ncs;
+  c.ldx = p->ncs;
+  c.scol = p->d_scol;
+  return c;
+}
+
 int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   if (!p || reps < 1) return BCCB_E_INVALID;
-  hipEvent_t e0, e1;
-  BCCB_HIP(hipEventCreate(&e0));
-  BCCB_HIP(hipEventCreate(&e1));
+  hipStream_t st = p->stream;
   RowArgs a;
   a.xy = p->d_xy;
   a.rhs = sparse_on(p) ? nullptr : p->d_rhs;
@@ -658,51 +835,50 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   a.beta = 0.5f;
   const bool spi = p->sparse_iterate != 0;
   const int rmode = spi ? ROW_FISTA_SP : ROW_FISTA;
-  float best_r = 1e30f, best_c = 1e30f;
-  PassCfg br = p->cfg_row, bc = p->cfg_col;
-  int rc = BCCB_OK;
+  const int cmode = sparse_on(p) ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
+  const bool pr = p->prune_ok;
+  const RowArgs ap = pr ? pruned_work_args(p) : RowArgs();
+  const ColArgs cp = pr ? pruned_col_args(p) : ColArgs();
+  float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};   // row, col, pruned row, pruned col
+  PassCfg br = p->cfg_row, bc = p->cfg_col, brp = p->cfg_rowp, bcp = p->cfg_colp;
+  auto consider = [&](float ms, int slot, PassCfg& keep, const PassCfg& cand) -> int {
+    if (ms < 0.f) return BCCB_E_DEVICE;
+    if (ms < best[slot]) {
+      best[slot] = ms;
+      keep = cand;
+    }
+    return BCCB_OK;
+  };
   const int Es[4] = {4, 8, 16, 32};
-  for (int cand = 0; cand < 8 && rc == BCCB_OK; ++cand) {
-    const int ei = cand % 4;
+  for (int cand = 0; cand < 8; ++cand) {
     const int spread = cand < 4 ? 1 : 8;
-    for (int k = 1; k <= 256 && rc == BCCB_OK; k *= 2) {
+    for (int k = 1; k <= 256; k *= 2) {
+      PassCfg r;
+      r.E = Es[cand % 4];
+      r.rpb = k;
+      r.spread = spread;
+      if (row_shape_ok(p->L1, r, spi))
+        BCCB_TRY(consider(time_launches(st, reps, [&] { return row_pass_on(p, r, rmode, a, st); }), 0, br, r));
+      if (pr && rowp_shape_ok(p->L1, r, p->ncs))
+        BCCB_TRY(consider(time_launches(st, reps, [&] { return row_pass_on(p, r, ROW_PRUNED, ap, st); }), 2, brp, r));
       PassCfg c;
-      c.E = Es[ei];
-      c.rpb = k;
+      c.E = Es[cand % 4];
+      c.W = k;
       c.spread = spread;
-      if (row_shape_ok(p->L1, c, spi)) {
-        rc = row_pass_on(p, c, rmode, a, p->stream);  // warm
-        if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
-        for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass_on(p, c, rmode, a, p->stream);
-        float ms = 0.f;
-        if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = BCCB_E_DEVICE;
-        if (rc == BCCB_OK && ms < best_r) { best_r = ms; br = c; }
-      }
-      PassCfg d;
-      d.E = Es[ei];
-      d.W = k;
-      d.spread = spread;
-      const int cmode = sparse_on(p) ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
-      if (rc == BCCB_OK && col_shape_ok(p->L1, p->L2, d)) {
-        rc = col_pass_on(p, d, cmode, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
-        if (rc == BCCB_OK && hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
-        for (int i = 0; i < reps && rc == BCCB_OK; ++i)
-          rc = col_pass_on(p, d, cmode, p->d_xy, p->d_coef, 0.f, 1.f, p->stream);
-        float ms = 0.f;
-        if (rc == BCCB_OK && (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = BCCB_E_DEVICE;
-        if (rc == BCCB_OK && ms < best_c) { best_c = ms; bc = d; }
-      }
+      if (col_shape_ok(p->L1, p->L2, c))
+        BCCB_TRY(consider(time_launches(st, reps, [&] { return col_pass_on(p, c, cmode, p->d_xy, p->d_coef, 0.f, 1.f, st); }),
+                          1, bc, c));
+      if (pr && colp_shape_ok(p->ncs, p->L2, c))
+        BCCB_TRY(consider(time_launches(st, reps, [&] { return kern(launch_col(p->L2, c, COL_PRUNED_AFFINE, cp, st)); }),
+                          3, bcp, c));
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc != BCCB_OK) return rc;
   p->cfg_row = br;
   p->cfg_col = bc;
+  p->cfg_rowp = brp;
+  p->cfg_colp = bcp;
+  // ISTA / FISTA take whichever pair of passes is faster per iteration
+  if (pr && p->use_support) p->use_prune = (best[2] + best[3] < best[0] + best[1]) ? 1 : 0;
   drop_graph(p);
   if (chosen) return bccb_plan_get_config(p, chosen);
   return BCCB_OK;
@@ -733,10 +909,21 @@ int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, dou
                                    : (sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE);
   if (sparse) a.rhs = nullptr;
   const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
+  // ISTA / FISTA on a plan whose solves take the pruned passes: time those
+  const bool pr = solver != 2 && pruned_on(p);
+  RowArgs ap = pr ? pruned_work_args(p) : RowArgs();
+  if (pr && solver == 0) {
+    ap.b2 = SlotBuf();
+    ap.beta = ap.beta_prev = 0.f;
+  }
+  const ColArgs cp = pr ? pruned_col_args(p) : ColArgs();
   if (hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
-  for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = col_pass(p, col_mode, p->d_xy, p->d_coef, 1.f, scale);
+  for (int i = 0; i < reps && rc == BCCB_OK; ++i)
+    rc = pr ? kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_AFFINE, cp, p->stream))
+            : col_pass(p, col_mode, p->d_xy, p->d_coef, 1.f, scale);
   if (rc == BCCB_OK && hipEventRecord(e1, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
-  for (int i = 0; i < reps && rc == BCCB_OK; ++i) rc = row_pass(p, row_mode, a);
+  for (int i = 0; i < reps && rc == BCCB_OK; ++i)
+    rc = pr ? row_pass_on(p, p->cfg_rowp, ROW_PRUNED, ap, p->stream) : row_pass(p, row_mode, a);
   if (rc == BCCB_OK && hipEventRecord(e2, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
   if (rc == BCCB_OK && hipEventSynchronize(e2) != hipSuccess) rc = BCCB_E_DEVICE;
   float m01 = 0.f, m12 = 0.f;

@@ -34,6 +34,18 @@ struct BatchClass {
   float2* d_xy = nullptr;         // [n][L]
   float2* d_rhs = nullptr;        // [n][L] mu_s * b_s
   float2* d_c = nullptr;          // [n][L] FISTA c^(t-1) -> c^(t)
+  // pruned iteration (every scene has a kept-column set): kept row spectra
+  // [n][L2][ncs], per-scene maps, c_t rotating over three SlotBufs [n][L2] / [n][L]
+  bool can_prune = false, prune = false;
+  int ncs = 0;
+  float2* d_xyc = nullptr;
+  int* d_scol = nullptr;          // [n][ncs] kept slot -> spectral column (-1 = padding)
+  int* d_colslot = nullptr;       // [n][L1] spectral column -> kept slot (-1 = not kept)
+  int* d_pcnt[3] = {nullptr, nullptr, nullptr};
+  unsigned short* d_psidx[3] = {nullptr, nullptr, nullptr};
+  float2* d_psval[3] = {nullptr, nullptr, nullptr};
+  float2* d_pdense[3] = {nullptr, nullptr, nullptr};
+  PassCfg cfg_rowp, cfg_colp;
   // FISTA iterate in per-row slots while the row is sparse (ROW_FISTA_SP)
   bool sp_iter = false;
   int* d_cnt = nullptr;           // [n][L2]
@@ -84,6 +96,12 @@ void batch_free(bccb_batch_s* b) {
                     static_cast<void*>(c.d_sval)})
       if (p) (void)hipFree(p);
     if (c.h_sdesc) (void)hipHostFree(c.h_sdesc);
+    for (void* p : {static_cast<void*>(c.d_xyc), static_cast<void*>(c.d_scol), static_cast<void*>(c.d_colslot)})
+      if (p) (void)hipFree(p);
+    for (int i = 0; i < 3; ++i)
+      for (void* p : {static_cast<void*>(c.d_pcnt[i]), static_cast<void*>(c.d_psidx[i]),
+                      static_cast<void*>(c.d_psval[i]), static_cast<void*>(c.d_pdense[i])})
+        if (p) (void)hipFree(p);
   }
   if (b->d_flag) (void)hipFree(b->d_flag);
   if (b->h_flag) (void)hipHostFree(b->h_flag);
@@ -113,6 +131,60 @@ void default_batch_cfg(BatchClass& c) {
   while (!col_shape_ok(c.L1, c.L2, c.cfg_col) && c.cfg_col.W > 1) c.cfg_col.W /= 2;
 }
 
+void default_pruned_cfg(BatchClass& c) {
+  c.cfg_rowp.E = c.L1 >= 16 ? 16 : 8;
+  const int Tr = c.L1 / c.cfg_rowp.E;
+  c.cfg_rowp.rpb = std::max(1, 256 / Tr);
+  while (!rowp_shape_ok(c.L1, c.cfg_rowp, c.ncs) && c.cfg_rowp.rpb > 1) c.cfg_rowp.rpb /= 2;
+  c.cfg_colp.E = c.L2 >= 16 ? 16 : 8;
+  const int Tc = c.L2 / c.cfg_colp.E;
+  c.cfg_colp.W = std::min(c.ncs, std::max(1, 256 / Tc));
+  while (!colp_shape_ok(c.ncs, c.L2, c.cfg_colp) && c.cfg_colp.W > 1) c.cfg_colp.W /= 2;
+}
+
+SlotBuf class_buf(const BatchClass& c, int i) {
+  SlotBuf b;
+  b.cnt = c.d_pcnt[i];
+  b.sidx = c.d_psidx[i];
+  b.sval = c.d_psval[i];
+  b.dense = c.d_pdense[i];
+  return b;
+}
+
+// Pruned-pass arguments over the class arenas: c_{t-1} in buffer i1, c_{t-2} in i2 (-1: none), c_t into i0.
+RowArgs class_pruned_args(const BatchClass& c, int i0, int i1, int i2) {
+  RowArgs a;
+  a.xy = c.d_xyc;
+  a.colslot = c.d_colslot;
+  a.colslot_stride = c.L1;
+  a.ncs = c.ncs;
+  a.b0 = class_buf(c, i0);
+  a.b1 = class_buf(c, i1);
+  if (i2 >= 0) a.b2 = class_buf(c, i2);
+  a.out_c = c.d_c;
+  a.kscale = c.d_kscale;
+  a.kappa = 1.f;
+  return a;
+}
+
+int class_colp(const BatchClass& c, const PassCfg& cfg, hipStream_t s) {
+  ColArgs a;
+  a.xy = c.d_xyc;
+  a.sup_ptr = c.d_sup_ptr;
+  a.sup_ptr_stride = c.L1 + 1;
+  a.sup = c.d_sup;
+  a.sup_rhs = c.d_sup_rhs;
+  a.coef = c.d_coef;
+  a.tw = c.tw2;
+  a.L1 = c.L1;
+  a.nscenes = c.n;
+  a.ncols = c.ncs;
+  a.ldx = c.ncs;
+  a.scol = c.d_scol;
+  a.scol_stride = c.ncs;
+  return kern(launch_col(c.L2, cfg, COL_PRUNED_AFFINE, a, s));
+}
+
 int class_row(const BatchClass& c, const PassCfg& cfg, int mode, RowArgs a, hipStream_t s) {
   a.tw = c.tw1;
   a.nrows = c.n * c.L2;
@@ -139,11 +211,21 @@ int class_col(const BatchClass& c, const PassCfg& cfg, int mode, float2* xy, flo
 
 int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
   double alpha = 1.0;
+  float beta_prev = 0.f;
   for (int t = 1; t <= iters; ++t) {
     const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
     const float beta = static_cast<float>((alpha - 1.0) / alpha_next);
     alpha = alpha_next;
     for (BatchClass& c : b->cls) {
+      if (c.prune) {
+        BCCB_TRY(class_colp(c, c.cfg_colp, s));
+        RowArgs a = class_pruned_args(c, t % 3, (t - 1) % 3, (t + 1) % 3);
+        a.beta = beta;
+        a.beta_prev = beta_prev;
+        a.last = (t == iters);
+        BCCB_TRY(class_row(c, c.cfg_rowp, ROW_PRUNED, a, s));
+        continue;
+      }
       BCCB_TRY(class_col(c, c.cfg_col, c.sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, c.d_xy, 1.f, s));
       RowArgs a;
       a.xy = c.d_xy;
@@ -159,6 +241,7 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
       a.last = (t == iters);
       BCCB_TRY(class_row(c, c.cfg_row, c.sp_iter ? ROW_FISTA_SP : ROW_FISTA, a, s));
     }
+    beta_prev = beta;
   }
   return BCCB_OK;
 }
@@ -248,6 +331,44 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
       if (rc == BCCB_OK && hipMemset(c.d_cnt, 0x7f, rows * sizeof(int)) != hipSuccess) rc = BCCB_E_DEVICE;
       c.sp_iter = true;
       while (!row_shape_ok(c.L1, c.cfg_row, true) && c.cfg_row.rpb > 1) c.cfg_row.rpb /= 2;
+    }
+    c.can_prune = c.sparse;
+    for (int k = 0; k < c.n && c.can_prune; ++k) {
+      const bccb_plan_s* p = plans[c.scenes[k]];
+      c.can_prune = p->prune_ok;
+      c.ncs = std::max(c.ncs, p->ncs);
+    }
+    if (c.can_prune && c.ncs > c.L1 / 2) c.can_prune = false;
+    if (rc == BCCB_OK && c.can_prune) {
+      const size_t rows = static_cast<size_t>(c.n) * c.L2;
+      std::vector<int> scol(static_cast<size_t>(c.n) * c.ncs, -1), colslot(static_cast<size_t>(c.n) * c.L1, -1);
+      for (int k = 0; k < c.n; ++k) {
+        const bccb_plan_s* p = plans[c.scenes[k]];
+        for (int j = 0; j < p->nscol; ++j) {
+          scol[static_cast<size_t>(k) * c.ncs + j] = p->h_scol[j];
+          colslot[static_cast<size_t>(k) * c.L1 + p->h_scol[j]] = j;
+        }
+      }
+      rc = dalloc(&c.d_xyc, rows * c.ncs);
+      if (rc == BCCB_OK) rc = dalloc(&c.d_scol, scol.size());
+      if (rc == BCCB_OK) rc = dalloc(&c.d_colslot, colslot.size());
+      for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
+        rc = dalloc(&c.d_pcnt[i], rows);
+        if (rc == BCCB_OK) rc = dalloc(&c.d_psidx[i], rows * (c.L1 / 8));
+        if (rc == BCCB_OK) rc = dalloc(&c.d_psval[i], rows * (c.L1 / 8));
+        if (rc == BCCB_OK) rc = dalloc(&c.d_pdense[i], pts);
+        // rows start out dense over a zeroed grid: nothing unwritten is ever read
+        if (rc == BCCB_OK && (hipMemset(c.d_pcnt[i], 0x7f, rows * sizeof(int)) != hipSuccess ||
+                              hipMemset(c.d_pdense[i], 0, pts * sizeof(float2)) != hipSuccess))
+          rc = BCCB_E_DEVICE;
+      }
+      if (rc == BCCB_OK && (hipMemcpy(c.d_scol, scol.data(), scol.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+                            hipMemcpy(c.d_colslot, colslot.data(), colslot.size() * sizeof(int),
+                                      hipMemcpyHostToDevice) != hipSuccess ||
+                            hipMemset(c.d_xyc, 0, rows * c.ncs * sizeof(float2)) != hipSuccess))
+        rc = BCCB_E_DEVICE;
+      c.prune = true;
+      default_pruned_cfg(c);
     }
     if (rc != BCCB_OK) break;
     std::vector<float2> coef(c.n);
@@ -351,6 +472,12 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
     BCCB_TRY(kern(launch_fill(c.d_c, static_cast<long>(c.n) * c.L, s)));
     BCCB_TRY(kern(launch_fill(c.d_xy, static_cast<long>(c.n) * c.L, s)));
     if (c.sp_iter) BCCB_TRY(kern(launch_fill_int(c.d_cnt, static_cast<long>(c.n) * c.L2, c.L1 + 1, s)));
+    if (c.prune) {
+      // c_0 = c_{-1} = 0 (empty rows); the kept row spectra of z_1 = 0
+      BCCB_TRY(kern(launch_fill_int(c.d_pcnt[0], static_cast<long>(c.n) * c.L2, 0, s)));
+      BCCB_TRY(kern(launch_fill_int(c.d_pcnt[2], static_cast<long>(c.n) * c.L2, 0, s)));
+      BCCB_TRY(kern(launch_fill(c.d_xyc, static_cast<long>(c.n) * c.L2 * c.ncs, s)));
+    }
   }
   if (iters > 0) {
     if (!b->exec || b->graph_iters != iters) {
@@ -388,8 +515,8 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
   if (!b || reps < 1) return BCCB_E_INVALID;
   const int Es[4] = {4, 8, 16, 32};
   for (BatchClass& c : b->cls) {
-    float best_r = 1e30f, best_c = 1e30f;
-    PassCfg br = c.cfg_row, bc = c.cfg_col;
+    float best_r = 1e30f, best_c = 1e30f, best_rp = 1e30f, best_cp = 1e30f;
+    PassCfg br = c.cfg_row, bc = c.cfg_col, brp = c.cfg_rowp, bcp = c.cfg_colp;
     for (int E : Es) {
       for (int k = 1; k <= 256; k *= 2) {
         PassCfg r;
@@ -411,9 +538,26 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
           if (ms < 0.f) return BCCB_E_DEVICE;
           if (ms < best_r) { best_r = ms; br = r; }
         }
+        if (c.can_prune && rowp_shape_ok(c.L1, r, c.ncs)) {
+          // timed on the state most iterations see: rows of c_{t-1}, c_{t-2} in slot form
+          const long rows = static_cast<long>(c.n) * c.L2;
+          if (kern(launch_fill_int(c.d_pcnt[1], rows, 4, b->stream)) != BCCB_OK ||
+              kern(launch_fill_int(c.d_pcnt[2], rows, 4, b->stream)) != BCCB_OK)
+            return BCCB_E_DEVICE;
+          RowArgs a = class_pruned_args(c, 0, 1, 2);
+          a.beta = a.beta_prev = 0.5f;
+          const float ms = time_launches(b->stream, reps, [&] { return class_row(c, r, ROW_PRUNED, a, b->stream); });
+          if (ms < 0.f) return BCCB_E_DEVICE;
+          if (ms < best_rp) { best_rp = ms; brp = r; }
+        }
         PassCfg w;
         w.E = E;
         w.W = k;
+        if (c.can_prune && colp_shape_ok(c.ncs, c.L2, w)) {
+          const float ms = time_launches(b->stream, reps, [&] { return class_colp(c, w, b->stream); });
+          if (ms < 0.f) return BCCB_E_DEVICE;
+          if (ms < best_cp) { best_cp = ms; bcp = w; }
+        }
         if (col_shape_ok(c.L1, c.L2, w)) {
           const int cm = c.sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE;
           const float ms = time_launches(b->stream, reps, [&] { return class_col(c, w, cm, c.d_xy, 1.f, b->stream); });
@@ -424,7 +568,32 @@ int bccb_batch_autotune(bccb_batch_t b, int reps) {
     }
     c.cfg_row = br;
     c.cfg_col = bc;
+    c.cfg_rowp = brp;
+    c.cfg_colp = bcp;
   }
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->graph_iters = -1;
+  return BCCB_OK;
+}
+
+int bccb_batch_class_config(bccb_batch_t b, int cls, int* cfg) {
+  if (!b || !cfg || cls < 0 || cls >= static_cast<int>(b->cls.size())) return BCCB_E_INVALID;
+  const BatchClass& c = b->cls[cls];
+  const PassCfg& r = c.prune ? c.cfg_rowp : c.cfg_row;
+  const PassCfg& w = c.prune ? c.cfg_colp : c.cfg_col;
+  cfg[0] = r.E;
+  cfg[1] = r.rpb;
+  cfg[2] = w.E;
+  cfg[3] = w.W;
+  cfg[4] = c.prune ? 1 : 0;
+  cfg[5] = c.prune ? c.ncs : c.L1;
+  return BCCB_OK;
+}
+
+int bccb_batch_set_support_columns(bccb_batch_t b, int on) {
+  if (!b || (on != 0 && on != 1)) return BCCB_E_INVALID;
+  for (BatchClass& c : b->cls) c.prune = on == 1 && c.can_prune;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
   b->graph_iters = -1;

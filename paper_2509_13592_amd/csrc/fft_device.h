@@ -147,6 +147,10 @@ struct Stockham {
     return p;
   }
 
+  // LDS slot of exchange element i: one padding slot after every 8, so the
+  // stage writes (stride R in i) spread over the banks instead of piling onto few
+  __device__ static __forceinline__ int px(int i) { return i + (i >> 3); }
+
   // element index held in register slot e, for a layout whose stage radix is R
   template <int R>
   __device__ static __forceinline__ int layout_index(int t, int e) {
@@ -160,7 +164,8 @@ struct Stockham {
   // phase is preceded by a barrier so that no thread overwrites a slot another
   // thread of the previous read phase still needs; `sm[i*ss]` is slot i.
   template <bool INV, int S>
-  __device__ static __forceinline__ void stage(float2* v, int t, const float2* tw, float2* sm, int ss) {
+  __device__ static __forceinline__ void stage(float2* v, int t, const float2* tw, float2* sm, int ss,
+                                               bool sync0 = true) {
     constexpr int R = radix(S, INV);
     constexpr int NS = span(S, INV);
     constexpr int G = E / R;
@@ -168,7 +173,7 @@ struct Stockham {
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[g * R + r] = sm[(t + T * g + r * (N / R)) * ss];
+        for (int r = 0; r < R; ++r) v[g * R + r] = sm[px(t + T * g + r * (N / R)) * ss];
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -184,14 +189,14 @@ struct Stockham {
       dft_reg<R, INV>(v + g * R);
     }
     if constexpr (S + 1 < NST) {
-      __syncthreads();
+      if (S > 0 || sync0) __syncthreads();
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int j = t + T * g;
         const int k = j & (NS - 1);
         const int base = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) sm[(base + r * NS) * ss] = v[g * R + r];
+        for (int r = 0; r < R; ++r) sm[px(base + r * NS) * ss] = v[g * R + r];
       }
       __syncthreads();
       stage<INV, S + 1>(v, t, tw, sm, ss);
@@ -199,14 +204,79 @@ struct Stockham {
   }
 
   // v: forward input layout -> forward output layout.  Every thread of the
-  // block must call it (it contains barriers when NST > 1).
-  __device__ static __forceinline__ void forward(float2* v, int t, const float2* tw, float2* sm, int ss) {
-    stage<false, 0>(v, t, tw, sm, ss);
+  // block must call it (it contains barriers when NST > 1).  sync0 = false
+  // skips the barrier before the first LDS write when nothing may still read sm.
+  __device__ static __forceinline__ void forward(float2* v, int t, const float2* tw, float2* sm, int ss,
+                                                 bool sync0 = true) {
+    stage<false, 0>(v, t, tw, sm, ss, sync0);
   }
   // v: forward output layout -> forward input layout, unnormalised inverse.
-  __device__ static __forceinline__ void inverse(float2* v, int t, const float2* tw, float2* sm, int ss) {
-    stage<true, 0>(v, t, tw, sm, ss);
+  __device__ static __forceinline__ void inverse(float2* v, int t, const float2* tw, float2* sm, int ss,
+                                                 bool sync0 = true) {
+    stage<true, 0>(v, t, tw, sm, ss, sync0);
+  }
+
+  // Two-area form: exchange i goes through area A (i even) or B (i odd), so a
+  // write never meets a read of the same area still in flight and each
+  // exchange needs one barrier instead of two.  The first exchange writes A
+  // after a barrier only when `sync0` (A may still be read by the caller).
+  // After the call the area of the last exchange is B iff kLastB; a following
+  // transform may start in the other area with sync0 = false.
+  static constexpr bool kTwoArea = NST >= 3;
+  static constexpr bool kLastB = NST >= 2 && ((NST - 2) & 1) == 1;
+
+  template <bool INV, int S>
+  __device__ static __forceinline__ void stage2(float2* v, int t, const float2* tw, float2* smA, float2* smB, int ss,
+                                                bool sync0) {
+    constexpr int R = radix(S, INV);
+    constexpr int NS = span(S, INV);
+    constexpr int G = E / R;
+    if constexpr (S > 0) {
+      const float2* rd = ((S - 1) & 1) ? smB : smA;
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[g * R + r] = rd[px(t + T * g + r * (N / R)) * ss];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = t + T * g;
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 w = tw[(r * k * (N / (NS * R))) & (N - 1)];
+          v[g * R + r] = INV ? cmulc(v[g * R + r], w) : cmul(v[g * R + r], w);
+        }
+      }
+      dft_reg<R, INV>(v + g * R);
+    }
+    if constexpr (S + 1 < NST) {
+      float2* wr = (S & 1) ? smB : smA;
+      if constexpr (S == 0) {
+        if (sync0) __syncthreads();
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int j = t + T * g;
+        const int k = j & (NS - 1);
+        const int base = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) wr[px(base + r * NS) * ss] = v[g * R + r];
+      }
+      __syncthreads();
+      stage2<INV, S + 1>(v, t, tw, smA, smB, ss, sync0);
+    }
+  }
+  __device__ static __forceinline__ void forward2(float2* v, int t, const float2* tw, float2* smA, float2* smB, int ss,
+                                                  bool sync0) {
+    stage2<false, 0>(v, t, tw, smA, smB, ss, sync0);
+  }
+  __device__ static __forceinline__ void inverse2(float2* v, int t, const float2* tw, float2* smA, float2* smB, int ss,
+                                                  bool sync0) {
+    stage2<true, 0>(v, t, tw, smA, smB, ss, sync0);
   }
 };
+
 
 }  // namespace bccb

@@ -15,6 +15,23 @@ enum RowMode {
   ROW_ADMM = 4,   // u = IDFT_rows(xy); c = rhs + u; z = S_k(c + v); v += c - z; xy = DFT_rows(z - v)
   ROW_FISTA_SP = 5,  // ROW_FISTA with c_{t-1} / c_t kept per row as (index, value) slots while the row
                      // has at most N/8 nonzeros (dense row in `state` otherwise; always dense at the last iteration)
+  // Pruned forms for a sparse spectral support: the row spectra exchanged with the
+  // column pass hold only the support columns, compact as [row][ncs] (spectral
+  // column k1 at slot colslot[k1], -1 = not kept), and carry only the correction
+  // -mu G z_t + mu b; the identity part z_t is rebuilt in the spatial domain.
+  ROW_PRUNED_FWD = 6,  // xy[:, kept] = DFT_rows(src)[:, kept]   (src == nullptr -> zeros)
+  ROW_PRUNED = 7,      // z = c1 + beta_prev (c1 - c2); u = z + IDFT_rows(xy); c = S_k(u) -> b0;
+                       // xy[:, kept] = DFT_rows(c + beta (c - c1))[:, kept]
+};
+
+// An iterate stored per row as (index, value) slots while the row has at most
+// N/8 nonzeros, as the dense row otherwise: cnt[row] <= N/8 -> slots
+// sidx/sval[row * (N/8) + j], j < cnt; cnt[row] > N/8 -> dense[row * N + l].
+struct SlotBuf {
+  int* cnt = nullptr;
+  unsigned short* sidx = nullptr;
+  float2* sval = nullptr;
+  float2* dense = nullptr;
 };
 
 struct RowArgs {
@@ -44,6 +61,15 @@ struct RowArgs {
   int* cnt = nullptr;
   unsigned short* sidx = nullptr;
   float2* sval = nullptr;
+  // ROW_PRUNED*: kept-column map [scene][N] (scene stride colslot_stride), compact row length
+  // ncs of xy, iterates c_{t-1} (b1), c_{t-2} (b2; cnt == nullptr -> zero) and c_t (b0);
+  // at the last iteration c_t goes densely to out_c instead of b0
+  const int* colslot = nullptr;
+  long colslot_stride = 0;
+  int ncs = 0;
+  SlotBuf b0, b1, b2;
+  float beta_prev = 0.f;
+  float2* keep_c = nullptr;        // ROW_PRUNED, not last: also store c_t densely here (nullable)
 };
 
 // Column pass (transforms along l2, stride L1).
@@ -61,6 +87,7 @@ enum ColMode {
   // per-column list instead of dense grids.
   COL_SPARSE_AFFINE = 7,// xy = IDFT_cols(m . DFT_cols(xy) + r): m = a off the support, a + b Omega_j on it; r = rhs_j
   COL_SPARSE_ADMM = 8,  // m = scale/rho off the support, scale/(Omega_j + rho) on it; r = rhs_j/(Omega_j + rho)
+  COL_PRUNED_AFFINE = 9,// kept columns only: m = 0 off the support, b Omega_j on it; r = rhs_j
 };
 
 // One support bin of a column: spectral row k2 and its eigenvalue.
@@ -89,6 +116,12 @@ struct ColArgs {
   const SupEntry* sup = nullptr;
   const float2* sup_rhs = nullptr;
   long sup_rhs_stride = 0;
+  // compact column sets: ncols columns per scene at row stride ldx (0 = L1 for both);
+  // column c of scene s is spectral column scol[s * scol_stride + c] (-1 = padding)
+  int ncols = 0;
+  int ldx = 0;
+  const int* scol = nullptr;
+  long scol_stride = 0;
 };
 
 // Spectral right-hand side on the support bins, per scene:
@@ -104,6 +137,31 @@ struct SupRhsDesc {
 // src_ptr: [entries + 1] offsets into src; src[q] = (sensor index << 1) | (1 if (-1)^(m1+m2) = -1)
 int launch_sup_rhs(const SupRhsDesc* desc, int nscenes, int max_entries, const int* src_ptr, const int* src,
                    float2* rhs, int* flag, hipStream_t s);
+
+// LDS slots (float2) of one exchange area of an N-point transform: N plus one
+// padding slot per 8 (bank spreading).
+constexpr int fft_area(int N) { return N + N / 8; }
+
+// LDS exchange areas of a transform of N points at E per thread: two (used in
+// turn, one barrier per exchange) when it has three or more stages, else one.
+constexpr int fft_areas(int N, int E) {
+  int logn = 0, loge = 0;
+  while ((1 << logn) < N) ++logn;
+  while ((1 << loge) < E) ++loge;
+  const int nst = logn / loge + (logn % loge ? 1 : 0);
+  return nst >= 3 ? 2 : 1;
+}
+
+// LDS of the pruned row pass, in float2 units: two areas per row (slot
+// expansions, then the transforms' exchange areas), N twiddles, the compact
+// kept columns of each row, two occupancy masks of N bits per row and, for
+// rows longer than a wavefront, T counts per row.
+constexpr long rowp_lds_floats(int N, int E, int rpb, int ncs) {
+  const int T = N / E;
+  const int MW = (N + 31) / 32;
+  return 2L * rpb * fft_area(N) + N + static_cast<long>(rpb) * ncs + (2L * rpb * MW + 1) / 2 +
+         (T > 64 ? (static_cast<long>(rpb) * T + 1) / 2 : 0);
+}
 
 // Launch shape of the passes for one transform length: E elements per thread
 // (T = N/E threads per transform), rows per block of the row pass, columns per

@@ -50,6 +50,15 @@ struct bccb_lista_s {
   float2* d_sup_rhs = nullptr;                  // [cap][nsup]
   SupRhsDesc* d_sdesc = nullptr;                // [cap]
   SupRhsDesc* h_sdesc = nullptr;                // pinned [cap]
+  // pruned fallback (the plan has a kept-column set): kept row spectra [cap][L2][ncs],
+  // c_t over three SlotBufs whose dense grids are d_R0, d_xy and d_cprev
+  bool prune = false;
+  float2* d_xyc = nullptr;
+  float2* d_R0 = nullptr;
+  int* d_pcnt[3] = {nullptr, nullptr, nullptr};
+  unsigned short* d_psidx[3] = {nullptr, nullptr, nullptr};
+  float2* d_psval[3] = {nullptr, nullptr, nullptr};
+  PassCfg rcfgp, ccfgp;
 };
 
 namespace {
@@ -71,6 +80,11 @@ void lista_free(bccb_lista_s* n) {
                   n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0)})
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < 3; ++i)
+    for (void* p : {static_cast<void*>(n->d_pcnt[i]), static_cast<void*>(n->d_psidx[i]), static_cast<void*>(n->d_psval[i])})
+      if (p) (void)hipFree(p);
   if (n->h_desc) (void)hipHostFree(n->h_desc);
   if (n->h_map) (void)hipHostFree(n->h_map);
   if (n->h_tau) (void)hipHostFree(n->h_tau);
@@ -168,7 +182,7 @@ int run_layers(bccb_lista_s* n, const float* params, int batch, bool save) {
 int kkt_sums(bccb_lista_s* n, int nact, const int* map) {
   RowArgs f;
   f.xy = n->d_A;
-  f.src = n->d_c;
+  f.src = n->d_c;   // the fallback keeps a dense copy of every check's iterate here
   f.scene_map = map;
   BCCB_TRY(row(n, ROW_FWD, f, nact));
   BCCB_TRY(col(n, COL_FILTER_AFFINE, n->d_A, nact, n->d_coef_gram, nullptr, map));
@@ -221,11 +235,12 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
   {
     const int T = n->L1 / n->bwdE;
     n->bwd_rpb = std::max(1, 128 / T);
-    while (n->bwd_rpb > 1 && (static_cast<long>(n->bwd_rpb + 1) * n->L1 * 8 + static_cast<long>(n->bwd_rpb) * T * 16 > 65536))
+    while (n->bwd_rpb > 1 && ((static_cast<long>(n->bwd_rpb) * fft_area(n->L1) + n->L1) * 8 +
+                              static_cast<long>(n->bwd_rpb) * T * 16 > 65536))
       n->bwd_rpb /= 2;
     const int Tc = n->L2 / (n->L2 >= 16 ? 16 : 8);
     n->bwd_W = std::min(n->L1, std::max(1, 128 / Tc));
-    while (n->bwd_W > 1 && static_cast<long>(n->bwd_W + 1) * n->L2 * 8 > 65536) n->bwd_W /= 2;
+    while (n->bwd_W > 1 && (static_cast<long>(n->bwd_W) * fft_area(n->L2) + n->L2) * 8 > 65536) n->bwd_W /= 2;
   }
   n->groups = std::max(1, std::min(64, 512 / std::max(1, n->L1 / n->bwd_W)));
 
@@ -264,6 +279,24 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
     if (rc == BCCB_OK) rc = dalloc(&n->d_sdesc, max_batch);
     if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&n->h_sdesc), max_batch * sizeof(SupRhsDesc)) != hipSuccess)
       rc = BCCB_E_NOMEM;
+  }
+  if (rc == BCCB_OK && plan->prune_ok && sparse_on(plan)) {
+    // pruned fallback FISTA: kept row spectra, slot buffers, one more dense grid
+    const size_t rows = static_cast<size_t>(max_batch) * n->L2;
+    rc = dalloc(&n->d_xyc, rows * plan->ncs);
+    if (rc == BCCB_OK) rc = dalloc(&n->d_R0, pts);
+    for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
+      rc = dalloc(&n->d_pcnt[i], rows);
+      if (rc == BCCB_OK) rc = dalloc(&n->d_psidx[i], rows * (n->L1 / 8));
+      if (rc == BCCB_OK) rc = dalloc(&n->d_psval[i], rows * (n->L1 / 8));
+    }
+    n->prune = rc == BCCB_OK;
+    n->rcfgp.E = n->L1 >= 16 ? 16 : 8;
+    n->rcfgp.rpb = std::max(1, 256 / (n->L1 / n->rcfgp.E));
+    while (!rowp_shape_ok(n->L1, n->rcfgp, plan->ncs) && n->rcfgp.rpb > 1) n->rcfgp.rpb /= 2;
+    n->ccfgp.E = n->L2 >= 16 ? 16 : 8;
+    n->ccfgp.W = std::min(plan->ncs, std::max(1, 256 / (n->L2 / n->ccfgp.E)));
+    while (!colp_shape_ok(plan->ncs, n->L2, n->ccfgp) && n->ccfgp.W > 1) n->ccfgp.W /= 2;
   }
   if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&n->h_desc), max_batch * sizeof(SceneDesc)) != hipSuccess ||
                         hipHostMalloc(reinterpret_cast<void**>(&n->h_map), max_batch * sizeof(int)) != hipSuccess ||
@@ -459,6 +492,19 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     BCCB_HIP(hipMemcpyAsync(n->d_sdesc, n->h_sdesc, batch * sizeof(SupRhsDesc), hipMemcpyHostToDevice, s));
     BCCB_TRY(kern(launch_sup_rhs(n->d_sdesc, batch, p->nsup, p->d_src_ptr, p->d_src, n->d_sup_rhs, n->d_flag, s)));
   }
+  // the pruned passes (kept spectral columns, iterates in slot buffers) when the plan allows them
+  const bool pruned = sparse && n->prune && pruned_on(n->plan);
+  bccb_plan_s* pl = n->plan;
+  auto pbuf = [&](int i) {
+    SlotBuf b;
+    b.cnt = n->d_pcnt[i];
+    b.sidx = n->d_psidx[i];
+    b.sval = n->d_psval[i];
+    b.dense = i == 0 ? n->d_R0 : (i == 1 ? n->d_xy : n->d_cprev);
+    return b;
+  };
+  int tp = 0;   // pruned iterations so far: c_t lives in buffer tp mod 3
+  float beta_prev = 0.f;
   if (!act.empty() && max_iters > 0) {
     // warm start: z = current c (network output or zeros) or its momentum continuation
     const int na = static_cast<int>(act.size());
@@ -472,13 +518,69 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
                                     n->d_map, s)));
       f.src = n->d_A;
     }
-    BCCB_TRY(row(n, ROW_FWD, f, na));
+    if (pruned) {
+      // c_0 (dense, buffer 0) = the current c; c_{-1} (buffer 2) = c_{K-2} of the layers or none
+      const long rows = static_cast<long>(batch) * n->L2;
+      BCCB_TRY(kern(launch_copy(n->d_R0, n->d_c, static_cast<long>(batch) * n->L, s)));
+      BCCB_TRY(kern(launch_fill_int(n->d_pcnt[0], rows, n->L1 + 1, s)));
+      BCCB_TRY(kern(launch_fill_int(n->d_pcnt[2], rows, carry ? n->L1 + 1 : 0, s)));
+      beta_prev = carry ? static_cast<float>(n->beta[n->K - 1]) : 0.f;
+      f.xy = n->d_xyc;
+      f.colslot = pl->d_colslot;
+      f.ncs = pl->ncs;
+      f.tw = pl->d_tw1;
+      f.nrows = na * n->L2;
+      f.rows_per_scene = n->L2;
+      BCCB_TRY(kern(launch_row(n->L1, n->rcfgp, ROW_PRUNED_FWD, f, s)));
+    } else {
+      BCCB_TRY(row(n, ROW_FWD, f, na));
+    }
   }
   while (!act.empty() && done_iters < max_iters) {
     const int na = static_cast<int>(act.size());
     const int steps = std::min(check_every, max_iters - done_iters);
     for (int t = 0; t < steps; ++t) {
       const double an = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+      const float beta = static_cast<float>((alpha - 1.0) / an);
+      alpha = an;
+      if (pruned) {
+        ColArgs c;
+        c.xy = n->d_xyc;
+        c.sup_ptr = pl->d_sup_ptr;
+        c.sup = pl->d_sup;
+        c.sup_rhs = n->d_sup_rhs;
+        c.sup_rhs_stride = pl->nsup;
+        c.coef = n->d_coef_fista;
+        c.tw = pl->d_tw2;
+        c.L1 = n->L1;
+        c.nscenes = na;
+        c.scene_map = n->d_map;
+        c.ncols = pl->ncs;
+        c.ldx = pl->ncs;
+        c.scol = pl->d_scol;
+        BCCB_TRY(kern(launch_col(n->L2, n->ccfgp, COL_PRUNED_AFFINE, c, s)));
+        ++tp;
+        RowArgs a;
+        a.xy = n->d_xyc;
+        a.colslot = pl->d_colslot;
+        a.ncs = pl->ncs;
+        a.b0 = pbuf(tp % 3);
+        a.b1 = pbuf((tp - 1) % 3);
+        a.b2 = pbuf((tp + 1) % 3);
+        a.out_c = n->d_c;
+        a.keep_c = (t + 1 == steps) ? n->d_c : nullptr;   // dense c_t for the check and the output
+        a.kscale = n->d_tau;
+        a.kappa = static_cast<float>(pl->mu);
+        a.beta = beta;
+        a.beta_prev = beta_prev;
+        a.scene_map = n->d_map;
+        a.tw = pl->d_tw1;
+        a.nrows = na * n->L2;
+        a.rows_per_scene = n->L2;
+        beta_prev = beta;
+        BCCB_TRY(kern(launch_row(n->L1, n->rcfgp, ROW_PRUNED, a, s)));
+        continue;
+      }
       BCCB_TRY(col(n, sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, n->d_xy, na, n->d_coef_fista, nullptr,
                    n->d_map));
       RowArgs a;
@@ -488,9 +590,8 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
       a.state = n->d_c;
       a.kscale = n->d_tau;
       a.kappa = static_cast<float>(n->plan->mu);
-      a.beta = static_cast<float>((alpha - 1.0) / an);
+      a.beta = beta;
       a.scene_map = n->d_map;
-      alpha = an;
       BCCB_TRY(row(n, ROW_FISTA, a, na));
     }
     done_iters += steps;

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_lista_bwd_row(ListaBwdRowArgs a, int rp
   using F = Stockham<N, E>;
   constexpr int T = F::T;
   extern __shared__ float2 lds[];
-  float2* stw = lds + rpb * N;
+  float2* stw = lds + rpb * fft_area(N);
   double* red = reinterpret_cast<double*>(stw + N);
   const int tid = threadIdx.x;
   const int nthreads = rpb * T;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_lista_bwd_row(ListaBwdRowArgs a, int rp
   const bool active = row < a.nrows;
   const int prow = active ? row : 0;
   const int scene = prow / a.rows_per_scene;
-  float2* sm = lds + r * N;
+  float2* sm = lds + r * fft_area(N);
   const size_t base = static_cast<size_t>(prow) * N;
   const float2 zero = make_float2(0.f, 0.f);
 
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_lista_bwd_col(ListaBwdColArgs a, int W)
   using F = Stockham<N, E>;
   constexpr int T = F::T;
   extern __shared__ float2 lds[];
-  float2* stw = lds + W * N;
+  float2* stw = lds + W * fft_area(N);
   const int tid = threadIdx.x;
   const int nthreads = W * T;
   const int c = tid % W, t = tid / W;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_kkt_row(KktRowArgs a, int rpb) {
   using F = Stockham<N, E>;
   constexpr int T = F::T;
   extern __shared__ float2 lds[];
-  float2* stw = lds + rpb * N;
+  float2* stw = lds + rpb * fft_area(N);
   double* red = reinterpret_cast<double*>(stw + N);
   const int tid = threadIdx.x;
   const int nthreads = rpb * T;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_kkt_row(KktRowArgs a, int rpb) {
     if (a.scene_map) scene = a.scene_map[scene];
     prow = scene * a.rows_per_scene + within;
   }
-  float2* sm = lds + r * N;
+  float2* sm = lds + r * fft_area(N);
   const size_t base = static_cast<size_t>(prow) * N;
   const float2 zero = make_float2(0.f, 0.f);
   float2 v[E], cc[E], bb[E];
@@ -260,7 +260,8 @@ int lista_launch_e(int which, const void* args, int rpb_or_w, int groups, hipStr
     if (rpb < 1 || rpb * T > 256) return -1;
     const int blocks = (nrows + rpb - 1) / rpb;
     if (blocks <= 0) return 0;
-    const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2) + static_cast<size_t>(rpb) * T * 2 * sizeof(double);
+    const size_t shm = (static_cast<size_t>(rpb) * fft_area(N) + N) * sizeof(float2) +
+                       static_cast<size_t>(rpb) * T * 2 * sizeof(double);
     if (shm > 65536) return -1;
     if (which == 0)
       hipLaunchKernelGGL((k_lista_bwd_row<N, E>), dim3(blocks), dim3(rpb * T), shm, s,
@@ -272,7 +273,7 @@ int lista_launch_e(int which, const void* args, int rpb_or_w, int groups, hipStr
     const ListaBwdColArgs& a = *static_cast<const ListaBwdColArgs*>(args);
     const int W = rpb_or_w;
     if (W < 1 || W * T > 256 || a.L1 % W != 0 || groups < 1) return -1;
-    const size_t shm = static_cast<size_t>(W + 1) * N * sizeof(float2);
+    const size_t shm = (static_cast<size_t>(W) * fft_area(N) + N) * sizeof(float2);
     if (shm > 65536) return -1;
     hipLaunchKernelGGL((k_lista_bwd_col<N, E>), dim3(a.L1 / W, groups), dim3(W * T), shm, s, a, W);
   }

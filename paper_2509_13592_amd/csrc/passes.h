@@ -21,6 +21,12 @@ __device__ __forceinline__ bool finite2(float2 v) {
   return __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
 }
 
+// c ? a : 0, selected per component: a select of whole float2 values (an
+// aggregate) is lowered through memory, as a flat load from a chosen address.
+__device__ __forceinline__ float2 keep_if(bool c, float2 a) {
+  return make_float2(c ? a.x : 0.f, c ? a.y : 0.f);
+}
+
 // Complex soft threshold S_k(z) = z max(1 - k/|z|, 0), zero for |z| <= k (R3).
 __device__ __forceinline__ float2 shrink(float2 z, float k) {
   const float a2 = z.x * z.x + z.y * z.y;
@@ -31,7 +37,7 @@ __device__ __forceinline__ float2 shrink(float2 z, float k) {
 
 // ---------------------------------------------------------------------------
 // Row pass: a block owns `rpb` consecutive rows, T threads each.
-// Dynamic LDS: rpb * N float2 exchange slots + N twiddles.
+// Dynamic LDS: rpb * (one or two padded exchange areas) + N twiddles (+ counts).
 // ---------------------------------------------------------------------------
 // With spread > 1 the grid holds spread x the blocks and only every spread-th
 // does work: on a GPU that deals consecutive blocks round-robin to its XCDs
@@ -42,6 +48,71 @@ __device__ __forceinline__ bool spread_block(int spread, int& bid) {
   if (bid % spread != 0) return false;
   bid /= spread;
   return true;
+}
+
+
+// Transform helpers over a row's (or column's) exchange areas A and B.  Two-area
+// transforms take one barrier per exchange; single-area ones use A only and a
+// barrier before every write.  fft_fwd / fft_inv start by writing A, after a
+// barrier when `sync0` (A may still be read); fft_fwd_after_inv follows an
+// fft_inv and starts in the area that transform did not use last, without a barrier.
+template <class F>
+__device__ __forceinline__ void fft_fwd(float2* v, int t, const float2* tw, float2* A, float2* B, bool sync0,
+                                        int ss = 1) {
+  if constexpr (F::kTwoArea) F::forward2(v, t, tw, A, B, ss, sync0);
+  else F::forward(v, t, tw, A, ss, sync0);
+}
+template <class F>
+__device__ __forceinline__ void fft_inv(float2* v, int t, const float2* tw, float2* A, float2* B, bool sync0 = false,
+                                        int ss = 1) {
+  if constexpr (F::kTwoArea) F::inverse2(v, t, tw, A, B, ss, sync0);
+  else F::inverse(v, t, tw, A, ss, sync0);
+}
+template <class F>
+__device__ __forceinline__ void fft_fwd_after_inv(float2* v, int t, const float2* tw, float2* A, float2* B, int ss = 1) {
+  if constexpr (F::kTwoArea) {
+    if constexpr (F::kLastB) F::forward2(v, t, tw, A, B, ss, false);
+    else F::forward2(v, t, tw, B, A, ss, false);
+  } else {
+    F::forward(v, t, tw, A, ss);
+  }
+}
+template <class F>
+__device__ __forceinline__ void fft_inv_after_fwd(float2* v, int t, const float2* tw, float2* A, float2* B, int ss = 1) {
+  if constexpr (F::kTwoArea) {
+    if constexpr (F::kLastB) F::inverse2(v, t, tw, A, B, ss, false);
+    else F::inverse2(v, t, tw, B, A, ss, false);
+  } else {
+    F::inverse(v, t, tw, A, ss);
+  }
+}
+
+// Number of nonzeros of a row (T threads, `mine` each) and the count before
+// thread t.  Rows of at most 64 threads sit inside one wavefront (T divides 64):
+// a segmented shuffle scan; longer rows go through LDS (`cnt`: T ints per row,
+// one barrier, reached by the whole block).
+template <int T>
+__device__ __forceinline__ void row_prefix(int mine, int t, int* cnt, int& total, int& before) {
+  if constexpr (T <= 64) {
+    int incl = mine;
+#pragma unroll
+    for (int d = 1; d < T; d <<= 1) {
+      const int y = __shfl_up(incl, d, T);
+      if (t >= d) incl += y;
+    }
+    before = incl - mine;
+    total = __shfl(incl, T - 1, T);
+  } else {
+    cnt[t] = mine;
+    __syncthreads();
+    total = 0;
+    before = 0;
+    for (int i = 0; i < T; ++i) {
+      const int ci = cnt[i];
+      total += ci;
+      before += (i < t) ? ci : 0;
+    }
+  }
 }
 
 template <int N>
@@ -58,8 +129,10 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   constexpr bool kState = (MODE == ROW_FISTA || MODE == ROW_ADMM);
   constexpr int CAP = SparseRow<N>::CAP;
   constexpr int SPT = (CAP + T - 1) / T;   // slots read per thread
+  constexpr int AR = fft_areas(N, E);
+  constexpr int FA = fft_area(N);
   extern __shared__ float2 lds[];
-  float2* stw = lds + rpb * N;
+  float2* stw = lds + AR * rpb * FA;
   int* rowcnt = reinterpret_cast<int*>(stw + N);   // kSp: rpb * T ints
   int bid;
   if (!spread_block(a.spread, bid)) return;  // whole block exits together
@@ -69,7 +142,8 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   const int r = tid / T, t = tid - (tid / T) * T;
   const int row = bid * rpb + r;
   const bool active = row < a.nrows;
-  float2* sm = lds + r * N;
+  float2* sm = lds + AR * r * FA;      // exchange area (and slot expansion)
+  float2* sm2 = sm + (AR - 1) * FA;    // second exchange area (two-area transforms)
   // logical row -> physical row of the arenas (scene compaction through scene_map)
   int scene = 0, prow = 0;
   if (active) {
@@ -169,19 +243,19 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
 #pragma unroll
     for (int e = 0; e < E; ++e) ok = ok && finite2(v[e]);
     if (!ok && a.flag) *a.flag = 1;
-    F::forward(v, t, stw, sm, 1);
+    fft_fwd<F>(v, t, stw, sm, sm2, false);
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) a.xy[base + F::out_index(t, e)] = v[e];
     }
   } else if constexpr (MODE == ROW_INV) {
-    F::inverse(v, t, stw, sm, 1);
+    fft_inv<F>(v, t, stw, sm, sm2);
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) a.dst[base + F::in_index(t, e)] = cscale(v[e], a.scale);
     }
   } else {
-    F::inverse(v, t, stw, sm, 1);
+    fft_inv<F>(v, t, stw, sm, sm2);
     float kbase = a.kappa, rs = a.rhs_scale;
     if (a.dscal) {
       kbase = a.dscal[0];
@@ -231,14 +305,8 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
       int mine = 0;
 #pragma unroll
       for (int e = 0; e < E; ++e) mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
-      rowcnt[r * T + t] = mine;
-      __syncthreads();
-      int total = 0, before = 0;
-      for (int i = 0; i < T; ++i) {
-        const int ci = rowcnt[r * T + i];
-        total += ci;
-        before += (i < t) ? ci : 0;
-      }
+      int total, before;
+      row_prefix<T>(mine, t, rowcnt + r * T, total, before);
       const bool dense = a.last || total > CAP;
       if (active) {
         if (dense) {
@@ -263,7 +331,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         v[e] = make_float2(v[e].x + a.beta * (v[e].x - sp[e].x), v[e].y + a.beta * (v[e].y - sp[e].y));
     }
     if (!a.last) {
-      F::forward(v, t, stw, sm, 1);
+      fft_fwd_after_inv<F>(v, t, stw, sm, sm2);
       if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) a.xy[base + F::out_index(t, e)] = v[e];
@@ -272,31 +340,254 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Pruned row pass (sparse spectral support).  G = IDFT2 . Omega . DFT2 and
+// Omega vanishes off the support bins, so (I - mu G) z_t + mu b = z_t +
+// IDFT2(-mu Omega DFT2(z_t) + mu DFT2(b)) has its spectral correction on the
+// support columns only: the column pass transforms just those, and this pass
+// reads / writes just those columns of the row spectra (compact [row][ncs]).
+// z_t is rebuilt in the spatial domain from c_{t-1} and c_{t-2}, which are kept
+// per row in SlotBufs (sparse rows as slots), so a late iteration moves a few
+// bytes per row instead of the whole grid.
+// Dynamic LDS: 3 rpb N float2 (expansions of c_{t-1}, c_{t-2} and the kept
+// spectral columns; the first is then the transforms' exchange area) + N
+// twiddles + rpb T counts.
+// ---------------------------------------------------------------------------
+template <int N, int E>
+__device__ __forceinline__ void load_slots(const SlotBuf& b, int prow, int t, int& n, unsigned short (&si)[(N / 8 + N / E - 1) / (N / E)],
+                                           float2 (&sv)[(N / 8 + N / E - 1) / (N / E)]) {
+  constexpr int T = N / E;
+  constexpr int CAP = N / 8;
+  constexpr int SPT = (CAP + T - 1) / T;
+  n = b.cnt ? b.cnt[prow] : 0;
+  if (!b.cnt) return;
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    const int j = t + T * q;
+    const int jj = j < CAP ? j : 0;
+    si[q] = b.sidx[static_cast<size_t>(prow) * CAP + jj];
+    sv[q] = b.sval[static_cast<size_t>(prow) * CAP + jj];
+  }
+}
+
+template <int N, int E, int MODE>
+__global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
+  using F = Stockham<N, E>;
+  constexpr int T = F::T;
+  constexpr int CAP = SparseRow<N>::CAP;
+  constexpr int SPT = (CAP + T - 1) / T;
+  constexpr int MW = (N + 31) / 32;
+  constexpr bool kTwo = F::kTwoArea;
+  extern __shared__ float2 lds[];
+  int bid;
+  if (!spread_block(a.spread, bid)) return;  // whole block exits together
+
+  const int tid = threadIdx.x;
+  const int nthreads = rpb * T;
+  const int r = tid / T, t = tid - (tid / T) * T;
+  const int row = bid * rpb + r;
+  const bool active = row < a.nrows;
+  const int ncs = a.ncs;
+  constexpr int FA = fft_area(N);
+  float2* sa = lds + (2 * r) * FA;      // exchange area A; c_{t-2} expansion
+  float2* sb = sa + FA;                 // exchange area B (two-area transforms); c_{t-1} expansion
+  float2* stw = lds + 2 * rpb * FA;
+  float2* lst = stw + N + r * ncs;      // the row's kept spectral columns, compact
+  unsigned* msk = reinterpret_cast<unsigned*>(stw + N + rpb * ncs) + r * 2 * MW;   // [2][MW]
+  int* rowcnt = reinterpret_cast<int*>(reinterpret_cast<unsigned*>(stw + N + rpb * ncs) + rpb * 2 * MW) + r * T;
+  int scene = 0, prow = 0;
+  if (active) {
+    scene = row / a.rows_per_scene;
+    const int within = row - scene * a.rows_per_scene;
+    if (a.scene_map) scene = a.scene_map[scene];
+    prow = scene * a.rows_per_scene + within;
+  }
+  const size_t base = static_cast<size_t>(prow) * N;
+  const size_t xrow = static_cast<size_t>(prow) * ncs;
+  const int* cs = a.colslot + scene * a.colslot_stride;
+  const float2 zero = make_float2(0.f, 0.f);
+
+  // kept-column slot of each of this thread's spectral bins (natural order out_index)
+  int ks[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) ks[e] = cs[F::out_index(t, e)];
+
+  if constexpr (MODE == ROW_PRUNED_FWD) {
+    float2 v[E];
+    if (a.src) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = a.src[base + F::in_index(t, e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = zero;
+    }
+    if (!active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = zero;
+    }
+    for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < E; ++e) ok = ok && finite2(v[e]);
+    if (!ok && a.flag) *a.flag = 1;
+    __syncthreads();
+    fft_fwd<F>(v, t, stw, sa, sb, false);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (ks[e] >= 0) a.xy[xrow + ks[e]] = v[e];
+    }
+  } else {
+    // global loads, all independent: slots of c_{t-1} and c_{t-2}, the compact
+    // kept columns (into LDS), the twiddles; the occupancy masks start empty
+    int n1, n2;
+    unsigned short i1[SPT], i2[SPT];
+    float2 w1[SPT], w2[SPT];
+    load_slots<N, E>(a.b1, prow, t, n1, i1, w1);
+    load_slots<N, E>(a.b2, prow, t, n2, i2, w2);
+    if (!active) n1 = n2 = 0;
+    for (int j = t; j < ncs; j += T) {
+      const float2 x = a.xy[xrow + j];   // row 0 when inactive: a valid address
+      lst[j] = keep_if(active, x);
+    }
+    for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+    for (int j = t; j < 2 * MW; j += T) msk[j] = 0u;
+    // dense rows go to their area straight from memory (each thread its own elements)
+    const bool full1 = n1 > CAP, full2 = n2 > CAP;
+    if (full1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sb[F::in_index(t, e)] = a.b1.dense[base + F::in_index(t, e)];
+    }
+    if (full2) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sa[F::in_index(t, e)] = a.b2.dense[base + F::in_index(t, e)];
+    }
+    __syncthreads();
+    // scatter the slot rows: c_{t-1} into B (it outlives a single-area transform), c_{t-2} into A
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const int j = t + T * q;
+      if (!full1 && j < n1) {
+        const int idx = i1[q] < N ? i1[q] : N - 1;
+        sb[idx] = w1[q];
+        atomicOr(&msk[idx >> 5], 1u << (idx & 31));
+      }
+      if (!full2 && j < n2) {
+        const int idx = i2[q] < N ? i2[q] : N - 1;
+        sa[idx] = w2[q];
+        atomicOr(&msk[MW + (idx >> 5)], 1u << (idx & 31));
+      }
+    }
+    __syncthreads();
+    // z_t = c_{t-1} + beta_{t-1} (c_{t-1} - c_{t-2}) at this thread's elements
+    float2 z[E];
+    float2 c1[kTwo ? E : 1];   // two-area transforms overwrite B: c_{t-1} stays in registers
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = F::in_index(t, e);
+      const float2 l1 = sb[idx], l2 = sa[idx];
+      const float2 p1 = keep_if(full1 || ((msk[idx >> 5] >> (idx & 31)) & 1u), l1);
+      const float2 p2 = keep_if(full2 || ((msk[MW + (idx >> 5)] >> (idx & 31)) & 1u), l2);
+      z[e] = make_float2(p1.x + a.beta_prev * (p1.x - p2.x), p1.y + a.beta_prev * (p1.y - p2.y));
+      if constexpr (kTwo) c1[e] = p1;
+    }
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = keep_if(ks[e] >= 0, lst[ks[e] >= 0 ? ks[e] : 0]);
+
+    fft_inv<F>(v, t, stw, sa, sb, true);   // the expansions were read from A / B
+    const float kappa = a.kscale ? a.kappa * a.kscale[scene] : a.kappa;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = shrink(make_float2(z[e].x + v[e].x, z[e].y + v[e].y), kappa);
+
+    if (a.last) {
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a.out_c[base + F::in_index(t, e)] = v[e];
+      }
+      return;   // uniform over the grid
+    }
+    if (a.keep_c && active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) a.keep_c[base + F::in_index(t, e)] = v[e];
+    }
+    // store c_t: slots if the row has at most CAP nonzeros, the dense row otherwise
+    int mine = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
+    int total, before;
+    row_prefix<T>(mine, t, rowcnt, total, before);
+    if (active) {
+      if (total > CAP) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a.b0.dense[base + F::in_index(t, e)] = v[e];
+      } else {
+        int o = before;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (v[e].x != 0.f || v[e].y != 0.f) {
+            a.b0.sidx[static_cast<size_t>(prow) * CAP + o] = static_cast<unsigned short>(F::in_index(t, e));
+            a.b0.sval[static_cast<size_t>(prow) * CAP + o] = v[e];
+            ++o;
+          }
+        }
+      }
+      if (t == 0) a.b0.cnt[prow] = total > CAP ? CAP + 1 + total : total;
+    }
+    // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); its row DFT on the kept columns
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      float2 p1;
+      if constexpr (kTwo) {
+        p1 = c1[e];
+      } else {
+        const int idx = F::in_index(t, e);
+        const float2 l1 = sb[idx];   // B is untouched by a single-area transform
+        p1 = keep_if(full1 || ((msk[idx >> 5] >> (idx & 31)) & 1u), l1);
+      }
+      v[e] = make_float2(v[e].x + a.beta * (v[e].x - p1.x), v[e].y + a.beta * (v[e].y - p1.y));
+    }
+    fft_fwd_after_inv<F>(v, t, stw, sa, sb);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (ks[e] >= 0) a.xy[xrow + ks[e]] = v[e];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Column pass: a block owns W adjacent columns of one scene; lane = c + W*t.
-// Dynamic LDS: W * N float2 exchange slots (column c at stride W) + N twiddles.
+// Dynamic LDS: W * (one or two padded exchange areas), column c at stride W, + N twiddles.
 // ---------------------------------------------------------------------------
 template <int N, int E, int MODE>
 __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   using F = Stockham<N, E>;
   constexpr int T = F::T;
+  constexpr int AR = fft_areas(N, E);
+  constexpr int FA = fft_area(N);
   extern __shared__ float2 lds[];
-  float2* stw = lds + W * N;
+  float2* stw = lds + AR * W * FA;
   int bid;
   if (!spread_block(a.spread, bid)) return;  // whole block exits together
 
   const int tid = threadIdx.x;
   const int nthreads = W * T;
   const int c = tid % W, t = tid / W;
-  const int strips = a.L1 / W;
+  const int ncols = a.ncols ? a.ncols : a.L1;
+  const int ldx = a.ldx ? a.ldx : a.L1;
+  const int strips = ncols / W;
   const int lscene = bid / strips;
   const int col = (bid - lscene * strips) * W + c;
   const int scene = a.scene_map ? a.scene_map[lscene] : lscene;
-  const size_t plane = static_cast<size_t>(N) * a.L1;
+  const size_t plane = static_cast<size_t>(N) * ldx;
   float2* g = a.xy + scene * plane + col;
-  float2* sms = lds + c;
+  float2* sms = lds + c;                    // column c's exchange slots, stride W
+  float2* sms2 = sms + (AR - 1) * W * FA;   // second area (two-area transforms)
+  const int k1 = a.scol ? a.scol[scene * a.scol_stride + col] : col;   // spectral column
 
-  constexpr bool kSparse = (MODE == COL_SPARSE_AFFINE || MODE == COL_SPARSE_ADMM);
+  constexpr bool kSparse = (MODE == COL_SPARSE_AFFINE || MODE == COL_SPARSE_ADMM || MODE == COL_PRUNED_AFFINE);
   constexpr bool kFwd = (MODE == COL_FWD || MODE == COL_FILTER_AFFINE || MODE == COL_FILTER_ADMM ||
                          MODE == COL_FILTER_CPLX || kSparse);
   constexpr bool kInv = (MODE != COL_FWD);
@@ -307,10 +598,10 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   float2 v[E];
   if constexpr (kFwd) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::in_index(t, e)) * a.L1];
+    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::in_index(t, e)) * ldx];
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::out_index(t, e)) * a.L1];
+    for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::out_index(t, e)) * ldx];
   }
   float om[(kMul && !kCplx) ? E : 1];
   float2 mc[kCplx ? E : 1];
@@ -326,7 +617,7 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
   __syncthreads();
 
-  if constexpr (kFwd) F::forward(v, t, stw, sms, W);
+  if constexpr (kFwd) fft_fwd<F>(v, t, stw, sms, sms2, false, W);
 
   if constexpr (kCplx) {
 #pragma unroll
@@ -346,6 +637,9 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
     if constexpr (MODE == COL_SPARSE_AFFINE) {
       ab = a.coef[scene];
       mdef = ab.x;
+    } else if constexpr (MODE == COL_PRUNED_AFFINE) {
+      ab = make_float2(0.f, a.coef[scene].y);   // correction only: the identity stays spatial
+      mdef = 0.f;
     } else {
       mdef = a.scale / a.rho;
     }
@@ -355,8 +649,8 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
       src[e] = v[e];
       v[e] = cscale(v[e], mdef);
     }
-    const int* ptr = a.sup_ptr + scene * a.sup_ptr_stride + col;
-    const int j0 = ptr[0], j1 = ptr[1];
+    const int* ptr = a.sup_ptr + scene * a.sup_ptr_stride + (k1 >= 0 ? k1 : 0);
+    const int j0 = ptr[0], j1 = k1 >= 0 ? ptr[1] : j0;   // padding columns: no entries
     const float2* rhs = a.sup_rhs + scene * a.sup_rhs_stride;
     for (int j = j0; j < j1; ++j) {
       const SupEntry en = a.sup[j];
@@ -364,7 +658,7 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (F::out_index(t, e) == en.k2) {
-          if constexpr (MODE == COL_SPARSE_AFFINE) {
+          if constexpr (MODE == COL_SPARSE_AFFINE || MODE == COL_PRUNED_AFFINE) {
             const float m = ab.x + ab.y * en.omega;
             v[e] = make_float2(src[e].x * m + r.x, src[e].y * m + r.y);
           } else {
@@ -378,13 +672,14 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   }
 
   if constexpr (kInv) {
-    F::inverse(v, t, stw, sms, W);
+    if constexpr (kFwd) fft_inv_after_fwd<F>(v, t, stw, sms, sms2, W);
+    else fft_inv<F>(v, t, stw, sms, sms2, false, W);
     const float s = (MODE == COL_INV) ? a.scale : 1.f;
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::in_index(t, e)) * a.L1] = cscale(v[e], s);
+    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::in_index(t, e)) * ldx] = cscale(v[e], s);
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::out_index(t, e)) * a.L1] = v[e];
+    for (int e = 0; e < E; ++e) g[static_cast<size_t>(F::out_index(t, e)) * ldx] = v[e];
   }
 }
 
@@ -397,14 +692,23 @@ int row_launch_e(int mode, const RowArgs& a, int rpb, hipStream_t s) {
   if (rpb < 1 || rpb * T > 256) return -1;
   const int blocks = (a.nrows + rpb - 1) / rpb;
   if (blocks <= 0) return 0;
-  const size_t shm = static_cast<size_t>(rpb + 1) * N * sizeof(float2) +
-                     (mode == ROW_FISTA_SP ? static_cast<size_t>(rpb) * T * sizeof(int) : 0);
+  const bool pruned = (mode == ROW_PRUNED || mode == ROW_PRUNED_FWD);
+  const size_t shm = pruned ? static_cast<size_t>(rowp_lds_floats(N, E, rpb, a.ncs)) * sizeof(float2)
+                            : (static_cast<size_t>(fft_areas(N, E)) * rpb * fft_area(N) + N) * sizeof(float2) +
+                                  (mode == ROW_FISTA_SP ? static_cast<size_t>(rpb) * T * sizeof(int) : 0);
   if (shm > 65536) return -1;
   if (mode == ROW_FISTA_SP && (!a.cnt || !a.sidx || !a.sval || !a.state)) return -1;
+  if (pruned && (!a.colslot || a.ncs < 1 || a.ncs > N / 2)) return -1;
+  if (mode == ROW_PRUNED && (!a.b1.cnt || !a.b1.sidx || !a.b1.sval || !a.b1.dense || !a.b0.cnt || !a.b0.sidx ||
+                             !a.b0.sval || !a.b0.dense || !a.out_c ||
+                             (a.b2.cnt && (!a.b2.sidx || !a.b2.sval || !a.b2.dense))))
+    return -1;
   const int spread = a.spread > 1 ? a.spread : 1;
   const dim3 grid(blocks * spread), block(rpb * T);
   switch (mode) {
     case ROW_FISTA_SP: hipLaunchKernelGGL((k_row<N, E, ROW_FISTA_SP>), grid, block, shm, s, a, rpb); break;
+    case ROW_PRUNED_FWD: hipLaunchKernelGGL((k_rowp<N, E, ROW_PRUNED_FWD>), grid, block, shm, s, a, rpb); break;
+    case ROW_PRUNED: hipLaunchKernelGGL((k_rowp<N, E, ROW_PRUNED>), grid, block, shm, s, a, rpb); break;
     case ROW_FWD: hipLaunchKernelGGL((k_row<N, E, ROW_FWD>), grid, block, shm, s, a, rpb); break;
     case ROW_INV: hipLaunchKernelGGL((k_row<N, E, ROW_INV>), grid, block, shm, s, a, rpb); break;
     case ROW_ISTA: hipLaunchKernelGGL((k_row<N, E, ROW_ISTA>), grid, block, shm, s, a, rpb); break;
@@ -418,10 +722,12 @@ int row_launch_e(int mode, const RowArgs& a, int rpb, hipStream_t s) {
 template <int N, int E>
 int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
   constexpr int T = Stockham<N, E>::T;
-  if (W < 1 || W * T > 256 || a.L1 % W != 0) return -1;
-  const int blocks = (a.L1 / W) * a.nscenes;
+  const int ncols = a.ncols ? a.ncols : a.L1;
+  if (W < 1 || W * T > 256 || ncols % W != 0) return -1;
+  if ((mode == COL_PRUNED_AFFINE) != (a.scol != nullptr)) return -1;
+  const int blocks = (ncols / W) * a.nscenes;
   if (blocks <= 0) return 0;
-  const size_t shm = static_cast<size_t>(W + 1) * N * sizeof(float2);
+  const size_t shm = (static_cast<size_t>(fft_areas(N, E)) * W * fft_area(N) + N) * sizeof(float2);
   if (shm > 65536) return -1;
   const int spread = a.spread > 1 ? a.spread : 1;
   const dim3 grid(blocks * spread), block(W * T);
@@ -435,6 +741,7 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
     case COL_MULINV_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_MULINV_ADMM>), grid, block, shm, s, a, W); break;
     case COL_SPARSE_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_AFFINE>), grid, block, shm, s, a, W); break;
     case COL_SPARSE_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_ADMM>), grid, block, shm, s, a, W); break;
+    case COL_PRUNED_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_AFFINE>), grid, block, shm, s, a, W); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;

@@ -56,6 +56,22 @@ struct bccb_plan_s {
   unsigned short* d_sidx = nullptr;
   float2* d_sval = nullptr;
 
+  // pruned iteration (sparse support): the spectral columns holding support bins,
+  // padded to ncs (a multiple of 4) with -1; colslot[k1] = position of k1 or -1;
+  // xyc [L2][ncs] the kept row spectra; c_t rotates over three SlotBufs
+  std::vector<int> h_scol;
+  int nscol = 0, ncs = 0;
+  bool prune_ok = false;
+  int use_prune = 1;
+  int* d_scol = nullptr;
+  int* d_colslot = nullptr;
+  float2* d_xyc = nullptr;
+  int* d_pcnt[3] = {nullptr, nullptr, nullptr};
+  unsigned short* d_psidx[3] = {nullptr, nullptr, nullptr};
+  float2* d_psval[3] = {nullptr, nullptr, nullptr};
+  float2* d_pdense[3] = {nullptr, nullptr, nullptr};
+  bccb::PassCfg cfg_rowp, cfg_colp;
+
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
   int use_graph = 1;
@@ -88,6 +104,9 @@ int begin_call(bccb_plan_s* p);
 int end_call(bccb_plan_s* p);
 bool row_shape_ok(int L1, const PassCfg& c, bool sparse_iterate = false);
 bool col_shape_ok(int L1, int L2, const PassCfg& c);
+bool rowp_shape_ok(int L1, const PassCfg& c, int ncs);    // pruned row pass over ncs kept columns
+bool colp_shape_ok(int ncs, int L2, const PassCfg& c);    // pruned column pass over ncs columns
+bool pruned_on(const bccb_plan_s* p);
 
 // Time `reps` launches of `launch()` on stream s with hipEvents; ms per launch, or < 0 on error.
 template <typename F>

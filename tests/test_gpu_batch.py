@@ -80,6 +80,7 @@ def test_batch_sparse_iterate_matches_dense_iterate():
     scenes.append(S.custom_scene(20, 6, 40, 16, 8, K=2, snr_db=20, seed=(16, 0, 0)))
     plans, ys, taus = _setup(scenes)
     batch = B.Batch(plans)
+    batch.set_support_columns(False)   # the full passes, where the option applies
     for iters in (1, 3, 40, 250):
         res = {}
         for on in (True, False):
@@ -97,6 +98,44 @@ def test_batch_sparse_iterate_matches_dense_iterate():
         x, r = _np(a), _np(b)
         assert np.linalg.norm(x - r) <= 1e-3 * max(np.linalg.norm(r), 1e-30)
     assert B.lib.bccb_batch_set_sparse_iterate(batch._h, 2) == B.BCCB_E_INVALID
+    batch.close()
+
+
+def test_batch_support_columns_matches_full_passes():
+    """The pruned batched iteration (kept spectral columns only; the default for size
+    classes whose scenes all have few such columns) and the full passes give the same
+    solutions to FP32 rounding, and both match the oracle's objective."""
+    scenes = [S.batched_scene(400 + i) for i in range(12)]
+    scenes.append(S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(19, 0, 0)))
+    scenes.append(S.custom_scene(20, 6, 40, 32, 8, K=2, snr_db=20, seed=(20, 0, 0)))   # too many columns
+    plans, ys, taus = _setup(scenes)
+    print("kept columns", [p.support_columns() for p in plans], flush=True)
+    batch = B.Batch(plans)
+    for iters in (0, 1, 5, 200):
+        res = {}
+        for on in (True, False):
+            batch.set_support_columns(on)
+            res[on] = [_np(o) for o in batch.fista(ys, taus, iters)]
+        for i, sc in enumerate(scenes):
+            a, b = res[True][i], res[False][i]
+            d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            if iters <= 5:
+                assert d <= 1e-4, (i, iters, d)
+            if iters == 200:
+                P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+                ref = P.fista(iters)
+                Fr = P.objective(ref)
+                rel = abs(P.objective(a) - Fr) / Fr
+                print(f"case batch pruned scene {i} L={sc.L1}x{sc.L2}: rel F={rel:.2e} |pruned-full|={d:.1e}",
+                      flush=True)
+                assert rel <= OBJ_TOL
+    batch.set_support_columns(True)
+    batch.autotune(reps=3)
+    o = batch.fista(ys, taus, 200)
+    for i in range(len(scenes)):
+        x, r = _np(o[i]), res[True][i]
+        assert np.linalg.norm(x - r) <= 1e-3 * max(np.linalg.norm(r), 1e-30)
+    assert B.lib.bccb_batch_set_support_columns(batch._h, 5) == B.BCCB_E_INVALID
     batch.close()
 
 

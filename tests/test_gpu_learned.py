@@ -188,4 +188,23 @@ def test_kkt_gated_solve():
             assert rk[i] <= target
             assert r_ref <= 1.05 * target
             assert abs(r_ref - rk[i]) <= 0.05 * target
+    # the fallback through the full passes (kept-column pruning off) follows the same
+    # trajectory to FP32 rounding: same checks passed, same iterates to the KKT target
+    ncols, pruned = plan.support_columns()
+    assert pruned, "the 16x16 URA at 256^2 keeps 16 spectral columns"
+    plan.set_config(support_columns=0)
+    for name in ("plain", "identity"):
+        c_full, it_full, rk_full, rc = net.solve(cases[name], ys, taus, kkt_target=target, check_every=10,
+                                                 max_iters=4000)
+        plan.set_config(support_columns=1)
+        c_pr, it_pr, rk_pr, rc2 = net.solve(cases[name], ys, taus, kkt_target=target, check_every=10,
+                                            max_iters=4000)
+        plan.set_config(support_columns=0)
+        assert rc == 0 and rc2 == 0
+        print(f"case kkt solve {name}: pruned iters {it_pr.tolist()} full iters {it_full.tolist()}", flush=True)
+        assert np.all(np.abs(it_pr - it_full) <= 10)
+        for i in range(len(scenes)):
+            a, b = c_pr[i].cpu().numpy(), c_full[i].cpu().numpy()
+            assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b)
+    plan.set_config(support_columns=1)
     net.close()

@@ -320,6 +320,7 @@ def test_sparse_iterate_matches_dense_iterate(geom):
     warm = (rng.standard_normal((sc.L2, sc.L1)) + 1j * rng.standard_normal((sc.L2, sc.L1))).astype(np.complex64)
     warm[np.abs(warm) < 1.5] = 0
     warm_d = B.to_device(warm)
+    plan.set_config(support_columns=0)   # the full passes, where the option applies
     for iters in (0, 1, 2, 7, 60, 300):
         for c0 in (None, warm_d):
             outs = {}
@@ -338,6 +339,50 @@ def test_sparse_iterate_matches_dense_iterate(geom):
     plan.set_config(sparse_iterate=1)
     g = _np(plan.fista(y, P.tau, 300))
     assert abs(P.objective(g) - P.objective(ref)) / P.objective(ref) <= OBJ_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("geom", ["tiny", "ragged", "wide", "paper"])
+def test_support_columns_path_matches_full_path(geom):
+    """The pruned iteration (kept spectral columns only, identity part in the spatial
+    domain) and the full passes solve the same problem: both within tolerance of the
+    oracle, and of each other, for ISTA and FISTA, cold and warm started, at iteration
+    counts from 0 up; a plan whose support spans too many columns runs the full passes."""
+    sc = {"tiny": S.tiny_scene(7),
+          "ragged": S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(17, 1, 0)),
+          "wide": S.custom_scene(20, 6, 40, 32, 8, K=2, snr_db=20, seed=(18, 1, 0)),
+          "paper": S.paper_scale_scene(6)}[geom]
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    ncols, pruned = plan.support_columns()
+    print(f"case {geom}: support columns {ncols} of {sc.L1}, pruned={pruned}", flush=True)
+    assert pruned == ((ncols + 3) // 4 * 4 <= sc.L1 // 2)
+    y = B.to_device(sc.y)
+    # warm start as a caller would use one: an earlier, rougher solution (20 oracle FISTA
+    # iterations), perturbed on its support
+    rng = np.random.default_rng(4)
+    w = P.fista(20)
+    w = w * (1 + 0.1 * rng.standard_normal(w.shape))
+    warm = w.reshape(sc.L2, sc.L1).astype(np.complex64)
+    for iters in (0, 1, 2, 9, 150):
+        for solver in ("ista", "fista"):
+            for c0 in (None, warm):
+                res = {}
+                for sc_on in (1, 0):
+                    plan.set_config(support_columns=sc_on)
+                    fn = plan.fista if solver == "fista" else plan.ista
+                    res[sc_on] = _np(fn(y, P.tau, iters, c0=None if c0 is None else B.to_device(c0)))
+                ref = (P.fista if solver == "fista" else P.ista)(iters, c0=None if c0 is None else c0.reshape(-1))
+                nr = max(np.linalg.norm(ref), 1e-30)
+                diff = np.linalg.norm(res[1] - res[0]) / nr
+                print(f"  {solver} iters={iters} warm={c0 is not None}: |pruned - full|/|ref| = {diff:.1e}",
+                      flush=True)
+                for sc_on in (1, 0):
+                    if iters <= 9:   # short runs: the iterates themselves
+                        assert np.linalg.norm(res[sc_on] - ref) / nr <= 1e-4
+                    else:            # long runs: FP32 trajectories drift apart, the objective does not
+                        Fr = P.objective(ref)
+                        assert abs(P.objective(res[sc_on]) - Fr) / Fr <= OBJ_TOL
     plan.close()
 
 
