@@ -26,14 +26,27 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration per grid point
 
 # HBM bytes per FISTA iteration (column pass + row pass) from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs, keyed by the kernel source they were measured on.  When the
-# source changes the figure is stale and `traffic` is reported as null.
+# WRITE_SIZE runs, keyed by the kernel source they were measured on, with the
+# launch shape of that run.  When the source or the chosen shape differs the
+# figure does not apply and `traffic` is reported as null.
 TRAFFIC = {}
 
 
+def _traffic_for(kh, launch):
+    t = TRAFFIC.get(kh)
+    if not t:
+        return None
+    keys = ("row_elems", "row_rows_per_block", "col_elems", "col_cols_per_block", "support_columns",
+            "prow_elems", "prow_rows_per_block", "pcol_elems", "pcol_cols_per_block")
+    if any(t["launch"].get(k) != launch.get(k) for k in keys):
+        return None
+    return t["bytes_per_iteration"]
+
+
 def _kernel_hash() -> str:
+    """Hash of the device sources the single-scene passes are built from."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_device.h"):
+    for f in ("kernels.h", "kernels.hip", "fft_device.h", "passes.h", "passes_n.hip"):
         with open(os.path.join(ROOT, "paper_2509_13592_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -176,6 +189,7 @@ def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000):
     plan = B.Plan(mask, 256, 256)
     ys, taus = T.make_split(B, plan, 1, 0, n, mask)
     net = B.Lista(plan, layers=rec["layers"], max_batch=n)
+    net.autotune(reps=3)
     out = {}
     for name, p in (("plain", None), ("learned", params)):
         net.solve(p, ys[:64].contiguous(), taus[:64], kkt_target=target, check_every=check_every, max_iters=cap)
@@ -215,6 +229,11 @@ def main():
                     help="subsets: the single-scene solve only, the batched workloads only, a uniform "
                          "256^2 batch only (profiling), or a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
+    ap.add_argument("--launch", type=str, default=None,
+                    help="JSON plan configuration for the single-scene solve instead of autotuning "
+                         "(profiling runs pin the shape the autotuner chose)")
+    ap.add_argument("--no-tune", action="store_true", help="batch256: default launch shapes, no autotuning")
+    ap.add_argument("--batch-iters", type=int, default=20, help="batch256: FISTA iterations per solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the workloads are single-GPU by design; "
@@ -241,14 +260,15 @@ def main():
         print(json.dumps({"batched": batched_runs(args)}))
         return
     if args.only == "batch256":
-        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], 20, reps=2)
-        print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": 20, "classes": classes}))
+        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
+                                  tune=not args.no_tune)
+        print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": args.batch_iters, "classes": classes}))
         return
     sc = S.paper_scale_scene(0)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     y = B.to_device(sc.y)
     tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
-    tuned = plan.autotune(reps=50)
+    tuned = plan.set_config(**json.loads(args.launch)) if args.launch else plan.autotune(reps=50)
     out = plan.grid()
     T = args.iters
     L = sc.L1 * sc.L2
@@ -274,7 +294,7 @@ def main():
     iter_ms = col_ms + row_ms
     achieved = ALGO_BYTES_PER_POINT["fista"] * L / (iter_ms * 1e-3) / 1e9
     kh = _kernel_hash()
-    traffic = TRAFFIC.get(kh)
+    traffic = _traffic_for(kh, tuned)
 
     rec = {
         "metric": "FISTA iters/s at L=256^2 (single scene)",

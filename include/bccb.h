@@ -280,6 +280,17 @@ int lista_solve(bccb_lista_t net, const float* params, const bccb_c32* y, const 
                 double* rkkt_out);
 
 /*
+ * lista_autotune -- where the plan has a kept-column set (see
+ *   bccb_config.support_columns), time the launchable shapes of the fallback
+ *   FISTA's pruned passes over the context's whole batch capacity, `reps`
+ *   launches each, with the iterate in the sparse form most iterations see,
+ *   and keep the fastest; otherwise nothing changes.  The learned layers keep
+ *   their shapes.  Timing only: results agree to FP32 rounding.  The context's
+ *   buffers hold nothing a later call reads.
+ */
+int lista_autotune(bccb_lista_t net, int reps);
+
+/*
  * Dense "regular" baseline (Sec. II-B and the runtime comparison of Sec. III-C):
  * the explicit L x L complex64 iteration matrix, multiplied by the iterate
  * every iteration -- O(L^2) bytes and flops per iteration against the

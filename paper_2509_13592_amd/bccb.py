@@ -393,6 +393,10 @@ class Lista:
               "lista_backward")
         return grad, loss.value
 
+    def autotune(self, reps: int = 5):
+        """Tune the fallback FISTA's pruned pass shapes (where the plan has kept columns)."""
+        check(lib.lista_autotune(self._h, int(reps)), "lista_autotune")
+
     def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None, restart=False):
         """KKT-gated solve (params=None: plain FISTA from zero); restart=True restarts the
         fallback momentum instead of continuing the unrolled FISTA.  Returns (c, iters, rkkt, status)."""

@@ -405,6 +405,82 @@ int lista_backward(bccb_lista_t n, const float* params, const bccb_c32* labels, 
   return BCCB_OK;
 }
 
+int lista_autotune(bccb_lista_t n, int reps) {
+  if (!n || reps < 1) return BCCB_E_INVALID;
+  if (!n->prune) return BCCB_OK;   // the full passes keep the layers' shapes
+  hipStream_t s = n->stream;
+  bccb_plan_s* pl = n->plan;
+  const int nb = n->cap;
+  const long rows = static_cast<long>(nb) * n->L2;
+  // c_{t-1}, c_{t-2} in slot form (a few entries per row), c_t into buffer 0
+  BCCB_TRY(kern(launch_fill(n->d_xyc, rows * pl->ncs, s)));
+  BCCB_TRY(kern(launch_fill_int(n->d_pcnt[0], rows, 0, s)));
+  BCCB_TRY(kern(launch_fill_int(n->d_pcnt[1], rows, 4, s)));
+  BCCB_TRY(kern(launch_fill_int(n->d_pcnt[2], rows, 4, s)));
+  RowArgs a;
+  a.xy = n->d_xyc;
+  a.colslot = pl->d_colslot;
+  a.ncs = pl->ncs;
+  SlotBuf b[3];
+  for (int i = 0; i < 3; ++i) {
+    b[i].cnt = n->d_pcnt[i];
+    b[i].sidx = n->d_psidx[i];
+    b[i].sval = n->d_psval[i];
+  }
+  b[0].dense = n->d_R0;
+  b[1].dense = n->d_xy;
+  b[2].dense = n->d_cprev;
+  a.b0 = b[0];
+  a.b1 = b[1];
+  a.b2 = b[2];
+  a.out_c = n->d_c;
+  a.kscale = n->d_tau;
+  a.kappa = static_cast<float>(pl->mu);
+  a.beta = a.beta_prev = 0.5f;
+  a.tw = pl->d_tw1;
+  a.nrows = nb * n->L2;
+  a.rows_per_scene = n->L2;
+  ColArgs c;
+  c.xy = n->d_xyc;
+  c.sup_ptr = pl->d_sup_ptr;
+  c.sup = pl->d_sup;
+  c.sup_rhs = n->d_sup_rhs;
+  c.sup_rhs_stride = pl->nsup;
+  c.coef = n->d_coef_fista;
+  c.tw = pl->d_tw2;
+  c.L1 = n->L1;
+  c.nscenes = nb;
+  c.ncols = pl->ncs;
+  c.ldx = pl->ncs;
+  c.scol = pl->d_scol;
+  float best_r = 1e30f, best_c = 1e30f;
+  PassCfg br = n->rcfgp, bc = n->ccfgp;
+  const int Es[4] = {4, 8, 16, 32};
+  for (int E : Es) {
+    for (int k = 1; k <= 256; k *= 2) {
+      PassCfg r;
+      r.E = E;
+      r.rpb = k;
+      if (rowp_shape_ok(n->L1, r, pl->ncs)) {
+        const float ms = time_launches(s, reps, [&] { return kern(launch_row(n->L1, r, ROW_PRUNED, a, s)); });
+        if (ms < 0.f) return BCCB_E_DEVICE;
+        if (ms < best_r) { best_r = ms; br = r; }
+      }
+      PassCfg w;
+      w.E = E;
+      w.W = k;
+      if (colp_shape_ok(pl->ncs, n->L2, w)) {
+        const float ms = time_launches(s, reps, [&] { return kern(launch_col(n->L2, w, COL_PRUNED_AFFINE, c, s)); });
+        if (ms < 0.f) return BCCB_E_DEVICE;
+        if (ms < best_c) { best_c = ms; bc = w; }
+      }
+    }
+  }
+  n->rcfgp = br;
+  n->ccfgp = bc;
+  return BCCB_OK;
+}
+
 int lista_adam(float* params, const float* grad, float* m, float* v, int cnt, int step, float lr, float beta1,
                float beta2, float eps, const float* lr_scale, void* stream) {
   if (!params || !grad || !m || !v || cnt < 1 || step < 1) return BCCB_E_INVALID;

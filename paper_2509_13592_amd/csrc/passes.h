@@ -90,7 +90,7 @@ __device__ __forceinline__ void fft_inv_after_fwd(float2* v, int t, const float2
 // Number of nonzeros of a row (T threads, `mine` each) and the count before
 // thread t.  Rows of at most 64 threads sit inside one wavefront (T divides 64):
 // a segmented shuffle scan; longer rows go through LDS (`cnt`: T ints per row,
-// one barrier, reached by the whole block).
+// two barriers, reached by the whole block).
 template <int T>
 __device__ __forceinline__ void row_prefix(int mine, int t, int* cnt, int& total, int& before) {
   if constexpr (T <= 64) {
@@ -103,6 +103,7 @@ __device__ __forceinline__ void row_prefix(int mine, int t, int* cnt, int& total
     before = incl - mine;
     total = __shfl(incl, T - 1, T);
   } else {
+    __syncthreads();   // a previous call's readers are done with cnt
     cnt[t] = mine;
     __syncthreads();
     total = 0;
@@ -536,6 +537,7 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
       if (t == 0) a.b0.cnt[prow] = total > CAP ? CAP + 1 + total : total;
     }
     // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); its row DFT on the kept columns
+    int zmine = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       float2 p1;
@@ -547,12 +549,47 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
         p1 = keep_if(full1 || ((msk[idx >> 5] >> (idx & 31)) & 1u), l1);
       }
       v[e] = make_float2(v[e].x + a.beta * (v[e].x - p1.x), v[e].y + a.beta * (v[e].y - p1.y));
+      zmine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
     }
-    fft_fwd_after_inv<F>(v, t, stw, sa, sb);
-    if (active) {
+    int ztot, zbefore;
+    row_prefix<T>(zmine, t, rowcnt, ztot, zbefore);
+    // A sparse z_{t+1} (at most CAP nonzeros in every row of the block) takes the
+    // kept bins as direct sums over its nonzeros; otherwise the row FFT.  The
+    // choice is the block's, as the FFT has block-wide barriers.
+    if (__syncthreads_or(ztot > CAP)) {
+      fft_fwd_after_inv<F>(v, t, stw, sa, sb);
+      if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (ks[e] >= 0) a.xy[xrow + ks[e]] = v[e];
+        for (int e = 0; e < E; ++e)
+          if (ks[e] >= 0) a.xy[xrow + ks[e]] = v[e];
+      }
+    } else {
+      // the row's nonzeros, compact: values in A, positions in B (both free now)
+      int* zpos = reinterpret_cast<int*>(sb);
+      int o = zbefore;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (v[e].x != 0.f || v[e].y != 0.f) {
+          sa[o] = v[e];
+          zpos[o] = F::in_index(t, e);
+          ++o;
+        }
+      }
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (ks[e] >= 0) {
+            const int k = F::out_index(t, e);
+            float2 acc = make_float2(0.f, 0.f);
+            for (int q = 0; q < ztot; ++q) {
+              const float2 w = stw[(k * zpos[q]) & (N - 1)];   // e^{-j 2 pi k l / N}
+              acc = cadd(acc, cmul(sa[q], w));
+            }
+            a.xy[xrow + ks[e]] = acc;
+          }
+        }
+      }
     }
   }
 }
@@ -572,6 +609,13 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   int bid;
   if (!spread_block(a.spread, bid)) return;  // whole block exits together
 
+  // XCD-aware strip order: a GPU that deals consecutive blocks to its 8 dies in
+  // turn gives die x the blocks x, x+8, ...; they take adjacent column strips,
+  // so strips sharing a cache line are read through one L2
+  {
+    const int nb = static_cast<int>(gridDim.x);
+    if (a.spread <= 1 && (nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  }
   const int tid = threadIdx.x;
   const int nthreads = W * T;
   const int c = tid % W, t = tid / W;

@@ -207,4 +207,10 @@ def test_kkt_gated_solve():
             a, b = c_pr[i].cpu().numpy(), c_full[i].cpu().numpy()
             assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b)
     plan.set_config(support_columns=1)
+    # tuned fallback shapes: the same solutions to FP32 rounding
+    net.autotune(reps=2)
+    c_t, it_t, rk_t, rc = net.solve(None, ys, taus, kkt_target=target, check_every=10, max_iters=4000)
+    assert rc == 0 and np.all(np.abs(it_t - plain_iters) <= 10)
+    assert np.all(rk_t <= target)
+    assert B.lib.lista_autotune(net._h, 0) == B.BCCB_E_INVALID
     net.close()
