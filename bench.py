@@ -29,15 +29,25 @@ ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration p
 # WRITE_SIZE runs, keyed by the kernel source they were measured on, with the
 # launch shape of that run.  When the source or the chosen shape differs the
 # figure does not apply and `traffic` is reported as null.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/fista_passes_256_single_rocprofv3.md: FETCH (297.5 + 559.0) KiB x 2 + WRITE (512.0 + 1023.2) KiB
+    "4196b43ace20197b": {
+        "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2,
+                   "support_columns": 0, "prow_elems": 4, "prow_rows_per_block": 1, "pcol_elems": 4,
+                   "pcol_cols_per_block": 1},
+        "bytes_per_iteration": int((297.5 + 559.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
+    },
+}
 
 
 def _traffic_for(kh, launch):
     t = TRAFFIC.get(kh)
     if not t:
         return None
-    keys = ("row_elems", "row_rows_per_block", "col_elems", "col_cols_per_block", "support_columns",
-            "prow_elems", "prow_rows_per_block", "pcol_elems", "pcol_cols_per_block")
+    # the shapes of the passes the solve runs (full or pruned)
+    keys = (("support_columns", "prow_elems", "prow_rows_per_block", "pcol_elems", "pcol_cols_per_block")
+            if launch.get("support_columns") else
+            ("support_columns", "row_elems", "row_rows_per_block", "col_elems", "col_cols_per_block"))
     if any(t["launch"].get(k) != launch.get(k) for k in keys):
         return None
     return t["bytes_per_iteration"]

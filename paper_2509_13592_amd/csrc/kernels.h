@@ -223,14 +223,18 @@ struct ListaBwdColArgs {
 };
 
 struct KktRowArgs {
-  const float2* gc = nullptr;      // row-spectral G c rows
+  const float2* gc = nullptr;      // row-spectral G c rows; kept form: kept columns [rows][ncs] of
+                                   // the row spectra of scale^-1 (b - G c)
   const float2* c = nullptr;
-  const float2* b = nullptr;
+  const float2* b = nullptr;       // full form only
   const float* tau = nullptr;      // per physical scene
   double* part = nullptr;          // [physical rows] sum of e^2
   const int* scene_map = nullptr;
   const float2* tw = nullptr;
   int nrows = 0, rows_per_scene = 1;
+  const int* colslot = nullptr;    // kept form: spectral column -> kept slot (-1 = none), [N]
+  int ncs = 0;
+  float scale = 1.f;               // kept form: b - G c = scale * IDFT_rows(kept spectra)
 };
 
 // Dense iteration-matrix product (the O(L^2) baseline).

@@ -53,7 +53,9 @@ struct bccb_lista_s {
   // pruned fallback (the plan has a kept-column set): kept row spectra [cap][L2][ncs],
   // c_t over three SlotBufs whose dense grids are d_R0, d_xy and d_cprev
   bool prune = false;
+  bool kkt_pruned = false;                      // the current solve checks KKT on the kept columns
   float2* d_xyc = nullptr;
+  float2* d_xyck = nullptr;                     // kept spectra of the KKT checks [cap][L2][ncs]
   float2* d_R0 = nullptr;
   int* d_pcnt[3] = {nullptr, nullptr, nullptr};
   unsigned short* d_psidx[3] = {nullptr, nullptr, nullptr};
@@ -80,7 +82,7 @@ void lista_free(bccb_lista_s* n) {
                   n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0)})
+  for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0), static_cast<void*>(n->d_xyck)})
     if (p) (void)hipFree(p);
   for (int i = 0; i < 3; ++i)
     for (void* p : {static_cast<void*>(n->d_pcnt[i]), static_cast<void*>(n->d_psidx[i]), static_cast<void*>(n->d_psval[i])})
@@ -180,6 +182,51 @@ int run_layers(bccb_lista_s* n, const float* params, int batch, bool save) {
 
 // sum of e^2 (KKT residual terms) per physical scene of the map, into d_rk
 int kkt_sums(bccb_lista_s* n, int nact, const int* map) {
+  if (n->kkt_pruned) {
+    // b - G c on the kept spectral columns: kept row DFT of c, then the pruned
+    // column pass with -mu Omega/L and mu S (the fallback's multiplier and
+    // right-hand side), so the row kernel scales by 1/mu
+    bccb_plan_s* pl = n->plan;
+    RowArgs f;
+    f.xy = n->d_xyck;
+    f.src = n->d_c;
+    f.scene_map = map;
+    f.colslot = pl->d_colslot;
+    f.ncs = pl->ncs;
+    f.tw = pl->d_tw1;
+    f.nrows = nact * n->L2;
+    f.rows_per_scene = n->L2;
+    BCCB_TRY(kern(launch_row(n->L1, n->rcfgp, ROW_PRUNED_FWD, f, n->stream)));
+    ColArgs c;
+    c.xy = n->d_xyck;
+    c.sup_ptr = pl->d_sup_ptr;
+    c.sup = pl->d_sup;
+    c.sup_rhs = n->d_sup_rhs;
+    c.sup_rhs_stride = pl->nsup;
+    c.coef = n->d_coef_fista;
+    c.tw = pl->d_tw2;
+    c.L1 = n->L1;
+    c.nscenes = nact;
+    c.scene_map = map;
+    c.ncols = pl->ncs;
+    c.ldx = pl->ncs;
+    c.scol = pl->d_scol;
+    BCCB_TRY(kern(launch_col(n->L2, n->ccfgp, COL_PRUNED_AFFINE, c, n->stream)));
+    KktRowArgs k;
+    k.gc = n->d_xyck;
+    k.c = n->d_c;
+    k.tau = n->d_tau;
+    k.part = n->d_rows;
+    k.scene_map = map;
+    k.tw = pl->d_tw1;
+    k.nrows = nact * n->L2;
+    k.rows_per_scene = n->L2;
+    k.colslot = pl->d_colslot;
+    k.ncs = pl->ncs;
+    k.scale = static_cast<float>(1.0 / pl->mu);
+    BCCB_TRY(kern(lista_launch(n->L1, 3, &k, n->bwdE, n->bwd_rpb, 1, n->stream)));
+    return kern(rows_to_scene(n->d_rows, n->L2, nact, map, n->d_rk, n->stream));
+  }
   RowArgs f;
   f.xy = n->d_A;
   f.src = n->d_c;   // the fallback keeps a dense copy of every check's iterate here
@@ -284,6 +331,7 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
     // pruned fallback FISTA: kept row spectra, slot buffers, one more dense grid
     const size_t rows = static_cast<size_t>(max_batch) * n->L2;
     rc = dalloc(&n->d_xyc, rows * plan->ncs);
+    if (rc == BCCB_OK) rc = dalloc(&n->d_xyck, rows * plan->ncs);
     if (rc == BCCB_OK) rc = dalloc(&n->d_R0, pts);
     for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
       rc = dalloc(&n->d_pcnt[i], rows);
@@ -498,6 +546,24 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     return BCCB_E_INVALID;
   hipStream_t s = n->stream;
   BCCB_TRY(setup_rhs(n, y, tau, batch));
+  const bool sparse = n->d_sup_rhs != nullptr;
+  // the pruned passes (kept spectral columns, iterates in slot buffers) when the plan allows them
+  const bool pruned = sparse && n->prune && pruned_on(n->plan);
+  if (sparse) {
+    // mu * D_s^H y of every scene on the support bins of its spectrum
+    bccb_plan_s* p = n->plan;
+    for (int i = 0; i < batch; ++i) {
+      SupRhsDesc& d = n->h_sdesc[i];
+      d.y = reinterpret_cast<const float2*>(y) + static_cast<size_t>(i) * p->M;
+      d.entry_off = 0;
+      d.nentries = p->nsup;
+      d.rhs_off = static_cast<long>(i) * p->nsup;
+      d.scale = static_cast<float>(p->mu);
+    }
+    BCCB_HIP(hipMemcpyAsync(n->d_sdesc, n->h_sdesc, batch * sizeof(SupRhsDesc), hipMemcpyHostToDevice, s));
+    BCCB_TRY(kern(launch_sup_rhs(n->d_sdesc, batch, p->nsup, p->d_src_ptr, p->d_src, n->d_sup_rhs, n->d_flag, s)));
+  }
+  n->kkt_pruned = pruned;
   // ||b_s||^2
   BCCB_TRY(kern(scene_sums(n->d_b, nullptr, n->L, batch, n->d_sum_part, n->d_sums, s)));
   std::vector<double> bn(batch), rk(batch, 0.0), r0(batch, 0.0);
@@ -553,23 +619,6 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
   const bool carry = params && !restart;
   int done_iters = 0;
   double alpha = carry ? n->alpha_end : 1.0;
-  const bool sparse = n->d_sup_rhs != nullptr;
-  if (sparse && !act.empty() && max_iters > 0) {
-    // mu * D_s^H y of every scene on the support bins of its spectrum
-    bccb_plan_s* p = n->plan;
-    for (int i = 0; i < batch; ++i) {
-      SupRhsDesc& d = n->h_sdesc[i];
-      d.y = reinterpret_cast<const float2*>(y) + static_cast<size_t>(i) * p->M;
-      d.entry_off = 0;
-      d.nentries = p->nsup;
-      d.rhs_off = static_cast<long>(i) * p->nsup;
-      d.scale = static_cast<float>(p->mu);
-    }
-    BCCB_HIP(hipMemcpyAsync(n->d_sdesc, n->h_sdesc, batch * sizeof(SupRhsDesc), hipMemcpyHostToDevice, s));
-    BCCB_TRY(kern(launch_sup_rhs(n->d_sdesc, batch, p->nsup, p->d_src_ptr, p->d_src, n->d_sup_rhs, n->d_flag, s)));
-  }
-  // the pruned passes (kept spectral columns, iterates in slot buffers) when the plan allows them
-  const bool pruned = sparse && n->prune && pruned_on(n->plan);
   bccb_plan_s* pl = n->plan;
   auto pbuf = [&](int i) {
     SlotBuf b;
@@ -683,6 +732,7 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     }
   }
   BCCB_TRY(kern(launch_copy(reinterpret_cast<float2*>(c_out), n->d_c, static_cast<long>(batch) * n->L, s)));
+  n->kkt_pruned = false;
   const int rc = finish(n);
   if (iters_out)
     for (int i = 0; i < batch; ++i) iters_out[i] = used[i];

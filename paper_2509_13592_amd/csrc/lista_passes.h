@@ -250,9 +250,89 @@ __global__ __launch_bounds__(256) void k_kkt_row(KktRowArgs a, int rpb) {
   if (active && t == 0) a.part[prow] = acc[0];
 }
 
+// The KKT check on the kept spectral columns (sparse support): the column pass
+// leaves the kept row spectra of (b - G c) / scale; this pass expands them,
+// takes the row IDFT and forms the per-row sums of e^2 as k_kkt_row does.
+// Dynamic LDS: rpb exchange areas + N twiddles + rpb * ncs kept values + sums.
+template <int N, int E>
+__global__ __launch_bounds__(256) void k_kkt_rowp(KktRowArgs a, int rpb) {
+  using F = Stockham<N, E>;
+  constexpr int T = F::T;
+  extern __shared__ float2 lds[];
+  float2* stw = lds + rpb * fft_area(N);
+  const int ncs = a.ncs;
+  float2* lstb = stw + N;
+  double* red = reinterpret_cast<double*>(lstb + rpb * ncs);
+  const int tid = threadIdx.x;
+  const int nthreads = rpb * T;
+  const int r = tid / T, t = tid - (tid / T) * T;
+  const int row = blockIdx.x * rpb + r;
+  const bool active = row < a.nrows;
+  int scene = 0, prow = 0;
+  if (active) {
+    scene = row / a.rows_per_scene;
+    const int within = row - scene * a.rows_per_scene;
+    if (a.scene_map) scene = a.scene_map[scene];
+    prow = scene * a.rows_per_scene + within;
+  }
+  float2* sm = lds + r * fft_area(N);
+  float2* lst = lstb + r * ncs;
+  const size_t base = static_cast<size_t>(prow) * N;
+  const size_t xrow = static_cast<size_t>(prow) * ncs;
+  int ks[E];
+  float2 cc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ks[e] = a.colslot[F::out_index(t, e)];
+    cc[e] = keep_if(active, a.c[base + F::in_index(t, e)]);
+  }
+  for (int j = t; j < ncs; j += T) {
+    const float2 x = a.gc[xrow + j];   // row 0 when inactive: a valid address
+    lst[j] = keep_if(active, x);
+  }
+  for (int j = tid; j < N; j += nthreads) stw[j] = a.tw[j];
+  __syncthreads();
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = keep_if(ks[e] >= 0, lst[ks[e] >= 0 ? ks[e] : 0]);
+  F::inverse(v, t, stw, sm, 1);
+  const double tau = active ? a.tau[scene] : 0.0;
+  const double sc = a.scale;
+  double acc[1] = {0.0};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const double gr = sc * v[e].x, gi = sc * v[e].y;   // b - G c
+    const double cr = cc[e].x, ci = cc[e].y;
+    const double ac = sqrt(cr * cr + ci * ci);
+    double e2;
+    if (ac > 0.0) {
+      const double er = gr - tau * cr / ac, ei = gi - tau * ci / ac;
+      e2 = er * er + ei * ei;
+    } else {
+      const double d = fmax(sqrt(gr * gr + gi * gi) - tau, 0.0);
+      e2 = d * d;
+    }
+    acc[0] += active ? e2 : 0.0;
+  }
+  row_sum<1, T>(red, r, t, acc);
+  if (active && t == 0) a.part[prow] = acc[0];
+}
+
 template <int N, int E>
 int lista_launch_e(int which, const void* args, int rpb_or_w, int groups, hipStream_t s) {
   constexpr int T = Stockham<N, E>::T;
+  if (which == 3) {  // KKT check on the kept columns
+    const KktRowArgs& a = *static_cast<const KktRowArgs*>(args);
+    const int rpb = rpb_or_w;
+    if (rpb < 1 || rpb * T > 256 || !a.colslot || a.ncs < 1 || a.ncs > N / 2) return -1;
+    const int blocks = (a.nrows + rpb - 1) / rpb;
+    if (blocks <= 0) return 0;
+    const size_t shm = (static_cast<size_t>(rpb) * fft_area(N) + N + static_cast<size_t>(rpb) * a.ncs) * sizeof(float2) +
+                       static_cast<size_t>(rpb) * T * sizeof(double);
+    if (shm > 65536) return -1;
+    hipLaunchKernelGGL((k_kkt_rowp<N, E>), dim3(blocks), dim3(rpb * T), shm, s, a, rpb);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+  }
   if (which == 0 || which == 2) {  // row kernels
     const int rpb = rpb_or_w;
     const int nrows = which == 0 ? static_cast<const ListaBwdRowArgs*>(args)->nrows
