@@ -70,6 +70,8 @@ struct RowArgs {
   SlotBuf b0, b1, b2;
   float beta_prev = 0.f;
   float2* keep_c = nullptr;        // ROW_PRUNED, not last: also store c_t densely here (nullable)
+  // ROW_PRUNED: dscal (nullable) overrides kappa with dscal[0]; at the last iteration out_prev
+  // (nullable) receives c_{t-1} densely; out_prev is also honoured by ROW_FISTA
 };
 
 // Column pass (transforms along l2, stride L1).
@@ -88,6 +90,15 @@ enum ColMode {
   COL_SPARSE_AFFINE = 7,// xy = IDFT_cols(m . DFT_cols(xy) + r): m = a off the support, a + b Omega_j on it; r = rhs_j
   COL_SPARSE_ADMM = 8,  // m = scale/rho off the support, scale/(Omega_j + rho) on it; r = rhs_j/(Omega_j + rho)
   COL_PRUNED_AFFINE = 9,// kept columns only: m = 0 off the support, b Omega_j on it; r = rhs_j
+  COL_PRUNED_CPLX = 10, // kept columns only, entries from `dil`: m = mulc[bin] - 1/L (complex),
+                        // r = dscal[1] * inv_mu * rhs[orig] (0 for orig < 0)
+};
+
+// One bin of a dilated support list: spectral row k2, and the entry of the
+// plan's support list holding the same bin (its right-hand side), or -1.
+struct DilEntry {
+  int k2;
+  int orig;
 };
 
 // One support bin of a column: spectral row k2 and its eigenvalue.
@@ -122,6 +133,11 @@ struct ColArgs {
   int ldx = 0;
   const int* scol = nullptr;
   long scol_stride = 0;
+  // COL_PRUNED_CPLX: dilated entries of column k1 are dil[sup_ptr[k1] .. sup_ptr[k1 + 1]);
+  // the layer's multiplier grid is mulc (stride 0), dscal its {kappa, mu} pair
+  const DilEntry* dil = nullptr;
+  const float* dscal = nullptr;
+  float inv_mu = 1.f;
 };
 
 // Spectral right-hand side on the support bins, per scene:

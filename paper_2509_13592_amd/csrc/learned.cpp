@@ -61,6 +61,16 @@ struct bccb_lista_s {
   unsigned short* d_psidx[3] = {nullptr, nullptr, nullptr};
   float2* d_psval[3] = {nullptr, nullptr, nullptr};
   PassCfg rcfgp, ccfgp;
+  // pruned learned layers: Omega'_k = Omega + Delta_k (*) Omega lives on the 5x5 dilation of
+  // Omega's support; its spectral columns (ncsd, padded), per-column entries and kept spectra
+  bool prune_layers = false;
+  int ncsd = 0;
+  int* d_dscol = nullptr;
+  int* d_dcolslot = nullptr;
+  int* d_dsup_ptr = nullptr;
+  DilEntry* d_dil = nullptr;
+  float2* d_xycd = nullptr;                     // [cap][L2][ncsd]
+  PassCfg rcfgd, ccfgd;
 };
 
 namespace {
@@ -82,7 +92,9 @@ void lista_free(bccb_lista_s* n) {
                   n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0), static_cast<void*>(n->d_xyck)})
+  for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0), static_cast<void*>(n->d_xyck),
+                  static_cast<void*>(n->d_dscol), static_cast<void*>(n->d_dcolslot), static_cast<void*>(n->d_dsup_ptr),
+                  static_cast<void*>(n->d_dil), static_cast<void*>(n->d_xycd)})
     if (p) (void)hipFree(p);
   for (int i = 0; i < 3; ++i)
     for (void* p : {static_cast<void*>(n->d_pcnt[i]), static_cast<void*>(n->d_psidx[i]), static_cast<void*>(n->d_psval[i])})
@@ -176,6 +188,67 @@ int run_layers(bccb_lista_s* n, const float* params, int batch, bool save) {
       a.save_c = n->d_C + k * lay;
     }
     BCCB_TRY(row(n, ROW_FISTA, a, batch));
+  }
+  return BCCB_OK;
+}
+
+// The unrolled layers through the pruned passes (inference): the correction
+// -mu_k Omega'_k DFT2(z) + mu_k DFT2(b) lives on the dilated support, the identity
+// part in the spatial domain; c_k rotates over the fallback's slot buffers.  The
+// last layer leaves c_{K-1} in d_c and c_{K-2} in d_cprev, as run_layers does.
+int run_layers_pruned(bccb_lista_s* n, const float* params, int batch) {
+  hipStream_t s = n->stream;
+  bccb_plan_s* pl = n->plan;
+  BCCB_TRY(kern(lista_prepare(params, pl->d_omega, static_cast<float>(pl->mu), n->L1, n->L2, n->K, n->d_mulc,
+                              n->d_omp, n->d_dscal, s)));
+  const long rows = static_cast<long>(batch) * n->L2;
+  BCCB_TRY(kern(launch_fill_int(n->d_pcnt[0], rows, 0, s)));   // c_0 = 0
+  BCCB_TRY(kern(launch_fill_int(n->d_pcnt[2], rows, 0, s)));   // c_{-1} = 0
+  BCCB_TRY(kern(launch_fill(n->d_xycd, rows * n->ncsd, s)));   // DFT_rows(z_1 = 0)
+  auto buf = [&](int i) {
+    SlotBuf b;
+    b.cnt = n->d_pcnt[i];
+    b.sidx = n->d_psidx[i];
+    b.sval = n->d_psval[i];
+    b.dense = i == 0 ? n->d_R0 : (i == 1 ? n->d_xy : n->d_cprev);
+    return b;
+  };
+  for (int k = 0; k < n->K; ++k) {
+    ColArgs c;
+    c.xy = n->d_xycd;
+    c.sup_ptr = n->d_dsup_ptr;
+    c.dil = n->d_dil;
+    c.sup_rhs = n->d_sup_rhs;
+    c.sup_rhs_stride = pl->nsup;
+    c.mulc = n->d_mulc + static_cast<size_t>(k) * n->L;
+    c.dscal = n->d_dscal + 2 * k;
+    c.inv_mu = static_cast<float>(1.0 / pl->mu);
+    c.scale = static_cast<float>(1.0 / static_cast<double>(n->L));
+    c.tw = pl->d_tw2;
+    c.L1 = n->L1;
+    c.nscenes = batch;
+    c.ncols = n->ncsd;
+    c.ldx = n->ncsd;
+    c.scol = n->d_dscol;
+    BCCB_TRY(kern(launch_col(n->L2, n->ccfgd, COL_PRUNED_CPLX, c, s)));
+    RowArgs a;
+    a.xy = n->d_xycd;
+    a.colslot = n->d_dcolslot;
+    a.ncs = n->ncsd;
+    a.b0 = buf((k + 1) % 3);
+    a.b1 = buf(k % 3);
+    a.b2 = buf((k + 2) % 3);
+    a.out_c = n->d_c;
+    a.kscale = n->d_tau;
+    a.dscal = n->d_dscal + 2 * k;
+    a.beta = static_cast<float>(n->beta[k]);
+    a.beta_prev = k > 0 ? static_cast<float>(n->beta[k - 1]) : 0.f;
+    a.last = (k == n->K - 1);
+    if (a.last) a.out_prev = n->d_cprev;
+    a.tw = pl->d_tw1;
+    a.nrows = batch * n->L2;
+    a.rows_per_scene = n->L2;
+    BCCB_TRY(kern(launch_row(n->L1, n->rcfgd, ROW_PRUNED, a, s)));
   }
   return BCCB_OK;
 }
@@ -345,6 +418,59 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
     n->ccfgp.E = n->L2 >= 16 ? 16 : 8;
     n->ccfgp.W = std::min(plan->ncs, std::max(1, 256 / (n->L2 / n->ccfgp.E)));
     while (!colp_shape_ok(plan->ncs, n->L2, n->ccfgp) && n->ccfgp.W > 1) n->ccfgp.W /= 2;
+  }
+  if (rc == BCCB_OK && n->prune) {
+    // the learned layers' support: every bin within the 5x5 box of a support bin of Omega
+    const int L1 = n->L1, L2 = n->L2;
+    std::vector<int> orig(static_cast<size_t>(n->L), -2);   // -2: off, -1: dilated only, >= 0: plan entry
+    for (int k1 = 0; k1 < L1; ++k1)
+      for (int j = plan->h_sup_ptr[k1]; j < plan->h_sup_ptr[k1 + 1]; ++j) {
+        const int k2 = plan->h_sup[j].k2;
+        for (int a = -2; a <= 2; ++a)
+          for (int b = -2; b <= 2; ++b) {
+            const long bin = static_cast<long>(((k2 + a) % L2 + L2) % L2) * L1 + ((k1 + b) % L1 + L1) % L1;
+            if (orig[bin] == -2) orig[bin] = -1;
+          }
+      }
+    for (int k1 = 0; k1 < L1; ++k1)
+      for (int j = plan->h_sup_ptr[k1]; j < plan->h_sup_ptr[k1 + 1]; ++j)
+        orig[static_cast<long>(plan->h_sup[j].k2) * L1 + k1] = j;
+    std::vector<int> scol, colslot(L1, -1), sptr(L1 + 1, 0);
+    std::vector<DilEntry> dil;
+    for (int k1 = 0; k1 < L1; ++k1) {
+      sptr[k1] = static_cast<int>(dil.size());
+      for (int k2 = 0; k2 < L2; ++k2) {
+        const int o = orig[static_cast<long>(k2) * L1 + k1];
+        if (o != -2) dil.push_back(DilEntry{k2, o});
+      }
+      if (static_cast<int>(dil.size()) > sptr[k1]) {
+        colslot[k1] = static_cast<int>(scol.size());
+        scol.push_back(k1);
+      }
+    }
+    sptr[L1] = static_cast<int>(dil.size());
+    n->ncsd = (static_cast<int>(scol.size()) + 3) / 4 * 4;
+    scol.resize(n->ncsd, -1);
+    if (n->ncsd <= L1 / 2) {
+      const size_t rows = static_cast<size_t>(max_batch) * L2;
+      rc = dalloc(&n->d_dscol, scol.size());
+      if (rc == BCCB_OK) rc = dalloc(&n->d_dcolslot, L1);
+      if (rc == BCCB_OK) rc = dalloc(&n->d_dsup_ptr, sptr.size());
+      if (rc == BCCB_OK) rc = dalloc(&n->d_dil, dil.size());
+      if (rc == BCCB_OK) rc = dalloc(&n->d_xycd, rows * n->ncsd);
+      if (rc == BCCB_OK &&
+          (hipMemcpy(n->d_dscol, scol.data(), scol.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(n->d_dcolslot, colslot.data(), L1 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(n->d_dsup_ptr, sptr.data(), sptr.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+           hipMemcpy(n->d_dil, dil.data(), dil.size() * sizeof(DilEntry), hipMemcpyHostToDevice) != hipSuccess))
+        rc = BCCB_E_DEVICE;
+      n->rcfgd = n->rcfgp;
+      while (!rowp_shape_ok(L1, n->rcfgd, n->ncsd) && n->rcfgd.rpb > 1) n->rcfgd.rpb /= 2;
+      n->ccfgd = n->ccfgp;
+      n->ccfgd.W = std::min(n->ncsd, std::max(1, 256 / (L2 / n->ccfgd.E)));
+      while (!colp_shape_ok(n->ncsd, L2, n->ccfgd) && n->ccfgd.W > 1) n->ccfgd.W /= 2;
+      n->prune_layers = rc == BCCB_OK && rowp_shape_ok(L1, n->rcfgd, n->ncsd) && colp_shape_ok(n->ncsd, L2, n->ccfgd);
+    }
   }
   if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&n->h_desc), max_batch * sizeof(SceneDesc)) != hipSuccess ||
                         hipHostMalloc(reinterpret_cast<void**>(&n->h_map), max_batch * sizeof(int)) != hipSuccess ||
@@ -594,7 +720,8 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
   BCCB_TRY(kern(launch_fill(n->d_c, static_cast<long>(batch) * n->L, s)));
   BCCB_TRY(residuals(act, r0));
   if (params) {
-    BCCB_TRY(run_layers(n, params, batch, false));
+    if (pruned && n->prune_layers) BCCB_TRY(run_layers_pruned(n, params, batch));
+    else BCCB_TRY(run_layers(n, params, batch, false));
     BCCB_TRY(residuals(act, rk));
   } else {
     rk = r0;

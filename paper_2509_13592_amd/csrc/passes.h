@@ -498,7 +498,8 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
     for (int e = 0; e < E; ++e) v[e] = keep_if(ks[e] >= 0, lst[ks[e] >= 0 ? ks[e] : 0]);
 
     fft_inv<F>(v, t, stw, sa, sb, true);   // the expansions were read from A / B
-    const float kappa = a.kscale ? a.kappa * a.kscale[scene] : a.kappa;
+    const float kbase = a.dscal ? a.dscal[0] : a.kappa;
+    const float kappa = a.kscale ? kbase * a.kscale[scene] : kbase;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = shrink(make_float2(z[e].x + v[e].x, z[e].y + v[e].y), kappa);
 
@@ -506,6 +507,20 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
       if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) a.out_c[base + F::in_index(t, e)] = v[e];
+        if (a.out_prev) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            float2 p1;
+            if constexpr (kTwo) {
+              p1 = c1[e];
+            } else {
+              const int idx = F::in_index(t, e);
+              const float2 l1 = sb[idx];   // B is untouched by a single-area transform
+              p1 = keep_if(full1 || ((msk[idx >> 5] >> (idx & 31)) & 1u), l1);
+            }
+            a.out_prev[base + F::in_index(t, e)] = p1;
+          }
+        }
       }
       return;   // uniform over the grid
     }
@@ -632,10 +647,11 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   const int k1 = a.scol ? a.scol[scene * a.scol_stride + col] : col;   // spectral column
 
   constexpr bool kSparse = (MODE == COL_SPARSE_AFFINE || MODE == COL_SPARSE_ADMM || MODE == COL_PRUNED_AFFINE);
+  constexpr bool kDil = (MODE == COL_PRUNED_CPLX);
   constexpr bool kFwd = (MODE == COL_FWD || MODE == COL_FILTER_AFFINE || MODE == COL_FILTER_ADMM ||
-                         MODE == COL_FILTER_CPLX || kSparse);
+                         MODE == COL_FILTER_CPLX || kSparse || kDil);
   constexpr bool kInv = (MODE != COL_FWD);
-  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV && !kSparse);
+  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV && !kSparse && !kDil);
   constexpr bool kCplx = (MODE == COL_FILTER_CPLX);
 
   // all global loads first (iterate, spectral multiplier, twiddles)
@@ -715,6 +731,39 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
     }
   }
 
+  if constexpr (kDil) {
+    // correction only (the identity stays spatial): m = mulc - 1/L on the dilated
+    // support bins of this column, zero elsewhere; r = (mu_k / mu) (mu S) on the plan's bins
+    float2 src[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      src[e] = v[e];
+      v[e] = make_float2(0.f, 0.f);
+    }
+    const int* ptr = a.sup_ptr + (k1 >= 0 ? k1 : 0);
+    const int j0 = ptr[0], j1 = k1 >= 0 ? ptr[1] : j0;   // padding columns: no entries
+    const float rs = a.dscal[1] * a.inv_mu;
+    const float invL = a.scale;
+    const float2* rhs = a.sup_rhs + scene * a.sup_rhs_stride;
+    for (int j = j0; j < j1; ++j) {
+      const DilEntry en = a.dil[j];
+      float2 m = a.mulc[static_cast<size_t>(en.k2) * a.L1 + k1];
+      m.x -= invL;
+      float2 r = make_float2(0.f, 0.f);
+      if (en.orig >= 0) {
+        const float2 q = rhs[en.orig];
+        r = make_float2(rs * q.x, rs * q.y);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (F::out_index(t, e) == en.k2) {
+          const float2 p = cmul(src[e], m);
+          v[e] = make_float2(p.x + r.x, p.y + r.y);
+        }
+      }
+    }
+  }
+
   if constexpr (kInv) {
     if constexpr (kFwd) fft_inv_after_fwd<F>(v, t, stw, sms, sms2, W);
     else fft_inv<F>(v, t, stw, sms, sms2, false, W);
@@ -768,7 +817,8 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
   constexpr int T = Stockham<N, E>::T;
   const int ncols = a.ncols ? a.ncols : a.L1;
   if (W < 1 || W * T > 256 || ncols % W != 0) return -1;
-  if ((mode == COL_PRUNED_AFFINE) != (a.scol != nullptr)) return -1;
+  if ((mode == COL_PRUNED_AFFINE || mode == COL_PRUNED_CPLX) != (a.scol != nullptr)) return -1;
+  if (mode == COL_PRUNED_CPLX && (!a.dil || !a.dscal || !a.mulc || !a.sup_rhs)) return -1;
   const int blocks = (ncols / W) * a.nscenes;
   if (blocks <= 0) return 0;
   const size_t shm = (static_cast<size_t>(fft_areas(N, E)) * W * fft_area(N) + N) * sizeof(float2);
@@ -786,6 +836,7 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
     case COL_SPARSE_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_AFFINE>), grid, block, shm, s, a, W); break;
     case COL_SPARSE_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_ADMM>), grid, block, shm, s, a, W); break;
     case COL_PRUNED_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_AFFINE>), grid, block, shm, s, a, W); break;
+    case COL_PRUNED_CPLX: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_CPLX>), grid, block, shm, s, a, W); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;

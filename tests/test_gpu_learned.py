@@ -249,3 +249,48 @@ def test_trained_network_gain():
         assert r_ref <= 1.05 * target
     net.close()
     plan.close()
+
+
+@pytest.mark.parametrize("which", ["trained", "random"])
+def test_pruned_layers_match_full_layers(which):
+    """In the gated solve the layers run through the pruned passes (the learned filter's
+    support is the 5x5 dilation of Omega's): with no fallback iterations the solve returns
+    the layers' output, which must match lista_forward's full-pass layers to FP32 rounding;
+    with the pruning off the solve runs the full layers and matches them bit for bit."""
+    from paper_2509_13592_amd import train_lista as T
+    mask, L1, L2 = S.learned_fixed_mask(), 256, 256
+    plan = B.Plan(mask, L1, L2)
+    n = 8
+    ys, taus = T.make_split(B, plan, 1, 60000, n, mask)
+    K = 16
+    if which == "trained":
+        params, _ = T.load_params()
+    else:
+        rng = np.random.default_rng(5)
+        p = np.asarray(B.lista_init_params(K).cpu().numpy(), dtype=np.float32)
+        p[:, 0] *= rng.uniform(0.8, 1.1, K)
+        p[:, 1] *= rng.uniform(0.8, 1.2, K)
+        p[:, 2:] += 0.02 * rng.standard_normal((K, p.shape[1] - 2))
+        params = torch.tensor(p, device="cuda")
+    net = B.Lista(plan, layers=K, max_batch=n)
+    ref = net.forward(params, ys, taus).clone()
+    for sc_on in (1, 0):
+        plan.set_config(support_columns=sc_on)
+        c, it, rk, rc = net.solve(params, ys, taus, kkt_target=1e-12, check_every=10, max_iters=0)
+        compared = 0
+        for i in range(n):
+            a, b = c[i].cpu().numpy(), ref[i].cpu().numpy()
+            if not np.any(a) and np.any(b):
+                print(f"case pruned layers {which} scene {i}: output discarded by the gate", flush=True)
+                continue
+            compared += 1
+            d = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            print(f"case pruned layers {which} support_columns={sc_on} scene {i}: rel diff {d:.2e}", flush=True)
+            if sc_on:
+                assert d <= 1e-4
+            else:
+                assert np.array_equal(a, b)
+        assert compared >= n - 1
+    plan.set_config(support_columns=1)
+    net.close()
+    plan.close()
