@@ -85,6 +85,76 @@ def cpu_baseline(sc, tau, budget_s=12.0):
             "sample": f"{n} FP64 FISTA iterations on the 256x256 scene (factored D_s^H D_s, numpy)"}
 
 
+def cpu_fft_reference(B, plan, y, tau, budget_s=4.0):
+    """The paper's CPU formulation of FISTA (G x = IFFT2(Omega . FFT2(x)) with scipy.fft on all
+    host cores), in complex64 and complex128, on the same scene: context for the GPU rate."""
+    import numpy as np
+    import scipy.fft as sf
+    workers = os.cpu_count() or 1
+    om = plan.omega().astype(np.float64)
+    b = plan.adjoint(y).cpu().numpy().astype(np.complex128)
+    mu = 1.0 / om.max()
+    out = {}
+    for name, dt in (("c64", np.complex64), ("c128", np.complex128)):
+        omd = om.astype(np.float32 if dt == np.complex64 else np.float64)
+        bb = b.astype(dt)
+        kap = mu * tau
+
+        def run(n):
+            c_prev = np.zeros_like(bb)
+            z = c_prev.copy()
+            a = 1.0
+            for _ in range(n):
+                g = sf.ifft2(omd * sf.fft2(z, workers=workers), workers=workers)
+                u = z - mu * g + mu * bb
+                mag = np.abs(u)
+                c = u * np.maximum(1.0 - kap / np.maximum(mag, 1e-30), 0.0)
+                an = (1.0 + np.sqrt(1.0 + 4.0 * a * a)) / 2.0
+                z = c + ((a - 1.0) / an) * (c - c_prev)
+                c_prev, a = c, an
+            return c_prev
+        t0 = time.perf_counter()
+        run(5)
+        per = (time.perf_counter() - t0) / 5
+        n = max(5, int(budget_s / 2 / max(per, 1e-6)))
+        t0 = time.perf_counter()
+        run(n)
+        out[name] = {"iters_per_s": round(n / (time.perf_counter() - t0), 1), "iters": n}
+    out["workers"] = workers
+    out["what"] = "scipy.fft FISTA on the host (the paper's CPU formulation), same 256^2 scene"
+    return out
+
+
+def copy_ceiling(B, gib=4.0, reps=5):
+    """Achievable HBM bandwidth: the best shape of the library's streaming copy over buffers 16x the
+    Infinity Cache (loads in flight per thread x non-temporal hints x workgroups per CU)."""
+    import torch
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = (0.0, None)
+    for variant in range(64):
+        if (variant >> 3) > 4:          # up to 4096 workgroups
+            continue
+        B.stream_copy(a, b, variant)
+        e0.record()
+        for _ in range(reps):
+            B.stream_copy(a, b, variant)
+        e1.record()
+        e1.synchronize()
+        gbps = 2 * n / (e0.elapsed_time(e1) / 1e3 / reps) / 1e9
+        if gbps > best[0]:
+            best = (gbps, variant)
+    del a, b
+    torch.cuda.empty_cache()
+    v = best[1]
+    return {"GBps": round(best[0], 1), "frac_of_peak": round(best[0] / HBM_PEAK_GBS, 4), "bytes_copied": n,
+            "shape": {"loads_in_flight": 1 << (v & 3), "nontemporal": bool((v >> 2) & 1),
+                      "workgroups": 256 << (v >> 3)},
+            "what": "read + write of a 4 GiB buffer by bccb_stream_copy, best of its shapes"}
+
+
 def _batch_rate(B, scenes, iters, reps, tune=True):
     """Build plans + a batch for `scenes`, solve `reps` times; returns (seconds per solve, info)."""
     import numpy as np
@@ -345,8 +415,12 @@ def main():
         rec["large_admm"] = large_admm_run(B, S)
     if not args.no_learned:
         rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes)
+    rec["hbm_copy_ceiling"] = copy_ceiling(B)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, tau)
+        plan2 = B.Plan(sc.mask, sc.L1, sc.L2)
+        rec["cpu_fft_reference"] = cpu_fft_reference(B, plan2, y, tau)
+        plan2.close()
     print(json.dumps(rec))
 
 

@@ -60,6 +60,19 @@ enum bccb_status {
 const char* bccb_status_string(int status);
 
 /*
+ * bccb_stream_copy -- copy `bytes` (a multiple of 16) from src to dst, both
+ *   device pointers aligned to 16 bytes, with the library's streaming copy
+ *   kernel (16-byte vector loads and stores), enqueued on `stream`.  variant
+ *   (0..63) picks the kernel shape: bits 0-1 give 1, 2, 4 or 8 loads in flight
+ *   per thread, bit 2 non-temporal hints, bits 3-5 256 << k workgroups.
+ *   Not part of the method: it measures the device's achievable HBM
+ *   bandwidth, the ceiling the passes are compared with.  BCCB_E_INVALID for
+ *   null pointers, misalignment, a size that is not a multiple of 16 or a
+ *   variant outside 0..63.
+ */
+int bccb_stream_copy(const void* src, void* dst, size_t bytes, int variant, void* stream);
+
+/*
  * bccb_plan -- per-geometry setup (Sec. III-A, III-B).
  *   Builds the first column r of G (property (iv) of Sec. III-A, from the
  *   masked Kronecker sum of eq. (17)) and its eigenvalues Omega by eq. (21) in

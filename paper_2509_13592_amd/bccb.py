@@ -99,6 +99,12 @@ _SIGS = {
     "bccb_dense_destroy": (_i, [_vp]),
     "bccb_dense_apply": (_i, [_vp, _vp, _vp]),
     "lasso_solve_dense": (_i, [_vp, _i, _vp, _f, _i, _vp]),
+    "bccb_plan_support_columns": (_i, [_vp, _pi, _pi]),
+    "bccb_batch_set_sparse_iterate": (_i, [_vp, _i]),
+    "bccb_batch_set_support_columns": (_i, [_vp, _i]),
+    "bccb_batch_class_config": (_i, [_vp, _i, _pi]),
+    "lista_autotune": (_i, [_vp, _i]),
+    "bccb_stream_copy": (_i, [_vp, _vp, ctypes.c_size_t, _i, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -136,6 +142,13 @@ def _ptr(t) -> int | None:
         raise TypeError(f"expected complex64, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _raw_ptr(t) -> int:
+    """Device address of a contiguous GPU tensor of any dtype."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous GPU tensor")
     return t.data_ptr()
 
 
@@ -262,6 +275,16 @@ class Plan:
         check(lib.bccb_profile_passes(self._h, code, int(reps), ctypes.byref(col), ctypes.byref(row)),
               "bccb_profile_passes")
         return col.value, row.value
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, variant: int = 0, stream: int | None = None):
+    """Device-to-device copy through the library's streaming kernel (bandwidth ceiling)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("destination smaller than source")
+    s = current_stream() if stream is None else stream
+    check(lib.bccb_stream_copy(_vp(_raw_ptr(src)), _vp(_raw_ptr(dst)), ctypes.c_size_t(nbytes), int(variant), s),
+          "bccb_stream_copy")
 
 
 def to_device(y: np.ndarray, device="cuda") -> torch.Tensor:

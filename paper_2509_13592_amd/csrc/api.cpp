@@ -452,6 +452,13 @@ int bccb_plan_info(bccb_plan_t plan, int* M, double* mu, float* omega_host) {
   return BCCB_OK;
 }
 
+int bccb_stream_copy(const void* src, void* dst, size_t bytes, int variant, void* stream) {
+  if (!src || !dst || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(dst) % 16 != 0 || variant < 0 || variant > 63)
+    return BCCB_E_INVALID;
+  return kern(launch_stream_copy(src, dst, static_cast<long>(bytes / 16), variant, static_cast<hipStream_t>(stream)));
+}
+
 int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned) {
   if (!plan) return BCCB_E_INVALID;
   if (ncols) *ncols = plan->nscol;

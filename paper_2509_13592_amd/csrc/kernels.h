@@ -285,6 +285,7 @@ int launch_kkt(const float2* c, const float2* b, const float2* gc, float tau, lo
 int launch_absmax(const float2* b, long L, double* partial, int* nblocks, hipStream_t s);
 int launch_fill(float2* p, long n, hipStream_t s);   // zero fill (graph-safe, no memset node)
 int launch_fill_int(int* p, long n, int value, hipStream_t s);
+int launch_stream_copy(const void* src, void* dst, long n16, int variant, hipStream_t s);   // n16 16-byte vectors
 // out = (1 + beta) a - beta b over n scenes of L points selected by map (nullable = identity)
 int launch_momentum(float2* out, const float2* a, const float2* b, float beta, long L, int n, const int* map,
                     hipStream_t s);

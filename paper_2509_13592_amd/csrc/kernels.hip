@@ -184,6 +184,27 @@ __global__ void k_copy(float2* dst, const float2* src, long n) {
     dst[i] = src[i];
 }
 
+// Streaming copy in 16-byte vectors (the achievable-bandwidth ceiling of the device):
+// each thread keeps U loads in flight before storing, consecutive threads take
+// consecutive vectors, the grid strides over the rest.  NT: non-temporal hints.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void k_stream_copy(const v4f_t* __restrict__ src, v4f_t* __restrict__ dst, long n) {
+  const long stride = static_cast<long>(gridDim.x) * blockDim.x;
+  long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    v4f_t r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (NT) __builtin_nontemporal_store(r[u], dst + i + u * stride);
+      else dst[i + u * stride] = r[u];
+    }
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------
@@ -326,6 +347,31 @@ int launch_copy(float2* dst, const float2* src, long n, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) return 0;
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int launch_stream_copy(const void* src, void* dst, long n16, int variant, hipStream_t s) {
+  if (n16 <= 0) return 0;
+  // variant: bits 0-1 select 1, 2, 4 or 8 loads in flight per thread, bit 2 the non-temporal
+  // hints, bits 3-5 the workgroups per CU (1 << k)
+  const int U = 1 << (variant & 3);
+  const bool nt = (variant >> 2) & 1;
+  long blocks = static_cast<long>(256) << ((variant >> 3) & 7);
+  const long need = (n16 + 255) / 256;
+  if (blocks > need) blocks = need;
+  const dim3 g(static_cast<unsigned>(blocks)), b(256);
+  const v4f_t* sp = static_cast<const v4f_t*>(src);
+  v4f_t* dp = static_cast<v4f_t*>(dst);
+  switch (U * 2 + (nt ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_stream_copy<1, false>), g, b, 0, s, sp, dp, n16); break;
+    case 3: hipLaunchKernelGGL((k_stream_copy<1, true>), g, b, 0, s, sp, dp, n16); break;
+    case 4: hipLaunchKernelGGL((k_stream_copy<2, false>), g, b, 0, s, sp, dp, n16); break;
+    case 5: hipLaunchKernelGGL((k_stream_copy<2, true>), g, b, 0, s, sp, dp, n16); break;
+    case 8: hipLaunchKernelGGL((k_stream_copy<4, false>), g, b, 0, s, sp, dp, n16); break;
+    case 9: hipLaunchKernelGGL((k_stream_copy<4, true>), g, b, 0, s, sp, dp, n16); break;
+    case 16: hipLaunchKernelGGL((k_stream_copy<8, false>), g, b, 0, s, sp, dp, n16); break;
+    default: hipLaunchKernelGGL((k_stream_copy<8, true>), g, b, 0, s, sp, dp, n16); break;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -54,6 +54,21 @@ def test_calls_reject_null_plan():
     assert B.lib.bccb_plan_info(None, None, None, None) == B.BCCB_E_INVALID
     assert B.lib.bccb_set_stream(None, None) == B.BCCB_E_INVALID
     assert B.lib.bccb_plan_destroy(None) == B.BCCB_OK
+    assert B.lib.bccb_plan_support_columns(None, None, None) == B.BCCB_E_INVALID
+    assert B.lib.bccb_plan_get_config(None, None) == B.BCCB_E_INVALID
+    assert B.lib.bccb_plan_autotune(None, 1, None) == B.BCCB_E_INVALID
+    assert B.lib.bccb_batch_set_sparse_iterate(None, 1) == B.BCCB_E_INVALID
+    assert B.lib.bccb_batch_set_support_columns(None, 1) == B.BCCB_E_INVALID
+    assert B.lib.bccb_batch_class_config(None, 0, None) == B.BCCB_E_INVALID
+    assert B.lib.lista_autotune(None, 1) == B.BCCB_E_INVALID
+    assert B.lib.bccb_stream_copy(None, None, ctypes.c_size_t(16), 0, None) == B.BCCB_E_INVALID
+    # misaligned or ragged copies are refused before anything is enqueued
+    assert B.lib.bccb_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_size_t(16), 0, None) == \
+        B.BCCB_E_INVALID
+    assert B.lib.bccb_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_size_t(24), 0, None) == \
+        B.BCCB_E_INVALID
+    assert B.lib.bccb_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_size_t(16), 64, None) == \
+        B.BCCB_E_INVALID
 
 
 def test_binding_requires_gpu_tensors():
@@ -62,3 +77,10 @@ def test_binding_requires_gpu_tensors():
         B._ptr(torch.zeros(4, dtype=torch.complex64))
     with pytest.raises(TypeError):
         B._ptr(np.zeros(4))
+
+
+def test_every_declared_function_has_a_signature():
+    """The binding states argument types for every entry point of the header (a pointer
+    or size passed without them would be truncated to a C int)."""
+    missing = [name for name in B.declared_functions() if name not in B._SIGS]
+    assert not missing, missing

@@ -4,6 +4,8 @@ Tolerances: per Gram product rel <= 1e-4 (L2 norm); solver objectives rel <= 1e-
 against the oracle trajectory at the same iteration count.  Every comparison
 also prints the error against FP64 (eps_r = ||c_gpu - c_oracle|| / ||c_oracle||).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -414,3 +416,24 @@ def test_sparse_support_path_matches_dense_path(geom):
         a, b = res[1][k], res[0][k]
         assert np.linalg.norm(a - b) <= 1e-3 * max(np.linalg.norm(b), 1e-30)
     plan.close()
+
+
+def test_stream_copy():
+    """The bandwidth-ceiling copy moves exactly the bytes asked for."""
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    B.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    part = torch.zeros_like(src)
+    assert B.lib.bccb_stream_copy(ctypes.c_void_p(B._raw_ptr(src)), ctypes.c_void_p(B._raw_ptr(part)),
+                                  ctypes.c_size_t(4096), 13, None) == B.BCCB_OK
+    torch.cuda.synchronize()
+    assert torch.equal(part[:1024], src[:1024]) and not torch.any(part[1024:])
+    # every shape, on a size whose vector count is not a multiple of any stride
+    big = torch.randn(5 * (1 << 20) + 12, device="cuda")
+    for variant in (0, 1, 2, 3, 4, 5, 6, 7, 8, 19, 31, 37):
+        out = torch.zeros_like(big)
+        B.stream_copy(big, out, variant)
+        torch.cuda.synchronize()
+        assert torch.equal(out, big), variant
