@@ -122,10 +122,26 @@ __device__ __forceinline__ void dft_reg(float2* v) {
   }
 }
 
+// Ordering of LDS exchanges: the whole block (WAVE = false), or, when every
+// transform lives inside one wavefront, only that wavefront: its LDS operations
+// are performed in program order, so a compiler-level barrier with wavefront
+// fences suffices and the block's other waves are not held up.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Mixed-radix Stockham FFT of N points over T = N/E threads.
+// Mixed-radix Stockham FFT of N points over T = N/E threads.  WAVE: the T
+// threads of every transform sit in one wavefront (T <= 64, rows aligned).
 // ---------------------------------------------------------------------------
-template <int N, int E>
+template <int N, int E, bool WAVE = false>
 struct Stockham {
   static_assert((N & (N - 1)) == 0 && N >= 8 && N <= 1024, "N");
   static_assert((E & (E - 1)) == 0 && E >= 2 && E <= 32 && E <= N, "E");
@@ -189,7 +205,7 @@ struct Stockham {
       dft_reg<R, INV>(v + g * R);
     }
     if constexpr (S + 1 < NST) {
-      if (S > 0 || sync0) __syncthreads();
+      if (S > 0 || sync0) lds_sync<WAVE>();
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int j = t + T * g;
@@ -198,7 +214,7 @@ struct Stockham {
 #pragma unroll
         for (int r = 0; r < R; ++r) sm[px(base + r * NS) * ss] = v[g * R + r];
       }
-      __syncthreads();
+      lds_sync<WAVE>();
       stage<INV, S + 1>(v, t, tw, sm, ss);
     }
   }
@@ -254,7 +270,7 @@ struct Stockham {
     if constexpr (S + 1 < NST) {
       float2* wr = (S & 1) ? smB : smA;
       if constexpr (S == 0) {
-        if (sync0) __syncthreads();
+        if (sync0) lds_sync<WAVE>();
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -264,7 +280,7 @@ struct Stockham {
 #pragma unroll
         for (int r = 0; r < R; ++r) wr[px(base + r * NS) * ss] = v[g * R + r];
       }
-      __syncthreads();
+      lds_sync<WAVE>();
       stage2<INV, S + 1>(v, t, tw, smA, smB, ss, sync0);
     }
   }

@@ -123,7 +123,8 @@ struct SparseRow {
 
 template <int N, int E, int MODE>
 __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
-  using F = Stockham<N, E>;
+  constexpr bool kWave = (N / E) <= 64;   // a row inside one wavefront: row-local exchanges sync the wave
+  using F = Stockham<N, E, kWave>;
   constexpr int T = F::T;
   constexpr bool kSp = (MODE == ROW_FISTA_SP);
   constexpr bool kIter = (MODE == ROW_ISTA || MODE == ROW_FISTA || MODE == ROW_ADMM || kSp);
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
     // expand the slots into the row's LDS area, then read the thread's elements
 #pragma unroll
     for (int e = 0; e < E; ++e) sm[F::in_index(t, e)] = zero;
-    __syncthreads();
+    lds_sync<kWave>();
     if (rcount <= CAP) {
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         if (j < rcount) sm[sl_i[q] < N ? sl_i[q] : N - 1] = sl_v[q];
       }
     }
-    __syncthreads();
+    lds_sync<kWave>();
     if (rcount <= CAP) {
 #pragma unroll
       for (int e = 0; e < E; ++e) sp[e] = sm[F::in_index(t, e)];
@@ -374,7 +375,8 @@ __device__ __forceinline__ void load_slots(const SlotBuf& b, int prow, int t, in
 
 template <int N, int E, int MODE>
 __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
-  using F = Stockham<N, E>;
+  constexpr bool kWave = (N / E) <= 64;   // a row inside one wavefront: row-local exchanges sync the wave
+  using F = Stockham<N, E, kWave>;
   constexpr int T = F::T;
   constexpr int CAP = SparseRow<N>::CAP;
   constexpr int SPT = (CAP + T - 1) / T;
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
         atomicOr(&msk[MW + (idx >> 5)], 1u << (idx & 31));
       }
     }
-    __syncthreads();
+    lds_sync<kWave>();   // the scatter is row-local
     // z_t = c_{t-1} + beta_{t-1} (c_{t-1} - c_{t-2}) at this thread's elements
     float2 z[E];
     float2 c1[kTwo ? E : 1];   // two-area transforms overwrite B: c_{t-1} stays in registers
@@ -568,10 +570,14 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
     }
     int ztot, zbefore;
     row_prefix<T>(zmine, t, rowcnt, ztot, zbefore);
-    // A sparse z_{t+1} (at most CAP nonzeros in every row of the block) takes the
+    // A sparse z_{t+1} (at most CAP nonzeros in every row of the group) takes the
     // kept bins as direct sums over its nonzeros; otherwise the row FFT.  The
-    // choice is the block's, as the FFT has block-wide barriers.
-    if (__syncthreads_or(ztot > CAP)) {
+    // group deciding together is the wavefront when rows sync per wave, else the
+    // block (the FFT's barriers are then block-wide).
+    bool use_fft;
+    if constexpr (kWave) use_fft = __any(ztot > CAP);
+    else use_fft = __syncthreads_or(ztot > CAP);
+    if (use_fft) {
       fft_fwd_after_inv<F>(v, t, stw, sa, sb);
       if (active) {
 #pragma unroll
@@ -579,7 +585,9 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
           if (ks[e] >= 0) a.xy[xrow + ks[e]] = v[e];
       }
     } else {
-      // the row's nonzeros, compact: values in A, positions in B (both free now)
+      // the row's nonzeros, compact: values in A, positions in B (both free now:
+      // the inverse transform and the reads of B finished before the decision)
+      if constexpr (kWave) lds_sync<true>();
       int* zpos = reinterpret_cast<int*>(sb);
       int o = zbefore;
 #pragma unroll
@@ -590,7 +598,7 @@ __global__ __launch_bounds__(256) void k_rowp(RowArgs a, int rpb) {
           ++o;
         }
       }
-      __syncthreads();
+      lds_sync<kWave>();
       if (active) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
