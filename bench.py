@@ -30,27 +30,23 @@ ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration p
 # launch shape of that run.  When the source or the chosen shape differs the
 # figure does not apply and `traffic` is reported as null.
 TRAFFIC = {
-    # profiles/fista_passes_256_single_rocprofv3.md: FETCH (297.5 + 559.0) KiB x 2 + WRITE (512.0 + 1023.2) KiB
-    "4196b43ace20197b": {
-        "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2,
-                   "support_columns": 0, "prow_elems": 4, "prow_rows_per_block": 1, "pcol_elems": 4,
-                   "pcol_cols_per_block": 1},
-        "bytes_per_iteration": int((297.5 + 559.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
+    # profiles/fista_passes_256_single_rocprofv3.md (FETCH_SIZE x 2 + WRITE_SIZE, KiB per dispatch)
+    "a18ad61f0a90c6c9": {
+        "full": {"bytes_per_iteration": int((297.5 + 559.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
+                 "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2}},
+        "pruned": {"bytes_per_iteration": int((187.7 + 172.4) * 2 * 1024 + (58.2 + 64.0) * 1024),
+                   "launch": {"prow_elems": 4, "prow_rows_per_block": 2, "pcol_elems": 4, "pcol_cols_per_block": 2}},
     },
 }
 
 
 def _traffic_for(kh, launch):
-    t = TRAFFIC.get(kh)
+    """(bytes per iteration, the launch shape they were counted on) for the passes the solve runs
+    (full or pruned), or (None, None) when the device sources changed since the count."""
+    t = TRAFFIC.get(kh, {}).get("pruned" if launch.get("support_columns") else "full")
     if not t:
-        return None
-    # the shapes of the passes the solve runs (full or pruned)
-    keys = (("support_columns", "prow_elems", "prow_rows_per_block", "pcol_elems", "pcol_cols_per_block")
-            if launch.get("support_columns") else
-            ("support_columns", "row_elems", "row_rows_per_block", "col_elems", "col_cols_per_block"))
-    if any(t["launch"].get(k) != launch.get(k) for k in keys):
-        return None
-    return t["bytes_per_iteration"]
+        return None, None
+    return t["bytes_per_iteration"], t["launch"]
 
 
 def _kernel_hash() -> str:
@@ -374,7 +370,7 @@ def main():
     iter_ms = col_ms + row_ms
     achieved = ALGO_BYTES_PER_POINT["fista"] * L / (iter_ms * 1e-3) / 1e9
     kh = _kernel_hash()
-    traffic = _traffic_for(kh, tuned)
+    traffic, traffic_launch = _traffic_for(kh, tuned)
 
     rec = {
         "metric": "FISTA iters/s at L=256^2 (single scene)",
@@ -397,6 +393,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "fista iteration = column pass + row pass",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "traffic_counted_on": traffic_launch,
                      "col_pass_us": round(col_ms * 1e3, 3), "row_pass_us": round(row_ms * 1e3, 3),
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
                      "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
