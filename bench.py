@@ -121,6 +121,54 @@ def cpu_fft_reference(B, plan, y, tau, budget_s=4.0):
     return out
 
 
+def paper_sweep(B, S, reps=3):
+    """The paper's runtime comparison (Sec. III-C) on this GPU: regular (explicit L x L matrix) vs
+    fast (BCCB passes) ISTA / FISTA / ADMM at its sweep geometry, and its Table I accuracy figure
+    eps_r = |c_reg - c_fast| / |c_reg| for each solver at 50..400 iterations."""
+    import numpy as np
+    import torch
+    rows = []
+    for L1 in (64, 128, 256, 512):
+        sc = S.paper_sweep_scene(L1)
+        plan = B.Plan(sc.mask, sc.L1, sc.L2)
+        y = B.to_device(sc.y)
+        tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+        plan.autotune(50)
+        rho = float(np.count_nonzero(sc.mask))      # the Gram's diagonal; rho = 1 leaves z = 0 here
+        row = {"L1": L1, "L2": sc.L2, "L": sc.L1 * sc.L2}
+        for solver in ("ista", "fista", "admm"):
+            dense = B.Dense(plan, kind=1 if solver == "admm" else 0, rho=rho)
+            fast = (lambda n: plan.admm(y, tau, rho, n)) if solver == "admm" else \
+                   (lambda n: getattr(plan, solver)(y, tau, n))
+            rate = {}
+            for name, fn, n in (("fast", fast, 400), ("regular", lambda n: dense.solve(solver, y, tau, n), 50)):
+                fn(n)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(n)
+                torch.cuda.synchronize()
+                rate[name] = reps * n / (time.perf_counter() - t0)
+            col_ms, row_ms = plan.profile_passes(solver, 200)
+            row[solver] = {"fast_iters_per_s": round(rate["fast"], 1), "regular_iters_per_s": round(rate["regular"], 1),
+                           "speedup": round(rate["fast"] / rate["regular"], 1),
+                           "col_pass_us": round(col_ms * 1e3, 2), "row_pass_us": round(row_ms * 1e3, 2)}
+            eps = {}
+            for n in (50, 100, 200, 400):
+                a = dense.solve(solver, y, tau, n).cpu().numpy().reshape(-1)
+                b = fast(n).cpu().numpy().reshape(-1)
+                eps[n] = float(np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-30))
+            row[solver]["eps_r_reg_vs_fast"] = {str(k): float(f"{v:.3g}") for k, v in eps.items()}
+            dense.close()
+        row["launch_config"] = plan.get_config()
+        plan.close()
+        rows.append(row)
+    return {"workload": "51x16 URA, 40 elements (aperture kept), L2 = 32, K ~ U{1..10}, 15 dB; "
+                        "regular = explicit L x L complex64 matrix, fast = BCCB passes; ADMM rho = 40 "
+                        "(the number of kept elements)",
+            "rows": rows}
+
+
 def copy_ceiling(B, gib=4.0, reps=5):
     """Achievable HBM bandwidth: the best shape of the library's streaming copy over buffers 16x the
     Infinity Cache (loads in flight per thread x non-temporal hints x workgroups per CU)."""
@@ -301,7 +349,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
-    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib"], default="all",
+    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep"], default="all",
                     help="subsets: the single-scene solve only, the batched workloads only, a uniform "
                          "256^2 batch only (profiling), or a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
@@ -334,6 +382,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched": batched_runs(args)}))
+        return
+    if args.only == "sweep":
+        print(json.dumps({"paper_sweep": paper_sweep(B, S)}))
         return
     if args.only == "batch256":
         dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
@@ -413,6 +464,8 @@ def main():
     if not args.no_learned:
         rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes)
     rec["hbm_copy_ceiling"] = copy_ceiling(B)
+    if not args.no_dense:
+        rec["paper_sweep"] = paper_sweep(B, S)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, tau)
         plan2 = B.Plan(sc.mask, sc.L1, sc.L2)

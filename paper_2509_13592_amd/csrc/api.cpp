@@ -159,6 +159,10 @@ void default_config(bccb_plan_s* p) {
   int W = Tc >= 64 ? 1 : 64 / Tc;
   if (W > p->L1) W = p->L1;
   p->cfg_col.W = W;
+  // A pass of at most 32 workgroups fits one die's 32 CUs: spreading it keeps
+  // the scene in that die's L2 between passes.
+  if ((p->L2 + p->cfg_row.rpb - 1) / p->cfg_row.rpb <= 32) p->cfg_row.spread = 8;
+  if (p->L1 / W <= 32) p->cfg_col.spread = 8;
   p->cfg_rowp = p->cfg_row;
   while (!rowp_shape_ok(p->L1, p->cfg_rowp, p->ncs) && p->cfg_rowp.rpb > 1) p->cfg_rowp.rpb /= 2;
   p->cfg_colp.E = 4;

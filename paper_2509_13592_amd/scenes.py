@@ -141,6 +141,17 @@ def tiny_scene(idx: int = 0) -> Scene:
     return Scene(mask, 32, 32, y, freqs, amps, sigma2, 20.0, 1, 0, idx)
 
 
+def paper_sweep_scene(L1: int, idx: int = 0) -> Scene:
+    """The geometry of the paper's runtime sweep (Sec. III-C): a 51 x 16 URA with 40 elements
+    kept, the aperture preserved (corner elements kept), L2 = 32, L1 = the sweep value,
+    K ~ U{1..10} unit-modulus targets, 15 dB."""
+    rng = _rng(6, L1, idx)
+    mask = _random_mask(rng, 51, 16, 40, keep_corners=True)
+    K = int(rng.integers(1, 11))
+    y, freqs, amps, sigma2 = _snapshot(rng, mask, K, None, 15.0)
+    return Scene(mask, L1, 32, y, freqs, amps, sigma2, 15.0, 6, L1, idx)
+
+
 def paper_scale_scene(idx: int = 0) -> Scene:
     """16x16 URA, 64 of 256 kept, L1 = L2 = 256, K = 5, |c_k| ~ U[0.5, 1], 20 dB."""
     rng = _rng(2, 0, idx)
