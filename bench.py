@@ -41,18 +41,22 @@ TRAFFIC = {
 
 
 def _traffic_for(kh, launch):
-    """(bytes per iteration, the launch shape they were counted on) for the passes the solve runs
-    (full or pruned), or (None, None) when the device sources changed since the count."""
-    t = TRAFFIC.get(kh, {}).get("pruned" if launch.get("support_columns") else "full")
+    """(bytes per iteration, the launch shape they were counted on) for the path the solve runs
+    (cooperative, pruned or full passes), or (None, None) when the device sources changed since
+    the count or none was taken for that path."""
+    path = "resident" if launch.get("resident_groups") else ("pruned" if launch.get("support_columns") else "full")
+    t = TRAFFIC.get(kh, {}).get(path)
     if not t:
         return None, None
     return t["bytes_per_iteration"], t["launch"]
 
 
-def _kernel_hash() -> str:
-    """Hash of the device sources the single-scene passes are built from."""
+def _kernel_hash(resident: bool = False) -> str:
+    """Hash of the device sources the single-scene passes (and, with `resident`, the
+    cooperative solver) are built from."""
     h = hashlib.sha256()
-    for f in ("kernels.h", "kernels.hip", "fft_device.h", "passes.h", "passes_n.hip"):
+    for f in ("kernels.h", "kernels.hip", "fft_device.h", "passes.h", "passes_n.hip") + \
+            (("resident_api.h", "resident.h", "resident_n.hip", "resident.hip") if resident else ()):
         with open(os.path.join(ROOT, "paper_2509_13592_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -149,10 +153,13 @@ def paper_sweep(B, S, reps=3):
                     fn(n)
                 torch.cuda.synchronize()
                 rate[name] = reps * n / (time.perf_counter() - t0)
-            col_ms, row_ms = plan.profile_passes(solver, 200)
             row[solver] = {"fast_iters_per_s": round(rate["fast"], 1), "regular_iters_per_s": round(rate["regular"], 1),
-                           "speedup": round(rate["fast"] / rate["regular"], 1),
-                           "col_pass_us": round(col_ms * 1e3, 2), "row_pass_us": round(row_ms * 1e3, 2)}
+                           "speedup": round(rate["fast"] / rate["regular"], 1)}
+            if plan.get_config()["resident_groups"]:
+                row[solver]["cooperative_us_per_iteration"] = round(plan.profile_resident(solver, 400, 5) * 1e3 / 400, 2)
+            else:
+                col_ms, row_ms = plan.profile_passes(solver, 200)
+                row[solver].update({"col_pass_us": round(col_ms * 1e3, 2), "row_pass_us": round(row_ms * 1e3, 2)})
             eps = {}
             for n in (50, 100, 200, 400):
                 a = dense.solve(solver, y, tau, n).cpu().numpy().reshape(-1)
@@ -416,11 +423,21 @@ def main():
     dt_i = timed(lambda: plan.ista(y, tau, T, out=out), side_steps, 1)
     dt_a = timed(lambda: plan.admm(y, tau, 1.0, T, z_out=out), side_steps, 1)
 
-    # live per-pass durations (hipEvents on the plan's stream)
-    col_ms, row_ms = plan.profile_passes("fista", reps=500)
-    iter_ms = col_ms + row_ms
+    # live kernel durations (hipEvents on the plan's stream): the two passes of an
+    # iteration, or the cooperative launch of a whole solve when the plan runs that
+    resident = bool(tuned.get("resident_groups"))
+    if resident:
+        solve_ms = plan.profile_resident("fista", T, reps=20)
+        iter_ms = solve_ms / T
+        kernel = f"fista solve of {T} iterations as one cooperative launch (k_resident)"
+        timing = {"solve_us": round(solve_ms * 1e3, 2), "iteration_us": round(iter_ms * 1e3, 3)}
+    else:
+        col_ms, row_ms = plan.profile_passes("fista", reps=500)
+        iter_ms = col_ms + row_ms
+        kernel = "fista iteration = column pass + row pass"
+        timing = {"col_pass_us": round(col_ms * 1e3, 3), "row_pass_us": round(row_ms * 1e3, 3)}
     achieved = ALGO_BYTES_PER_POINT["fista"] * L / (iter_ms * 1e-3) / 1e9
-    kh = _kernel_hash()
+    kh = _kernel_hash(resident)
     traffic, traffic_launch = _traffic_for(kh, tuned)
 
     rec = {
@@ -441,11 +458,10 @@ def main():
                    "iters_per_step": T, "launch_config": tuned},
         "other_rates": {"ista_iters_per_s": round(side_steps * T / dt_i, 1),
                         "admm_iters_per_s": round(side_steps * T / dt_a, 1)},
-        "roofline": {"bound": "hbm", "kernel": "fista iteration = column pass + row pass",
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "traffic_counted_on": traffic_launch,
-                     "col_pass_us": round(col_ms * 1e3, 3), "row_pass_us": round(row_ms * 1e3, 3),
+                     "traffic_counted_on": traffic_launch, **timing,
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
                      "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
     }

@@ -361,6 +361,18 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   pcol_elems, pcol_cols_per_block: the pruned column pass's shape (columns
  *   per block must divide the padded kept-column count).  Ignored (and
  *   returned as set internally) when the plan has no such column set.
+ *   resident_groups: 0 = the passes above; G > 0 = ISTA, FISTA and ADMM run as
+ *   one cooperative launch of G workgroups (256 threads each) that stay resident
+ *   for the whole solve: workgroup g owns L2/G grid rows and L1/G columns, keeps
+ *   the iterate state of its rows and the spectral multiplier of its columns in
+ *   registers, and meets the others at a grid barrier between the column and
+ *   the row phase of every iteration (the same arithmetic as the passes at
+ *   E = 4).  Needs the spectral support (a mask smaller than the grid), L1 and
+ *   L2 in {32, ..., 512}, G <= 256 dividing both, L1 L2 / (1024 G) in 1..4
+ *   (workgroups of 256 threads) or L1 L2 / G = 512 (128 threads), and all
+ *   G x resident_spread workgroups co-resident; a barrier that waits longer
+ *   than one second abandons the solve and it returns BCCB_E_DEVICE.
+ *   resident_spread: 1, 2, 4 or 8 -- as row_spread, for the cooperative launch.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -378,6 +390,8 @@ typedef struct {
   int prow_rows_per_block;
   int pcol_elems;
   int pcol_cols_per_block;
+  int resident_groups;
+  int resident_spread;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */
@@ -402,6 +416,11 @@ int bccb_plan_set_config(bccb_plan_t plan, const bccb_config* cfg);
  *   it in *chosen (nullable).  Where the plan has a kept-column set (see
  *   support_columns) the pruned passes are tuned too, and support_columns is
  *   set to whichever pair is faster per iteration (when spectral_support is on).
+ *   With the spectral support on, the chosen passes and every launchable
+ *   cooperative shape (resident_groups, resident_spread) are then timed as the
+ *   iterations of a 200-iteration FISTA solve (reps / 10 solves each, at least
+ *   one; the passes replayed from their captured graph when use_graph is set)
+ *   and the fastest is kept (resident_groups = 0 for the passes).
  *   use_graph is left as it was.
  */
 int bccb_plan_autotune(bccb_plan_t plan, int reps, bccb_config* chosen);
@@ -415,6 +434,17 @@ int bccb_plan_autotune(bccb_plan_t plan, int reps, bccb_config* chosen);
  *   launch.  reps >= 1.  Used for the live roofline figures of the benchmark.
  */
 int bccb_profile_passes(bccb_plan_t plan, int solver, int reps, double* col_ms, double* row_ms);
+
+/*
+ * bccb_profile_resident -- measured duration of one cooperative solve (see
+ *   resident_groups) of `iters` iterations of `solver` (0 = ISTA, 1 = FISTA,
+ *   2 = ADMM): `reps` launches back to back on the plan's stream over the plan's
+ *   own workspace (whatever it holds; outputs are discarded), bracketed by
+ *   hipEvents; *ms = average milliseconds per launch, including the small
+ *   kernel that clears the barrier counter before each.  BCCB_E_UNSUPPORTED if
+ *   the plan's solves do not take the cooperative solver.
+ */
+int bccb_profile_resident(bccb_plan_t plan, int solver, int iters, int reps, double* ms);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,8 @@ class Config(ctypes.Structure):
                 ("row_spread", ctypes.c_int), ("col_spread", ctypes.c_int),
                 ("sparse_iterate", ctypes.c_int), ("support_columns", ctypes.c_int),
                 ("prow_elems", ctypes.c_int), ("prow_rows_per_block", ctypes.c_int),
-                ("pcol_elems", ctypes.c_int), ("pcol_cols_per_block", ctypes.c_int)]
+                ("pcol_elems", ctypes.c_int), ("pcol_cols_per_block", ctypes.c_int),
+                ("resident_groups", ctypes.c_int), ("resident_spread", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -81,6 +82,7 @@ _SIGS = {
     "lasso_solve_admm": (_i, [_vp, _vp, _f, _f, _i, _vp, _vp]),
     "bccb_objective_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd, _pd]),
     "bccb_profile_passes": (_i, [_vp, _i, _i, _pd, _pd]),
+    "bccb_profile_resident": (_i, [_vp, _i, _i, _i, _pd]),
     "bccb_plan_get_config": (_i, [_vp, _vp]),
     "bccb_plan_set_config": (_i, [_vp, _vp]),
     "bccb_plan_autotune": (_i, [_vp, _i, _vp]),
@@ -275,6 +277,14 @@ class Plan:
         check(lib.bccb_profile_passes(self._h, code, int(reps), ctypes.byref(col), ctypes.byref(row)),
               "bccb_profile_passes")
         return col.value, row.value
+
+    def profile_resident(self, solver: str, iters: int, reps: int = 20) -> float:
+        """Average ms per cooperative solve of `iters` iterations (plans whose solves take it)."""
+        code = {"ista": 0, "fista": 1, "admm": 2}[solver]
+        ms = ctypes.c_double()
+        check(lib.bccb_profile_resident(self._h, code, int(iters), int(reps), ctypes.byref(ms)),
+              "bccb_profile_resident")
+        return ms.value
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, variant: int = 0, stream: int | None = None):

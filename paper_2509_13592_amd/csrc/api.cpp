@@ -71,6 +71,8 @@ void plan_free(bccb_plan_s* p) {
     dfree(p->d_pdense[i]);
   }
   dfree(p->d_tmp);
+  dfree(p->d_beta);
+  dfree(p->d_sync);
   dfree(p->d_coef);
   dfree(p->d_red);
   dfree(p->d_flag);
@@ -148,6 +150,78 @@ bool rowp_shape_ok(int L1, const PassCfg& c, int ncs) {
 bool colp_shape_ok(int ncs, int L2, const PassCfg& c) { return ncs >= 1 && col_shape_ok(ncs, L2, c); }
 
 bool pruned_on(const bccb_plan_s* p) { return p->prune_ok && p->use_prune && p->has_support && p->use_support; }
+
+bool resident_on(const bccb_plan_s* p) { return p->resident_groups > 0 && p->has_support && p->use_support; }
+
+// The cooperative solver can run on this plan with G working workgroups, spread
+// launched per working one, for all three solvers.
+static bool resident_shape_ok(const bccb_plan_s* p, int groups, int spread) {
+  if (groups < 1 || groups > kResidentMaxGroups || !(spread == 1 || spread == 2 || spread == 4 || spread == 8))
+    return false;
+  ResidentArgs a;
+  a.groups = groups;
+  a.spread = spread;
+  for (int m = RES_ISTA; m <= RES_ADMM; ++m)
+    if (launch_resident(p->L1, p->L2, m, a, 1, nullptr) != 0) return false;
+  return true;
+}
+
+// FISTA momenta beta_t = (alpha_t - 1) / alpha_{t+1} of eqs. (10)-(12) for t = 1..iters in
+// d_beta[t - 1], computed on the host exactly as the two-pass driver does (the
+// sequence does not depend on the iteration count, so the table only grows).
+static int ensure_beta(bccb_plan_s* p, int iters) {
+  if (iters <= p->beta_cap) return BCCB_OK;
+  int cap = p->beta_cap > 0 ? p->beta_cap : 1024;
+  while (cap < iters) cap = cap > (1 << 29) ? iters : cap * 2;
+  std::vector<float> h(cap);
+  double alpha = 1.0;
+  for (int t = 0; t < cap; ++t) {
+    const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    h[t] = static_cast<float>((alpha - 1.0) / alpha_next);
+    alpha = alpha_next;
+  }
+  BCCB_HIP(hipStreamSynchronize(p->stream));
+  dfree(p->d_beta);
+  p->d_beta = nullptr;
+  p->beta_cap = 0;
+  BCCB_TRY(dmalloc(&p->d_beta, static_cast<size_t>(cap)));
+  BCCB_HIP(hipMemcpy(p->d_beta, h.data(), static_cast<size_t>(cap) * sizeof(float), hipMemcpyHostToDevice));
+  p->beta_cap = cap;
+  return BCCB_OK;
+}
+
+// Enqueue one cooperative solve on stream s (the right-hand side on the support
+// bins already in d_sup_rhs).  mode: RES_ISTA / RES_FISTA (kappa = mu tau; out_c
+// receives c^(T)) or RES_ADMM (kappa = tau / rho, scale = rho / L; out_z, out_c).
+static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, float rho, float scale,
+                            const float2* init, float2* out_c, float2* out_z, hipStream_t s) {
+  if (2 * static_cast<long long>(iters) + 1 >= (1ll << 31)) return BCCB_E_UNSUPPORTED;   // barrier epochs
+  if (mode == RES_FISTA) BCCB_TRY(ensure_beta(p, iters));
+  BCCB_TRY(kern(launch_fill_int(reinterpret_cast<int*>(p->d_sync),
+                                kResidentArriveOffset + p->resident_groups * kResidentArriveStride, 0, s)));
+  ResidentArgs a;
+  a.xy = p->d_xy;
+  a.init = init;
+  a.out_c = out_c;
+  a.out_z = out_z;
+  a.tw1 = p->d_tw1;
+  a.tw2 = p->d_tw2;
+  a.beta = p->d_beta;
+  a.coef = p->d_coef;
+  a.sup_ptr = p->d_sup_ptr;
+  a.sup = p->d_sup;
+  a.sup_rhs = p->d_sup_rhs;
+  a.kappa = kappa;
+  a.rho = rho;
+  a.scale = scale;
+  a.iters = iters;
+  a.groups = p->resident_groups;
+  a.spread = p->resident_spread;
+  a.sync = p->d_sync;
+  a.flag = p->d_flag;
+  a.timeout_ticks = p->wall_ticks_per_s;   // one second per barrier wait
+  return kern(launch_resident(p->L1, p->L2, mode, a, 0, s));
+}
 
 // Latency-oriented default: E = 4, about one wave per workgroup.
 void default_config(bccb_plan_s* p) {
@@ -250,6 +324,7 @@ int begin_call(bccb_plan_s* p) {
 int end_call(bccb_plan_s* p) {
   BCCB_HIP(hipMemcpyAsync(p->h_flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   BCCB_HIP(hipStreamSynchronize(p->stream));
+  if (*p->h_flag & 2) return BCCB_E_DEVICE;   // a grid barrier of the cooperative solver timed out
   return *p->h_flag ? BCCB_E_NONFINITE : BCCB_OK;
 }
 
@@ -395,6 +470,12 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
       rc = BCCB_E_DEVICE;
   }
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
+  if (rc == BCCB_OK) rc = dmalloc(&p->d_sync, kResidentSyncWords);
+  if (rc == BCCB_OK) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;
+    p->wall_ticks_per_s = static_cast<long long>(khz) * 1000;
+  }
   if (rc == BCCB_OK) rc = dmalloc(&p->d_red, static_cast<size_t>(kReduceBlocks) * 8);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_flag, 1);
   if (rc == BCCB_OK && hipHostMalloc(reinterpret_cast<void**>(&p->h_red), kReduceBlocks * 8 * sizeof(double)) != hipSuccess)
@@ -523,7 +604,7 @@ static SlotBuf pruned_buf(bccb_plan_s* p, int i, float2* out) {
   return b;
 }
 
-static int solve_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const float2* init, float2* out) {
+static int enqueue_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const float2* init, float2* out) {
   hipStream_t st = p->stream;
   const bool fista = (mode == ROW_FISTA);
   if (init && init != out) BCCB_TRY(kern(launch_copy(out, init, p->L, st)));
@@ -538,7 +619,7 @@ static int solve_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const 
   f.colslot = p->d_colslot;
   f.ncs = p->ncs;
   BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED_FWD, f, st));   // kept columns of DFT_rows(z_1 = c_0)
-  if (iters == 0) return end_call(p);
+  if (iters == 0) return BCCB_OK;
   const unsigned long long key[8] = {static_cast<unsigned long long>(mode), static_cast<unsigned long long>(iters),
                                      reinterpret_cast<unsigned long long>(out), fbits(kappa), 1, 0, 1, 2};
   BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
@@ -577,21 +658,18 @@ static int solve_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const 
     }
     return BCCB_OK;
   }));
-  return end_call(p);
+  return BCCB_OK;
 }
 
-// ISTA (mode ROW_ISTA) and FISTA (ROW_FISTA) share one driver.
-static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau, int iters, const bccb_c32* c0,
-                           bccb_c32* c_out) {
-  BCCB_TRY(check_solve(p, y, tau, iters, c_out));
-  float2* out = reinterpret_cast<float2*>(c_out);
-  const float2* init = reinterpret_cast<const float2*>(c0);
-  BCCB_TRY(begin_call(p));
+// The iterations of an ISTA (mode ROW_ISTA) or FISTA (ROW_FISTA) solve with
+// kappa = mu tau, the right-hand side already in place: the cooperative solver,
+// the pruned passes or the full passes, as the plan's configuration selects.
+static int enqueue_prox_grad(bccb_plan_s* p, int mode, int iters, float kappa, const float2* init, float2* out) {
   const bool sparse = sparse_on(p);
-  // mu * D_s^H y: on the support bins of the spectrum (sparse) or as a grid
-  if (sparse) BCCB_TRY(fill_sup_rhs(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu)));
-  else BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
-  if (pruned_on(p)) return solve_pruned(p, mode, iters, static_cast<float>(p->mu * tau), init, out);
+  if (resident_on(p) && iters > 0)
+    return resident_enqueue(p, mode == ROW_FISTA ? RES_FISTA : RES_ISTA, iters, kappa, 0.f, 1.f, init, out, nullptr,
+                            p->stream);
+  if (pruned_on(p)) return enqueue_pruned(p, mode, iters, kappa, init, out);
   // z^(1) = c^(0): its row DFT starts the first column pass; FISTA keeps c^(t-1) in c_out
   RowArgs f;
   f.xy = p->d_xy;
@@ -602,7 +680,6 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
     if (init && init != out) BCCB_TRY(kern(launch_copy(out, init, p->L, p->stream)));
     else if (!init) BCCB_TRY(kern(launch_fill(out, p->L, p->stream)));
   }
-  const float kappa = static_cast<float>(p->mu * tau);
   // FISTA with the iterate in per-row slots: c^(0) is read densely (all counts "dense")
   const int rmode = (mode == ROW_FISTA && p->sparse_iterate) ? ROW_FISTA_SP : mode;
   if (rmode == ROW_FISTA_SP) BCCB_TRY(kern(launch_fill_int(p->d_cnt, p->L2, p->L1 + 1, p->stream)));
@@ -633,6 +710,22 @@ static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau
       return BCCB_OK;
     }));
   }
+  return BCCB_OK;
+}
+
+
+// ISTA (mode ROW_ISTA) and FISTA (ROW_FISTA) share one driver.
+static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau, int iters, const bccb_c32* c0,
+                           bccb_c32* c_out) {
+  BCCB_TRY(check_solve(p, y, tau, iters, c_out));
+  float2* out = reinterpret_cast<float2*>(c_out);
+  const float2* init = reinterpret_cast<const float2*>(c0);
+  BCCB_TRY(begin_call(p));
+  const bool sparse = sparse_on(p);
+  // mu * D_s^H y: on the support bins of the spectrum (sparse) or as a grid
+  if (sparse) BCCB_TRY(fill_sup_rhs(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu)));
+  else BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), static_cast<float>(p->mu), p->d_rhs));
+  BCCB_TRY(enqueue_prox_grad(p, mode, iters, static_cast<float>(p->mu * tau), init, out));
   return end_call(p);
 }
 
@@ -665,6 +758,12 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
     a.xy = p->d_tmp;
     a.dst = p->d_rhs;
     BCCB_TRY(row_pass(p, ROW_INV, a));
+  }
+  if (sparse && resident_on(p) && iters > 0) {
+    BCCB_TRY(resident_enqueue(p, RES_ADMM, iters, tau / rho, rho,
+                              static_cast<float>(static_cast<double>(rho) / static_cast<double>(p->L)), nullptr, co, zo,
+                              p->stream));
+    return end_call(p);
   }
   BCCB_TRY(kern(launch_fill(p->d_state, p->L, p->stream)));  // v^(0) = 0
   BCCB_TRY(kern(launch_fill(p->d_xy, p->L, p->stream)));     // DFT_rows(z^(0) - v^(0)) = 0
@@ -760,6 +859,8 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->prow_rows_per_block = p->cfg_rowp.rpb;
   cfg->pcol_elems = p->cfg_colp.E;
   cfg->pcol_cols_per_block = p->cfg_colp.W;
+  cfg->resident_groups = p->resident_groups;
+  cfg->resident_spread = p->resident_spread;
   return BCCB_OK;
 }
 
@@ -776,6 +877,9 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   const bool spi = cfg->sparse_iterate != 0;
   if (!row_shape_ok(p->L1, r, spi) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread) ||
       (spi && p->L1 < 8))
+    return BCCB_E_INVALID;
+  if (cfg->resident_groups < 0 || (cfg->resident_groups > 0 && (!p->has_support ||
+                                     !resident_shape_ok(p, cfg->resident_groups, cfg->resident_spread))))
     return BCCB_E_INVALID;
   PassCfg rp = p->cfg_rowp, cp = p->cfg_colp;
   if (p->prune_ok) {
@@ -795,6 +899,8 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   p->use_graph = cfg->use_graph ? 1 : 0;
   p->use_support = cfg->spectral_support ? 1 : 0;
   p->sparse_iterate = spi ? 1 : 0;
+  p->resident_groups = cfg->resident_groups;
+  p->resident_spread = cfg->resident_groups > 0 ? cfg->resident_spread : 1;
   drop_graph(p);
   return BCCB_OK;
 }
@@ -890,8 +996,55 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   p->cfg_colp = bcp;
   // ISTA / FISTA take whichever pair of passes is faster per iteration
   if (pr && p->use_support) p->use_prune = (best[2] + best[3] < best[0] + best[1]) ? 1 : 0;
+  // the cooperative solver (every launchable group count and spread) against
+  // those passes, each timed as a FISTA solve of kIt iterations enqueues it
+  // (the passes replayed from their captured graph when use_graph is set)
+  if (p->has_support && p->use_support) {
+    constexpr int kIt = 200;
+    const int n = reps / 10 > 1 ? reps / 10 : 1;
+    auto solve_ms = [&]() {
+      return time_launches(st, n, [&] { return enqueue_prox_grad(p, ROW_FISTA, kIt, 1.f, nullptr, p->d_tmp); });
+    };
+    p->resident_groups = 0;
+    p->resident_spread = 1;
+    float best_ms = solve_ms();
+    if (best_ms < 0.f) return BCCB_E_DEVICE;
+    int bg = 0, bs = 1;
+    for (int G = 1; G <= kResidentMaxGroups; G *= 2) {
+      for (int sp = 1; sp <= 8; sp *= 8) {
+        if (!resident_shape_ok(p, G, sp)) continue;
+        p->resident_groups = G;
+        p->resident_spread = sp;
+        const float ms = solve_ms();
+        p->resident_groups = 0;
+        p->resident_spread = 1;
+        if (ms < 0.f) return BCCB_E_DEVICE;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bg = G;
+          bs = sp;
+        }
+      }
+    }
+    p->resident_groups = bg;
+    p->resident_spread = bs;
+  }
   drop_graph(p);
   if (chosen) return bccb_plan_get_config(p, chosen);
+  return BCCB_OK;
+}
+
+int bccb_profile_resident(bccb_plan_t p, int solver, int iters, int reps, double* ms) {
+  if (!p || reps < 1 || iters < 1 || solver < 0 || solver > 2 || !ms) return BCCB_E_INVALID;
+  if (!resident_on(p)) return BCCB_E_UNSUPPORTED;
+  const int mode = solver == 0 ? RES_ISTA : (solver == 1 ? RES_FISTA : RES_ADMM);
+  const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
+  const float m = time_launches(p->stream, reps, [&] {
+    return mode == RES_ADMM ? resident_enqueue(p, mode, iters, 1.f, 1.f, scale, nullptr, nullptr, p->d_tmp, p->stream)
+                            : resident_enqueue(p, mode, iters, 1.f, 0.f, 1.f, nullptr, p->d_tmp, nullptr, p->stream);
+  });
+  if (m < 0.f) return BCCB_E_DEVICE;
+  *ms = m;
   return BCCB_OK;
 }
 

@@ -18,10 +18,12 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libbccb.so")
 
-SOURCES = ["kernels.hip", "batch_kernels.hip", "learned_kernels.hip", "dense_kernels.hip",
+SOURCES = ["kernels.hip", "resident.hip", "batch_kernels.hip", "learned_kernels.hip", "dense_kernels.hip",
            "plan_math.cpp", "api.cpp", "batch.cpp", "learned.cpp", "dense.cpp"]
 # the pass kernels are compiled once per transform length (parallel build)
 PASS_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024]
+# the single-scene cooperative solver: row lengths (each with column lengths 32..512)
+RESIDENT_LENGTHS = [32, 64, 128, 256, 512]
 
 ARCH = os.environ.get("BCCB_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{HERE}", "-Wall", "-Wno-unused-function"]
@@ -52,6 +54,7 @@ def _compile(job) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = [(f"passes_n.hip", [f"-DPASS_N={n}"], f".{n}") for n in reversed(PASS_LENGTHS)]
+    jobs += [(f"resident_n.hip", [f"-DRES_N1={n}"], f".{n}") for n in reversed(RESIDENT_LENGTHS)]
     jobs += [(s, [], "") for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
     workers = max(1, min(int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16, len(jobs)))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:

@@ -7,6 +7,7 @@
 
 #include "bccb.h"
 #include "kernels.h"
+#include "resident_api.h"
 #include "plan_math.h"
 
 struct bccb_plan_s {
@@ -72,6 +73,16 @@ struct bccb_plan_s {
   float2* d_pdense[3] = {nullptr, nullptr, nullptr};
   bccb::PassCfg cfg_rowp, cfg_colp;
 
+  // single-scene cooperative solver (resident.h): groups > 0 turns it on for ISTA,
+  // FISTA and ADMM when the spectral support is in use; FISTA momenta beta_t in
+  // d_beta[t - 1] (capacity beta_cap); d_sync = arrival counter and abort word
+  int resident_groups = 0;
+  int resident_spread = 1;
+  float* d_beta = nullptr;
+  int beta_cap = 0;
+  unsigned* d_sync = nullptr;
+  long long wall_ticks_per_s = 0;
+
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
   int use_graph = 1;
@@ -107,6 +118,7 @@ bool col_shape_ok(int L1, int L2, const PassCfg& c);
 bool rowp_shape_ok(int L1, const PassCfg& c, int ncs);    // pruned row pass over ncs kept columns
 bool colp_shape_ok(int ncs, int L2, const PassCfg& c);    // pruned column pass over ncs columns
 bool pruned_on(const bccb_plan_s* p);
+bool resident_on(const bccb_plan_s* p);
 
 // Time `reps` launches of `launch()` on stream s with hipEvents; ms per launch, or < 0 on error.
 template <typename F>

@@ -1,0 +1,335 @@
+// Single-scene solver in one cooperative launch.
+//
+// The two-pass iteration (column pass, then row pass, see passes.h) moves the
+// row-spectral grid through memory twice per iteration and pays two kernel
+// boundaries.  For one scene of a few hundred thousand points the boundaries
+// dominate.  Here G workgroups stay resident for the whole solve: workgroup g
+// owns L2/G rows and L1/G columns of the grid, the per-row state (c^(t-1) of
+// FISTA, v of ADMM) and the per-column spectral multiplier (Omega and the
+// right-hand side on the support bins, eq. (21)) live in its registers, and
+// the phases are separated by grid barriers instead of launches.  Per
+// iteration: column phase (DFT_cols, multiply, IDFT_cols on the owned
+// columns), barrier, row phase (IDFT_rows, the proximal / momentum / ADMM
+// update of eqs. (9)-(15), DFT_rows on the owned rows), barrier.  The
+// arithmetic is that of the two-pass path at E = 4 element for element.
+//
+// The launch is cooperative (all G workgroups co-resident, or the launch
+// fails), and every barrier wait is bounded in wall-clock time: a workgroup
+// that waits too long raises the abort word and the flag, and every
+// workgroup then leaves at its next barrier.
+#pragma once
+
+#include "passes.h"
+#include "resident_api.h"
+
+namespace bccb {
+
+constexpr int kResidentElems = 4;
+
+// NT threads per workgroup: 256 (1024-point chunks, 1..4 per workgroup and
+// phase) or 128 (one 512-point chunk, for twice the workgroups).
+template <int N1, int N2, int NT_>
+struct ResidentShape {
+  static constexpr int E = kResidentElems;
+  static constexpr int NT = NT_;
+  static constexpr int T1 = N1 / E, T2 = N2 / E;
+  static constexpr int RPC = NT / T1;   // rows per chunk of the row phase
+  static constexpr int CPC = NT / T2;   // columns per chunk of the column phase
+  static constexpr int AR1 = fft_areas(N1, E), AR2 = fft_areas(N2, E);
+  static constexpr int FA1 = fft_area(N1), FA2 = fft_area(N2);
+  static constexpr int WORK = (RPC * AR1 * FA1 > CPC * AR2 * FA2) ? RPC * AR1 * FA1 : CPC * AR2 * FA2;
+  static constexpr size_t LDS_BYTES = static_cast<size_t>(N1 + N2 + WORK) * sizeof(float2);
+};
+
+// Grid barrier number k (k = 1, 2, ...).  Every wave waits for its own stores
+// to complete and the block meets; thread 0 publishes the block's stores at
+// agent scope (one L2 write-back per block rather than one per wave) and
+// writes k to the block's arrival word (its own 128-byte line: arrivals do
+// not contend on one address); the first wave then polls all G arrival words
+// at once, one per lane, until every one holds k or more (bounded in
+// wall-clock time; a timeout raises the abort word and the flag, an abort
+// raised elsewhere ends the wait), acquires for the block (its waves share
+// one CU and its L1) and the block meets again.  Returns false when the solve
+// is being abandoned.
+__device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsigned k, int* s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    unsigned* arrive = a.sync + kResidentArriveOffset;
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(arrive + static_cast<size_t>(g) * kResidentArriveStride, k, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    while (true) {
+      bool mine = true;
+      for (int i = tid; i < a.groups; i += 64)
+        mine = mine && __hip_atomic_load(arrive + static_cast<size_t>(i) * kResidentArriveStride, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) >= k;
+      if (__all(mine)) break;
+      if (__hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > a.timeout_ticks) {
+        if (tid == 0) {
+          __hip_atomic_store(a.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid == 0) *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Store of exchanged data, written through to the agent-coherent level at once
+// (an agent-scope relaxed atomic store), so the block's release before a
+// barrier finds no dirty lines of it to write back.
+__device__ __forceinline__ void store_through(float2* p, float2 v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N1, int N2, int MODE, int NT_>
+__global__ __launch_bounds__(256) void k_resident(ResidentArgs a) {
+  using S = ResidentShape<N1, N2, NT_>;
+  constexpr int E = S::E, NT = S::NT, T1 = S::T1, RPC = S::RPC, CPC = S::CPC;
+  constexpr int MAXCH = kResidentMaxChunks;
+  using FR = Stockham<N1, E, (T1 <= 64)>;   // a row inside one wavefront: row-local exchanges sync the wave
+  using FC = Stockham<N2, E>;
+  constexpr bool kFista = (MODE == RES_FISTA);
+  constexpr bool kAdmm = (MODE == RES_ADMM);
+  constexpr bool kState = kFista || kAdmm;
+  extern __shared__ float2 lds[];
+  __shared__ int s_ok;
+  float2* tw1 = lds;
+  float2* tw2 = lds + N1;
+  float2* work = tw2 + N2;
+
+  int g;
+  if (!spread_block(a.spread, g)) return;   // whole block exits together
+  const int G = a.groups;
+  const int nch = (N1 * N2) / (E * NT * G);   // chunks per phase, 1..MAXCH (checked by the launcher)
+  const int tid = threadIdx.x;
+  const int rr = tid / T1, rt = tid - (tid / T1) * T1;   // row phase: row in chunk, thread in row
+  float2* rA = work + S::AR1 * rr * S::FA1;
+  float2* rB = rA + (S::AR1 - 1) * S::FA1;
+  const int cc = tid % CPC, ct = tid / CPC;               // column phase: column in chunk, thread in column
+  float2* cA = work + cc;
+  float2* cB = cA + (S::AR2 - 1) * CPC * S::FA2;
+  const int row0 = g * (N2 / G), col0 = g * (N1 / G);
+  const float2 zero = make_float2(0.f, 0.f);
+
+  for (int j = tid; j < N1; j += NT) tw1[j] = a.tw1[j];
+  for (int j = tid; j < N2; j += NT) tw2[j] = a.tw2[j];
+
+  // Spectral multiplier of the owned columns: m off the support, its value and
+  // the right-hand side r on the support bins (as the sparse column modes).
+  float cm[MAXCH][E];
+  float2 cr[MAXCH][E];
+  {
+    float mdef;
+    float2 ab = zero;
+    if constexpr (kAdmm) {
+      mdef = a.scale / a.rho;
+    } else {
+      ab = a.coef[0];
+      mdef = ab.x;
+    }
+#pragma unroll
+    for (int ch = 0; ch < MAXCH; ++ch) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cm[ch][e] = mdef;
+        cr[ch][e] = zero;
+      }
+      if (ch < nch) {
+        const int k1 = col0 + ch * CPC + cc;
+        const int j0 = a.sup_ptr[k1], j1 = a.sup_ptr[k1 + 1];
+        for (int j = j0; j < j1; ++j) {
+          const SupEntry en = a.sup[j];
+          const float2 r = a.sup_rhs[j];
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (FC::out_index(ct, e) == en.k2) {
+              if constexpr (kAdmm) {
+                const float d = 1.f / (en.omega + a.rho);
+                cm[ch][e] = a.scale * d;
+                cr[ch][e] = make_float2(r.x * d, r.y * d);
+              } else {
+                cm[ch][e] = ab.x + ab.y * en.omega;
+                cr[ch][e] = r;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // Start: FISTA/ISTA take z^(1) = c^(0) (the warm start, or zero), ADMM z - v = 0;
+  // the owned rows' DFT_rows goes to xy.
+  float2 st[kState ? MAXCH : 1][E];
+#pragma unroll
+  for (int ch = 0; ch < MAXCH; ++ch) {
+    if (ch < nch) {
+      const size_t base = static_cast<size_t>(row0 + ch * RPC + rr) * N1;
+      float2 v[E];
+      if (!kAdmm && a.init) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = a.init[base + FR::in_index(rt, e)];
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = zero;
+      }
+      bool ok = true;
+#pragma unroll
+      for (int e = 0; e < E; ++e) ok = ok && finite2(v[e]);
+      if (!ok) __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if constexpr (kState) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) st[ch][e] = v[e];
+      }
+      __syncthreads();   // twiddles in place; the previous chunk is done with the areas
+      fft_fwd<FR>(v, rt, tw1, rA, rB, false);
+#pragma unroll
+      for (int e = 0; e < E; ++e) store_through(a.xy + base + FR::out_index(rt, e), v[e]);
+    }
+  }
+  unsigned epoch = 1;
+  if (!resident_sync(a, g, epoch, &s_ok)) return;
+
+  for (int t = 1; t <= a.iters; ++t) {
+    // column phase: DFT_cols -> multiplier -> IDFT_cols on the owned columns
+#pragma unroll
+    for (int ch = 0; ch < MAXCH; ++ch) {
+      if (ch < nch) {
+        float2* gcol = a.xy + (col0 + ch * CPC + cc);
+        float2 v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = gcol[static_cast<size_t>(FC::in_index(ct, e)) * N1];
+        __syncthreads();
+        fft_fwd<FC>(v, ct, tw2, cA, cB, false, CPC);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const float m = cm[ch][e];
+          const float2 r = cr[ch][e];
+          v[e] = make_float2(v[e].x * m + r.x, v[e].y * m + r.y);
+        }
+        fft_inv_after_fwd<FC>(v, ct, tw2, cA, cB, CPC);
+#pragma unroll
+        for (int e = 0; e < E; ++e) store_through(gcol + static_cast<size_t>(FC::in_index(ct, e)) * N1, v[e]);
+      }
+    }
+    if (!resident_sync(a, g, ++epoch, &s_ok)) return;
+
+    // row phase: IDFT_rows -> update -> DFT_rows on the owned rows
+    const bool last = (t == a.iters);
+    const float beta = kFista ? a.beta[t - 1] : 0.f;
+#pragma unroll
+    for (int ch = 0; ch < MAXCH; ++ch) {
+      if (ch < nch) {
+        const size_t base = static_cast<size_t>(row0 + ch * RPC + rr) * N1;
+        float2 v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = a.xy[base + FR::out_index(rt, e)];
+        __syncthreads();
+        fft_inv<FR>(v, rt, tw1, rA, rB);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const size_t idx = base + FR::in_index(rt, e);
+          if constexpr (MODE == RES_ISTA) {
+            const float2 c = shrink(v[e], a.kappa);
+            if (last) a.out_c[idx] = c;
+            v[e] = c;
+          } else if constexpr (kFista) {
+            const float2 c = shrink(v[e], a.kappa);
+            const float2 cp = st[ch][e];
+            st[ch][e] = c;
+            if (last) a.out_c[idx] = c;
+            v[e] = make_float2(c.x + beta * (c.x - cp.x), c.y + beta * (c.y - cp.y));
+          } else {   // ADMM: c = w + IDFT(...) with w applied spectrally, z = S(c + v), v += c - z
+            const float2 c = v[e];
+            const float2 vv = st[ch][e];
+            const float2 z = shrink(cadd(c, vv), a.kappa);
+            const float2 vn = csub(cadd(vv, c), z);
+            st[ch][e] = vn;
+            if (last) {
+              a.out_z[idx] = z;
+              if (a.out_c) a.out_c[idx] = c;
+            }
+            v[e] = csub(z, vn);
+          }
+        }
+        if (!last) {
+          fft_fwd_after_inv<FR>(v, rt, tw1, rA, rB);
+#pragma unroll
+          for (int e = 0; e < E; ++e) store_through(a.xy + base + FR::out_index(rt, e), v[e]);
+        }
+      }
+    }
+    if (!last) {
+      if (!resident_sync(a, g, ++epoch, &s_ok)) return;
+    }
+  }
+}
+
+template <int N1, int N2, int MODE, int NT>
+int resident_launch_t(const ResidentArgs& a, int check_only, hipStream_t s) {
+  using S = ResidentShape<N1, N2, NT>;
+  const int G = a.groups;
+  const long per = static_cast<long>(N1) * N2 / G;
+  if (per % (S::E * S::NT) != 0 || per / (S::E * S::NT) < 1 || per / (S::E * S::NT) > kResidentMaxChunks) return -1;
+  if (S::RPC > N2 || S::CPC > N1 || (N2 / G) % S::RPC != 0 || (N1 / G) % S::CPC != 0) return -1;
+  const int spread = a.spread > 1 ? a.spread : 1;
+  const auto kfn = k_resident<N1, N2, MODE, NT>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S::NT, S::LDS_BYTES) != hipSuccess) return -4;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -4;
+  if (static_cast<long>(per_cu) * cus < static_cast<long>(G) * spread) return -1;
+  if (check_only) return 0;
+  if (!a.xy || !a.tw1 || !a.tw2 || !a.sup_ptr || !a.sup || !a.sup_rhs || !a.sync || !a.flag || a.iters < 1) return -1;
+  if (MODE == RES_FISTA && !a.beta) return -1;
+  if (MODE != RES_ADMM && (!a.out_c || !a.coef)) return -1;
+  if (MODE == RES_ADMM && !a.out_z) return -1;
+  void* args[] = {const_cast<ResidentArgs*>(&a)};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(G * spread), dim3(S::NT), args,
+                                                  static_cast<unsigned>(S::LDS_BYTES), s);
+  return e == hipSuccess ? 0 : -4;
+}
+
+// Launch (check_only: only report whether the shape can be launched co-resident).
+// 256 threads when each group gets whole 1024-point chunks, 128 threads when it
+// gets one 512-point chunk.
+template <int N1, int N2, int MODE>
+int resident_launch_m(const ResidentArgs& a, int check_only, hipStream_t s) {
+  const int G = a.groups;
+  if (G < 1 || G > kResidentMaxGroups || N2 % G != 0 || N1 % G != 0) return -1;
+  const long per = static_cast<long>(N1) * N2 / G;
+  if (per >= 1024) return resident_launch_t<N1, N2, MODE, 256>(a, check_only, s);
+  if (per == 512) return resident_launch_t<N1, N2, MODE, 128>(a, check_only, s);
+  return -1;
+}
+
+template <int N1, int N2>
+int resident_launch_nn(int mode, const ResidentArgs& a, int check_only, hipStream_t s) {
+  switch (mode) {
+    case RES_ISTA: return resident_launch_m<N1, N2, RES_ISTA>(a, check_only, s);
+    case RES_FISTA: return resident_launch_m<N1, N2, RES_FISTA>(a, check_only, s);
+    case RES_ADMM: return resident_launch_m<N1, N2, RES_ADMM>(a, check_only, s);
+    default: return -1;
+  }
+}
+
+}  // namespace bccb

@@ -61,6 +61,7 @@ def test_calls_reject_null_plan():
     assert B.lib.bccb_batch_set_support_columns(None, 1) == B.BCCB_E_INVALID
     assert B.lib.bccb_batch_class_config(None, 0, None) == B.BCCB_E_INVALID
     assert B.lib.lista_autotune(None, 1) == B.BCCB_E_INVALID
+    assert B.lib.bccb_profile_resident(None, 1, 10, 1, ctypes.byref(d)) == B.BCCB_E_INVALID
     assert B.lib.bccb_stream_copy(None, None, ctypes.c_size_t(16), 0, None) == B.BCCB_E_INVALID
     # misaligned or ragged copies are refused before anything is enqueued
     assert B.lib.bccb_stream_copy(ctypes.c_void_p(16), ctypes.c_void_p(8), ctypes.c_size_t(16), 0, None) == \

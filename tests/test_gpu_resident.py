@@ -1,0 +1,169 @@
+"""GPU parity of the single-scene cooperative solver (one launch per solve, the
+workgroups meeting at grid barriers between the column and row phases) against
+the two-pass path and the FP64 oracle.
+
+The cooperative kernel does the arithmetic of the passes at E = 4 element for
+element, so against those passes the iterates agree to FP32 rounding of the
+compiler's contraction choices (rel <= 1e-5 over short runs); over long runs
+both are held to the oracle's objective (rel <= 1e-5).
+"""
+import numpy as np
+import pytest
+
+from oracle import bccb_oracle as O
+from paper_2509_13592_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+B = pytest.importorskip("paper_2509_13592_amd.bccb")
+
+OBJ_TOL = 1e-5
+SHORT_TOL = 1e-5
+
+GEOMS = {
+    "tiny": lambda: S.tiny_scene(3),                    # 32 x 32: a single workgroup
+    "sweep64": lambda: S.paper_sweep_scene(64, 1),      # L1 = 64, L2 = 32
+    "sweep512": lambda: S.paper_sweep_scene(512, 1),    # L1 = 512, L2 = 32
+    "rect": lambda: S.custom_scene(12, 9, 50, 128, 256, K=3, snr_db=20, seed=(21, 0, 0)),
+    "paper": lambda: S.paper_scale_scene(2),            # 256 x 256
+}
+
+
+def _np(t):
+    return t.detach().cpu().numpy().reshape(-1).astype(np.complex128)
+
+
+def _shapes(plan):
+    """Launchable (groups, spread) pairs of the cooperative solver on this plan."""
+    ok = []
+    for k in range(9):
+        for sp in (1, 8):
+            try:
+                plan.set_config(resident_groups=1 << k, resident_spread=sp)
+                ok.append((1 << k, sp))
+            except B.BCCBError:
+                pass
+    plan.set_config(resident_groups=0, resident_spread=1)
+    return ok
+
+
+def _passes(plan):
+    plan.set_config(resident_groups=0, resident_spread=1, support_columns=0, row_elems=4, row_rows_per_block=1,
+                    col_elems=4, col_cols_per_block=1)
+
+
+def _solve(plan, solver, y, tau, iters, rho, c0=None):
+    if solver == "admm":
+        z, c = plan.admm(y, tau, rho, iters, want_c=True)
+        return np.concatenate([_np(z), _np(c)])
+    fn = plan.fista if solver == "fista" else plan.ista
+    return _np(fn(y, tau, iters, c0=c0))
+
+
+@pytest.mark.parametrize("geom", list(GEOMS))
+def test_resident_matches_passes(geom):
+    sc = GEOMS[geom]()
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    shapes = _shapes(plan)
+    print(f"case {geom} L1={sc.L1} L2={sc.L2}: cooperative shapes {shapes}", flush=True)
+    assert shapes, "no launchable cooperative shape"
+    # the fewest and the most workgroups, each with and without spreading
+    Gs = sorted({shapes[0][0], shapes[-1][0]})
+    picks = [s for s in shapes if s[0] in Gs]
+    y = B.to_device(sc.y)
+    tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    rho = float(np.count_nonzero(sc.mask))
+    rng = np.random.default_rng(5)
+    for solver in ("ista", "fista", "admm"):
+        for iters in (1, 2, 37):
+            for warm in ((False, True) if solver != "admm" else (False,)):
+                c0 = None
+                if warm:
+                    _passes(plan)
+                    w = _np(plan.fista(y, tau, 15)) * (1 + 0.1 * rng.standard_normal(sc.L1 * sc.L2))
+                    c0 = B.to_device(w.reshape(sc.L2, sc.L1).astype(np.complex64))
+                _passes(plan)
+                ref = _solve(plan, solver, y, tau, iters, rho, c0)
+                nr = max(np.linalg.norm(ref), 1e-30)
+                for G, sp in picks:
+                    plan.set_config(resident_groups=G, resident_spread=sp)
+                    got = _solve(plan, solver, y, tau, iters, rho, c0)
+                    d = np.linalg.norm(got - ref) / nr
+                    print(f"  {solver} iters={iters} warm={warm} G={G} spread={sp}: rel diff {d:.1e}", flush=True)
+                    assert d <= SHORT_TOL, (solver, iters, warm, G, sp, d)
+    plan.close()
+
+
+@pytest.mark.parametrize("geom", ["tiny", "sweep512", "paper"])
+def test_resident_objective_matches_oracle(geom):
+    """Long runs through the cooperative solver against the FP64 oracle's objective."""
+    sc = GEOMS[geom]()
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    shapes = _shapes(plan)
+    G, sp = shapes[len(shapes) // 2]
+    plan.set_config(resident_groups=G, resident_spread=sp)
+    y = B.to_device(sc.y)
+    rho = float(np.count_nonzero(sc.mask))
+    iters = 300
+    for solver in ("ista", "fista", "admm"):
+        print(f"case {geom} {solver} G={G} spread={sp} iters={iters}", flush=True)
+        if solver == "admm":
+            g = _np(plan.admm(y, P.tau, rho, iters))
+            ref = P.admm(rho, iters)[0]
+        else:
+            g = _np((plan.fista if solver == "fista" else plan.ista)(y, P.tau, iters))
+            ref = (P.fista if solver == "fista" else P.ista)(iters)
+        Fr = P.objective(ref)
+        rel = abs(P.objective(g) - Fr) / Fr
+        eps = np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(f"  rel F = {rel:.2e}, eps_r = {eps:.2e}", flush=True)
+        assert rel <= OBJ_TOL
+    plan.close()
+
+
+def test_resident_rejects_nonfinite_warm_start_and_recovers():
+    sc = GEOMS["paper"]()
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    G, sp = _shapes(plan)[0]
+    plan.set_config(resident_groups=G, resident_spread=sp)
+    y = B.to_device(sc.y)
+    tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    bad = np.zeros((sc.L2, sc.L1), np.complex64)
+    bad[3, 7] = np.nan
+    print("case non-finite warm start", flush=True)
+    with pytest.raises(B.NonFiniteError):
+        plan.fista(y, tau, 5, c0=B.to_device(bad))
+    # the next solve on the same plan is unaffected
+    a = _np(plan.fista(y, tau, 20))
+    _passes(plan)
+    b = _np(plan.fista(y, tau, 20))
+    assert np.linalg.norm(a - b) <= SHORT_TOL * np.linalg.norm(b)
+    plan.close()
+
+
+def test_resident_autotune_and_profile():
+    """autotune weighs the cooperative shapes against the passes; whatever it keeps
+    solves the same problem, and the cooperative launch can be timed on its own."""
+    sc = GEOMS["paper"]()
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    cfg = plan.autotune(20)
+    print(f"case autotune: {cfg}", flush=True)
+    y = B.to_device(sc.y)
+    g = _np(plan.fista(y, P.tau, 200))
+    ref = P.fista(200)
+    assert abs(P.objective(g) - P.objective(ref)) / P.objective(ref) <= OBJ_TOL
+    G, sp = _shapes(plan)[-1]
+    plan.set_config(resident_groups=G, resident_spread=sp)
+    for solver in ("ista", "fista", "admm"):
+        ms = plan.profile_resident(solver, 100, reps=3)
+        print(f"  {solver}: {ms * 1e3 / 100:.2f} us per iteration (G={G}, spread={sp})", flush=True)
+        assert ms > 0
+    plan.set_config(resident_groups=0)
+    with pytest.raises(B.BCCBError):
+        plan.profile_resident("fista", 10, reps=1)
+    plan.close()
