@@ -372,6 +372,15 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   (workgroups of 256 threads) or L1 L2 / G = 512 (128 threads), and all
  *   G x resident_spread workgroups co-resident; a barrier that waits longer
  *   than one second abandons the solve and it returns BCCB_E_DEVICE.
+ *   With support_columns in effect as well, ISTA and FISTA run the pruned
+ *   cooperative form when it fits: only the kept spectral columns of the row
+ *   spectra are exchanged, every group rebuilds DFT2 of the iterate on the
+ *   support bins from all of them as direct sums, and an iteration takes one
+ *   grid barrier; it has 1024 / L1 rows per group (L2 L1 / 1024 groups, the
+ *   value of resident_groups then only switching it on) and needs the kept
+ *   row spectra of all rows, the twiddles and the support tables in 64 KB of
+ *   LDS (16 kept columns of 256 rows at the paper-scale geometry).  ADMM keeps
+ *   the full cooperative form with resident_groups groups.
  *   resident_spread: 1, 2, 4 or 8 -- as row_spread, for the cooperative launch.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
@@ -402,7 +411,8 @@ int bccb_plan_get_config(bccb_plan_t plan, bccb_config* cfg);
  *   holding support bins of Omega (Sec. III-A, eq. (21)); *pruned (nullable):
  *   1 if ISTA / FISTA solves on this plan take the pruned passes under the
  *   current configuration (support_columns and spectral_support set, the
- *   columns few enough), else 0.
+ *   columns few enough), 2 if they take the pruned form of the cooperative
+ *   solver (resident_groups set as well, and that form launchable), else 0.
  */
 int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned);
 

@@ -259,11 +259,12 @@ class Plan:
         check(lib.bccb_plan_set_config(self._h, ctypes.byref(c)), "bccb_plan_set_config")
         return self.get_config()
 
-    def support_columns(self) -> tuple[int, bool]:
-        """(spectral columns holding support bins, whether ISTA/FISTA take the pruned passes)."""
+    def support_columns(self) -> tuple[int, int]:
+        """(spectral columns holding support bins, how ISTA/FISTA use them: 0 = full passes or
+        the full cooperative form, 1 = the pruned passes, 2 = the pruned cooperative form)."""
         n, pr = ctypes.c_int(), ctypes.c_int()
         check(lib.bccb_plan_support_columns(self._h, ctypes.byref(n), ctypes.byref(pr)), "bccb_plan_support_columns")
-        return n.value, bool(pr.value)
+        return n.value, pr.value
 
     def autotune(self, reps: int = 50) -> dict:
         c = Config()

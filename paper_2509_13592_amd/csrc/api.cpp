@@ -73,6 +73,7 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_tmp);
   dfree(p->d_beta);
   dfree(p->d_sync);
+  dfree(p->d_rpart);
   dfree(p->d_coef);
   dfree(p->d_red);
   dfree(p->d_flag);
@@ -166,6 +167,30 @@ static bool resident_shape_ok(const bccb_plan_s* p, int groups, int spread) {
   return true;
 }
 
+// Groups of the pruned cooperative form: rows of 1024 / L1 per 256-thread group.
+static int resident_pruned_groups(const bccb_plan_s* p) {
+  const int rpc = 1024 / p->L1;
+  return rpc >= 1 && p->L2 % rpc == 0 ? p->L2 / rpc : 0;
+}
+
+// ISTA / FISTA take the pruned cooperative form: the solves take the pruned
+// passes otherwise (pruned_on) and that form can be launched with the plan's
+// spread (cached per spread: the check queries the occupancy API).
+static bool resident_pruned_on(bccb_plan_s* p) {
+  if (!pruned_on(p) || !p->d_rpart) return false;
+  if (p->res_pruned_spread != p->resident_spread) {
+    ResidentArgs a;
+    a.groups = resident_pruned_groups(p);
+    a.spread = p->resident_spread;
+    a.ncs = p->ncs;
+    a.nsup = p->nsup;
+    p->res_pruned_ok = a.groups > 0 && launch_resident(p->L1, p->L2, RES_PRUNED_FISTA, a, 1, nullptr) == 0 &&
+                       launch_resident(p->L1, p->L2, RES_PRUNED_ISTA, a, 1, nullptr) == 0;
+    p->res_pruned_spread = p->resident_spread;
+  }
+  return p->res_pruned_ok;
+}
+
 // FISTA momenta beta_t = (alpha_t - 1) / alpha_{t+1} of eqs. (10)-(12) for t = 1..iters in
 // d_beta[t - 1], computed on the host exactly as the two-pass driver does (the
 // sequence does not depend on the iteration count, so the table only grows).
@@ -192,15 +217,23 @@ static int ensure_beta(bccb_plan_s* p, int iters) {
 
 // Enqueue one cooperative solve on stream s (the right-hand side on the support
 // bins already in d_sup_rhs).  mode: RES_ISTA / RES_FISTA (kappa = mu tau; out_c
-// receives c^(T)) or RES_ADMM (kappa = tau / rho, scale = rho / L; out_z, out_c).
+// receives c^(T); the pruned form when the plan takes it) or RES_ADMM (kappa =
+// tau / rho, scale = rho / L; out_z, out_c).
 static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, float rho, float scale,
                             const float2* init, float2* out_c, float2* out_z, hipStream_t s) {
   if (2 * static_cast<long long>(iters) + 1 >= (1ll << 31)) return BCCB_E_UNSUPPORTED;   // barrier epochs
-  if (mode == RES_FISTA) BCCB_TRY(ensure_beta(p, iters));
-  BCCB_TRY(kern(launch_fill_int(reinterpret_cast<int*>(p->d_sync),
-                                kResidentArriveOffset + p->resident_groups * kResidentArriveStride, 0, s)));
+  const bool pruned = mode != RES_ADMM && resident_pruned_on(p);
+  if (pruned) mode = (mode == RES_FISTA) ? RES_PRUNED_FISTA : RES_PRUNED_ISTA;
+  const int groups = pruned ? resident_pruned_groups(p) : p->resident_groups;
+  if (mode == RES_FISTA || mode == RES_PRUNED_FISTA) BCCB_TRY(ensure_beta(p, iters));
+  BCCB_TRY(kern(launch_fill_int(reinterpret_cast<int*>(p->d_sync), kResidentArriveOffset + groups * kResidentArriveStride,
+                                0, s)));
   ResidentArgs a;
-  a.xy = p->d_xy;
+  a.xy = pruned ? p->d_rpart : p->d_xy;
+  a.scol = p->d_scol;
+  a.colslot = p->d_colslot;
+  a.ncs = p->ncs;
+  a.nsup = p->nsup;
   a.init = init;
   a.out_c = out_c;
   a.out_z = out_z;
@@ -215,7 +248,7 @@ static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, fl
   a.rho = rho;
   a.scale = scale;
   a.iters = iters;
-  a.groups = p->resident_groups;
+  a.groups = groups;
   a.spread = p->resident_spread;
   a.sync = p->d_sync;
   a.flag = p->d_flag;
@@ -471,6 +504,9 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   }
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_sync, kResidentSyncWords);
+  // the pruned cooperative form's per-group parts of DFT2 at the support bins
+  if (rc == BCCB_OK && p->prune_ok && resident_pruned_groups(p) > 0)
+    rc = dmalloc(&p->d_rpart, static_cast<size_t>(resident_pruned_groups(p)) * p->nsup);
   if (rc == BCCB_OK) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;
@@ -547,7 +583,7 @@ int bccb_stream_copy(const void* src, void* dst, size_t bytes, int variant, void
 int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned) {
   if (!plan) return BCCB_E_INVALID;
   if (ncols) *ncols = plan->nscol;
-  if (pruned) *pruned = pruned_on(plan) ? 1 : 0;
+  if (pruned) *pruned = pruned_on(plan) ? (resident_on(plan) && resident_pruned_on(plan) ? 2 : 1) : 0;
   return BCCB_OK;
 }
 
@@ -1005,29 +1041,58 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
     auto solve_ms = [&]() {
       return time_launches(st, n, [&] { return enqueue_prox_grad(p, ROW_FISTA, kIt, 1.f, nullptr, p->d_tmp); });
     };
-    p->resident_groups = 0;
-    p->resident_spread = 1;
+    const int pass_prune = p->use_prune;
+    auto restore = [&]() {
+      p->resident_groups = 0;
+      p->resident_spread = 1;
+      p->use_prune = pass_prune;
+    };
+    restore();
     float best_ms = solve_ms();
     if (best_ms < 0.f) return BCCB_E_DEVICE;
-    int bg = 0, bs = 1;
+    int bg = 0, bs = 1, bprune = pass_prune;
+    // per spread: the fastest full cooperative group count (ADMM runs that form)
+    float full_ms[9];
+    int full_g[9];
+    for (int i = 0; i < 9; ++i) {
+      full_ms[i] = 1e30f;
+      full_g[i] = 0;
+    }
+    bool pruned_done[9] = {false, false, false, false, false, false, false, false, false};
     for (int G = 1; G <= kResidentMaxGroups; G *= 2) {
       for (int sp = 1; sp <= 8; sp *= 8) {
         if (!resident_shape_ok(p, G, sp)) continue;
-        p->resident_groups = G;
-        p->resident_spread = sp;
-        const float ms = solve_ms();
-        p->resident_groups = 0;
-        p->resident_spread = 1;
-        if (ms < 0.f) return BCCB_E_DEVICE;
-        if (ms < best_ms) {
-          best_ms = ms;
-          bg = G;
-          bs = sp;
+        for (int pz = 0; pz <= (pr ? 1 : 0); ++pz) {
+          if (pz == 1 && pruned_done[sp]) continue;   // the pruned form's groups do not depend on G
+          p->resident_groups = G;
+          p->resident_spread = sp;
+          p->use_prune = pz;
+          if (pz == 1) {
+            pruned_done[sp] = true;
+            if (!resident_pruned_on(p)) {
+              restore();
+              continue;
+            }
+          }
+          const float ms = solve_ms();
+          restore();
+          if (ms < 0.f) return BCCB_E_DEVICE;
+          if (pz == 0 && ms < full_ms[sp]) {
+            full_ms[sp] = ms;
+            full_g[sp] = G;
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            bg = G;
+            bs = sp;
+            bprune = pz;
+          }
         }
       }
     }
-    p->resident_groups = bg;
-    p->resident_spread = bs;
+    p->resident_groups = bg > 0 ? (full_g[bs] > 0 ? full_g[bs] : bg) : 0;
+    p->resident_spread = bg > 0 ? bs : 1;
+    p->use_prune = bprune;
   }
   drop_graph(p);
   if (chosen) return bccb_plan_get_config(p, chosen);

@@ -82,6 +82,9 @@ struct bccb_plan_s {
   int beta_cap = 0;
   unsigned* d_sync = nullptr;
   long long wall_ticks_per_s = 0;
+  float2* d_rpart = nullptr;       // pruned form: [groups][nsup] per-group parts of DFT2 at the bins
+  int res_pruned_spread = -1;      // spread the cached pruned-form check was made for
+  bool res_pruned_ok = false;
 
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)

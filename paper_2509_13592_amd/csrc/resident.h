@@ -322,12 +322,242 @@ int resident_launch_m(const ResidentArgs& a, int check_only, hipStream_t s) {
   return -1;
 }
 
+// ---------------------------------------------------------------------------
+// Pruned form (ISTA / FISTA).  By eq. (21) Omega and DFT2(b) vanish off the
+// support bins, so (I - mu G) z + mu b = z + IDFT2(V) with V = m . DFT2(z) + r
+// living on the support (m = -mu Omega / L, r = mu S, as the pruned column
+// pass).  Group g owns RPC = 1024 / L1 rows (G = L2 / RPC groups of 256
+// threads) with z_t and c_{t-1} in registers.  DFT2(z_t) at a support bin
+// (k1, k2) is a sum over the rows of DFT_rows(z_t)[l2][k1] e^{-j 2 pi k2 l2 / L2};
+// each group publishes the part of that sum over its own rows for every bin
+// (nsup values), and after the one grid barrier of an iteration every group
+// adds the G parts of every bin in a fixed order.  An iteration:
+//   Z_j = sum over groups of the parts; V_j = m_j Z_j + r_j;
+//   the owned rows' kept spectra of IDFT2(V): sums over the bins of each kept
+//   column with the rows' twiddles (a table built once); IDFT_rows of them
+//   (zero off the kept columns); u = z_t + that; c_t = S_kappa(u);
+//   z_{t+1} = c_t + beta_t (c_t - c_{t-1}); DFT_rows(z_{t+1}) at the kept
+//   columns; this group's parts of DFT2(z_{t+1}) at the bins -> xy; barrier.
+// The column transforms of the passes become these sums, so the results agree
+// with the pruned passes to FP32 rounding, not element for element.
+// ---------------------------------------------------------------------------
+template <int N1, int N2>
+struct ResidentPrunedShape {
+  static constexpr int E = kResidentElems;
+  static constexpr int NT = 256;
+  static constexpr int T1 = N1 / E;
+  static constexpr int RPC = NT / T1;   // rows per group
+  static constexpr int AR1 = fft_areas(N1, E), FA1 = fft_area(N1);
+  // dynamic LDS in bytes for ncs kept columns and nsup support bins
+  static constexpr size_t lds_bytes(int ncs, int nsup) {
+    return sizeof(float2) * (static_cast<size_t>(N1) + static_cast<size_t>(RPC) * AR1 * FA1 +
+                             static_cast<size_t>(RPC) * nsup + static_cast<size_t>(RPC) * ncs + 2 * static_cast<size_t>(nsup)) +
+           sizeof(float) * nsup + sizeof(int) * (static_cast<size_t>(nsup) + 2 * static_cast<size_t>(ncs));
+  }
+};
+
+// Threads adding up the parts of one bin: a power of two, at most 16, with
+// every bin of a pass over the block covered.
+__host__ __device__ constexpr int resident_part_lanes(int nsup, int nt) {
+  int q = 1;
+  while (q < 16 && 2 * q * nsup <= nt) q *= 2;
+  return q;
+}
+
+template <int N1, int N2, int MODE>
+__global__ __launch_bounds__(256) void k_resident_pruned(ResidentArgs a) {
+  using S = ResidentPrunedShape<N1, N2>;
+  constexpr int E = S::E, NT = S::NT, T1 = S::T1, RPC = S::RPC;
+  using FR = Stockham<N1, E, (T1 <= 64)>;
+  constexpr bool kFista = (MODE == RES_PRUNED_FISTA);
+  constexpr int PB = 16;   // parts loaded per thread and batch
+  extern __shared__ float2 lds[];
+  __shared__ int s_ok;
+  const int ncs = a.ncs, nsup = a.nsup, G = a.groups;
+  float2* tw1 = lds;
+  float2* area = tw1 + N1;                              // RPC rows x AR1 exchange areas
+  float2* cw = area + RPC * S::AR1 * S::FA1;            // [RPC][nsup] e^{+j 2 pi k2_j l2 / L2}, owned rows
+  float2* xk = cw + RPC * nsup;                         // [RPC][ncs] owned rows' kept forward spectra
+  float2* vs = xk + RPC * ncs;                          // [nsup] V_j
+  float2* br = vs + nsup;                               // [nsup] r_j
+  float* bm = reinterpret_cast<float*>(br + nsup);      // [nsup] m_j
+  int* bslot = reinterpret_cast<int*>(bm + nsup);       // [nsup] kept slot of bin j
+  int* sbeg = bslot + nsup;                             // [ncs] bins of slot s: sbeg[s] .. send[s]
+  int* send = sbeg + ncs;
+
+  int g;
+  if (!spread_block(a.spread, g)) return;   // whole block exits together
+  const int tid = threadIdx.x;
+  const int rr = tid / T1, rt = tid - (tid / T1) * T1;
+  const int row = g * RPC + rr;
+  float2* rA = area + S::AR1 * rr * S::FA1;
+  float2* rB = rA + (S::AR1 - 1) * S::FA1;
+  const size_t base = static_cast<size_t>(row) * N1;
+  const float2 zero = make_float2(0.f, 0.f);
+  float2* part = a.xy;   // [G][nsup] parts of DFT2(z) at the bins, one row block per group
+
+  for (int j = tid; j < N1; j += NT) tw1[j] = a.tw1[j];
+  {
+    const float cb = a.coef[0].y;   // -mu / L
+    for (int s2 = tid; s2 < ncs; s2 += NT) {
+      const int k1 = a.scol[s2];
+      const int j0 = k1 >= 0 ? a.sup_ptr[k1] : 0, j1 = k1 >= 0 ? a.sup_ptr[k1 + 1] : 0;
+      sbeg[s2] = j0;
+      send[s2] = j1;
+      for (int j = j0; j < j1; ++j) {
+        const SupEntry en = a.sup[j];
+        bslot[j] = s2;
+        bm[j] = cb * en.omega;
+        br[j] = a.sup_rhs[j];
+        for (int r2 = 0; r2 < RPC; ++r2) {
+          const float2 w = a.tw2[(en.k2 * (g * RPC + r2)) & (N2 - 1)];
+          cw[r2 * nsup + j] = make_float2(w.x, -w.y);
+        }
+      }
+    }
+  }
+  int myslot[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) myslot[e] = a.colslot[FR::out_index(rt, e)];
+
+  // this group's parts of DFT2(v) at the bins, from the kept forward row spectra
+  // v[] of its rows (forward-output layout); the block meets inside
+  auto publish = [&](const float2* v) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (myslot[e] >= 0) xk[rr * ncs + myslot[e]] = v[e];
+    __syncthreads();
+    for (int j = tid; j < nsup; j += NT) {
+      const int sl = bslot[j];
+      float2 acc = zero;
+      for (int r2 = 0; r2 < RPC; ++r2) {
+        const float2 x = xk[r2 * ncs + sl];
+        const float2 w = cw[r2 * nsup + j];   // conj: forward
+        acc = make_float2(acc.x + x.x * w.x + x.y * w.y, acc.y + x.y * w.x - x.x * w.y);
+      }
+      store_through(part + static_cast<size_t>(g) * nsup + j, acc);
+    }
+  };
+
+  // z_1 = c_0 (warm start or zero), c_{-1} = c_0 as the passes take it
+  float2 z[E], cp[E];
+  {
+    float2 v[E];
+    if (a.init) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = a.init[base + FR::in_index(rt, e)];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = zero;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ok = ok && finite2(v[e]);
+      z[e] = v[e];
+      cp[e] = v[e];
+    }
+    if (!ok) __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();   // twiddles and bin tables in place
+    fft_fwd<FR>(v, rt, tw1, rA, rB, false);
+    publish(v);
+  }
+  unsigned epoch = 1;
+  if (!resident_sync(a, g, epoch, &s_ok)) return;
+
+  const int Q = resident_part_lanes(nsup, NT);
+  const float kappa = a.kappa;
+  for (int t = 1; t <= a.iters; ++t) {
+    const float beta = kFista ? a.beta[t - 1] : 0.f;
+    // Z_j: the G parts of every bin, Q threads per bin (adjacent lanes), each
+    // over the groups q, q + Q, ... in order, then a fixed butterfly
+    for (int j0 = 0; j0 < nsup; j0 += NT / Q) {
+      const int j = j0 + tid / Q, q = tid % Q;
+      const int jj = j < nsup ? j : nsup - 1;
+      float2 acc = zero;
+      for (int g0 = q; g0 < G; g0 += PB * Q) {
+        float2 pv[PB];
+#pragma unroll
+        for (int k = 0; k < PB; ++k) {
+          const int gg = g0 + k * Q;
+          pv[k] = keep_if(gg < G, part[static_cast<size_t>(gg < G ? gg : 0) * nsup + jj]);
+        }
+#pragma unroll
+        for (int k = 0; k < PB; ++k) acc = cadd(acc, pv[k]);
+      }
+      for (int off = 1; off < Q; off <<= 1) {
+        const float ox = __shfl_xor(acc.x, off, 64), oy = __shfl_xor(acc.y, off, 64);
+        acc = (q & off) ? make_float2(ox + acc.x, oy + acc.y) : make_float2(acc.x + ox, acc.y + oy);
+      }
+      if (q == 0 && j < nsup) vs[j] = make_float2(acc.x * bm[j] + br[j].x, acc.y * bm[j] + br[j].y);
+    }
+    __syncthreads();
+    // the owned rows' kept spectra of IDFT2(V) at this thread's positions
+    const bool last = (t == a.iters);
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      float2 acc = zero;
+      if (myslot[e] >= 0) {
+        const int s2 = myslot[e];
+        for (int j = sbeg[s2]; j < send[s2]; ++j) acc = cadd(acc, cmul(vs[j], cw[rr * nsup + j]));
+      }
+      v[e] = acc;
+    }
+    fft_inv<FR>(v, rt, tw1, rA, rB);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const float2 u = cadd(z[e], v[e]);
+      const float2 c = shrink(u, kappa);
+      if (last) a.out_c[base + FR::in_index(rt, e)] = c;
+      const float2 zn = kFista ? make_float2(c.x + beta * (c.x - cp[e].x), c.y + beta * (c.y - cp[e].y)) : c;
+      cp[e] = c;
+      z[e] = zn;
+      v[e] = zn;
+    }
+    if (last) break;
+    fft_fwd_after_inv<FR>(v, rt, tw1, rA, rB);
+    publish(v);
+    if (!resident_sync(a, g, ++epoch, &s_ok)) return;
+  }
+}
+
+template <int N1, int N2, int MODE>
+int resident_launch_p(const ResidentArgs& a, int check_only, hipStream_t s) {
+  using S = ResidentPrunedShape<N1, N2>;
+  if (S::RPC < 1 || S::RPC > N2 || N2 % S::RPC != 0) return -1;
+  const int G = N2 / S::RPC;
+  if (a.groups != G || G > kResidentMaxGroups) return -1;
+  if (a.ncs < 1 || a.ncs > N1 / 2 || a.nsup < 1) return -1;
+  const size_t shm = S::lds_bytes(a.ncs, a.nsup);
+  if (shm > 65536) return -1;
+  const int spread = a.spread > 1 ? a.spread : 1;
+  const auto kfn = k_resident_pruned<N1, N2, MODE>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S::NT, shm) != hipSuccess) return -4;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -4;
+  if (static_cast<long>(per_cu) * cus < static_cast<long>(G) * spread) return -1;
+  if (check_only) return 0;
+  if (!a.xy || !a.tw1 || !a.tw2 || !a.sup_ptr || !a.sup || !a.sup_rhs || !a.sync || !a.flag || !a.scol ||
+      !a.colslot || !a.coef || !a.out_c || a.iters < 1)
+    return -1;
+  if (MODE == RES_PRUNED_FISTA && !a.beta) return -1;
+  void* args[] = {const_cast<ResidentArgs*>(&a)};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(G * spread), dim3(S::NT), args,
+                                                  static_cast<unsigned>(shm), s);
+  return e == hipSuccess ? 0 : -4;
+}
+
 template <int N1, int N2>
 int resident_launch_nn(int mode, const ResidentArgs& a, int check_only, hipStream_t s) {
   switch (mode) {
     case RES_ISTA: return resident_launch_m<N1, N2, RES_ISTA>(a, check_only, s);
     case RES_FISTA: return resident_launch_m<N1, N2, RES_FISTA>(a, check_only, s);
     case RES_ADMM: return resident_launch_m<N1, N2, RES_ADMM>(a, check_only, s);
+    case RES_PRUNED_ISTA: return resident_launch_p<N1, N2, RES_PRUNED_ISTA>(a, check_only, s);
+    case RES_PRUNED_FISTA: return resident_launch_p<N1, N2, RES_PRUNED_FISTA>(a, check_only, s);
     default: return -1;
   }
 }

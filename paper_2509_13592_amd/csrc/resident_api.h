@@ -9,7 +9,17 @@ namespace bccb {
 // One cooperative launch runs a whole ISTA, FISTA or ADMM solve of one scene:
 // G workgroups own L2/G rows and L1/G columns each and meet at grid barriers
 // between the column and the row phase of every iteration.
-enum ResidentMode { RES_ISTA = 0, RES_FISTA = 1, RES_ADMM = 2 };
+enum ResidentMode {
+  RES_ISTA = 0,
+  RES_FISTA = 1,
+  RES_ADMM = 2,
+  // pruned forms (ISTA / FISTA): only the kept spectral columns of the row
+  // spectra cross between groups, and every group rebuilds the spectrum on the
+  // support bins from all of them, so an iteration needs one grid barrier
+  RES_PRUNED_ISTA = 3,
+  RES_PRUNED_FISTA = 4,
+};
+
 constexpr int kResidentMaxChunks = 4;   // 1024-point chunks per workgroup and phase (256 threads)
 constexpr int kResidentMaxGroups = 256;
 constexpr int kResidentArriveOffset = 32;   // sync words: [0] abort, then one arrival word per group
@@ -35,6 +45,13 @@ struct ResidentArgs {
   unsigned* sync = nullptr;         // [kResidentSyncWords]: abort word, arrival words; zero at launch
   int* flag = nullptr;              // |= 1: non-finite warm start; |= 2: a barrier wait timed out
   long long timeout_ticks = 0;      // wall-clock ticks one barrier wait may take
+  // pruned forms: xy holds [G][nsup] per-group parts of DFT2 of the iterate at the support
+  // bins; scol[s] = spectral column of slot s (-1 = padding), colslot[k1] = slot of
+  // column k1 (-1 = not kept); nsup = entries of sup
+  const int* scol = nullptr;
+  const int* colslot = nullptr;
+  int ncs = 0;
+  int nsup = 0;
 };
 
 // Returns 0, -1 (shape or arguments not launchable, or not co-resident), -2 (size

@@ -167,3 +167,57 @@ def test_resident_autotune_and_profile():
     with pytest.raises(B.BCCBError):
         plan.profile_resident("fista", 10, reps=1)
     plan.close()
+
+
+@pytest.mark.parametrize("geom", ["tiny", "sweep512", "rect", "paper"])
+def test_resident_pruned_matches_passes(geom):
+    """The pruned cooperative form (kept spectral columns exchanged, the support-bin
+    spectrum rebuilt by every group as direct sums, one barrier per iteration) against
+    the pruned and the full passes, cold and warm started, and the oracle's objective
+    over a long run."""
+    sc = GEOMS[geom]()
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    shapes = _shapes(plan)
+    G, sp = shapes[0]
+    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+    ncols, mode = plan.support_columns()
+    print(f"case {geom}: kept columns {ncols}, support-column mode {mode}", flush=True)
+    if mode != 2:
+        plan.close()
+        pytest.skip("the pruned cooperative form does not fit this geometry")
+    y = B.to_device(sc.y)
+    tau = P.tau
+    rng = np.random.default_rng(6)
+    w = P.fista(15) * (1 + 0.1 * rng.standard_normal(sc.L1 * sc.L2))
+    warm = B.to_device(w.reshape(sc.L2, sc.L1).astype(np.complex64))
+    for solver in ("ista", "fista"):
+        fn = plan.fista if solver == "fista" else plan.ista
+        for iters in (1, 2, 37):
+            for c0 in (None, warm):
+                plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+                got = _np(fn(y, tau, iters, c0=c0))
+                plan.set_config(resident_groups=0, support_columns=1)
+                ref_p = _np(fn(y, tau, iters, c0=c0))
+                plan.set_config(resident_groups=0, support_columns=0)
+                ref_f = _np(fn(y, tau, iters, c0=c0))
+                nr = max(np.linalg.norm(ref_f), 1e-30)
+                dp = np.linalg.norm(got - ref_p) / nr
+                df = np.linalg.norm(got - ref_f) / nr
+                print(f"  {solver} iters={iters} warm={c0 is not None}: vs pruned passes {dp:.1e}, "
+                      f"vs full passes {df:.1e}", flush=True)
+                assert dp <= SHORT_TOL and df <= SHORT_TOL, (solver, iters, dp, df)
+        plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+        g = _np(fn(y, tau, 300))
+        ref = (P.fista if solver == "fista" else P.ista)(300)
+        Fr = P.objective(ref)
+        rel = abs(P.objective(g) - Fr) / Fr
+        print(f"  {solver} 300 iterations: rel F = {rel:.2e}", flush=True)
+        assert rel <= OBJ_TOL
+    # ADMM on the same configuration takes the full cooperative form
+    rho = float(np.count_nonzero(sc.mask))
+    z = _np(plan.admm(y, tau, rho, 37))
+    plan.set_config(resident_groups=0)
+    zr = _np(plan.admm(y, tau, rho, 37))
+    assert np.linalg.norm(z - zr) <= SHORT_TOL * max(np.linalg.norm(zr), 1e-30)
+    plan.close()
