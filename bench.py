@@ -37,6 +37,12 @@ TRAFFIC = {
         "pruned": {"bytes_per_iteration": int((187.7 + 172.4) * 2 * 1024 + (58.2 + 64.0) * 1024),
                    "launch": {"prow_elems": 4, "prow_rows_per_block": 2, "pcol_elems": 4, "pcol_cols_per_block": 2}},
     },
+    # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
+    # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
+    "b9a0e1f0cbac3260": {
+        "resident_pruned": {"bytes_per_iteration": 366602,
+                            "launch": {"resident_groups": 64, "resident_spread": 1, "support_columns": 1}},
+    },
 }
 
 
@@ -44,7 +50,10 @@ def _traffic_for(kh, launch):
     """(bytes per iteration, the launch shape they were counted on) for the path the solve runs
     (cooperative, pruned or full passes), or (None, None) when the device sources changed since
     the count or none was taken for that path."""
-    path = "resident" if launch.get("resident_groups") else ("pruned" if launch.get("support_columns") else "full")
+    if launch.get("resident_groups"):
+        path = "resident_pruned" if launch.get("support_columns") else "resident"
+    else:
+        path = "pruned" if launch.get("support_columns") else "full"
     t = TRAFFIC.get(kh, {}).get(path)
     if not t:
         return None, None
