@@ -438,7 +438,8 @@ def main():
     if resident:
         solve_ms = plan.profile_resident("fista", T, reps=20)
         iter_ms = solve_ms / T
-        kernel = f"fista solve of {T} iterations as one cooperative launch (k_resident)"
+        kernel = (f"fista solve of {T} iterations as one cooperative launch "
+                  f"({'k_resident_pruned' if tuned.get('support_columns') else 'k_resident'})")
         timing = {"solve_us": round(solve_ms * 1e3, 2), "iteration_us": round(iter_ms * 1e3, 3)}
     else:
         col_ms, row_ms = plan.profile_passes("fista", reps=500)
