@@ -438,8 +438,9 @@ def main():
     if resident:
         solve_ms = plan.profile_resident("fista", T, reps=20)
         iter_ms = solve_ms / T
+        pruned_coop = plan.support_columns()[1] == 2
         kernel = (f"fista solve of {T} iterations as one cooperative launch "
-                  f"({'k_resident_pruned' if tuned.get('support_columns') else 'k_resident'})")
+                  f"({'k_resident_pruned' if pruned_coop else 'k_resident'})")
         timing = {"solve_us": round(solve_ms * 1e3, 2), "iteration_us": round(iter_ms * 1e3, 3)}
     else:
         col_ms, row_ms = plan.profile_passes("fista", reps=500)
