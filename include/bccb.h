@@ -373,14 +373,15 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   G x resident_spread workgroups co-resident; a barrier that waits longer
  *   than one second abandons the solve and it returns BCCB_E_DEVICE.
  *   With support_columns in effect as well, ISTA and FISTA run the pruned
- *   cooperative form when it fits: only the kept spectral columns of the row
- *   spectra are exchanged, every group rebuilds DFT2 of the iterate on the
- *   support bins from all of them as direct sums, and an iteration takes one
- *   grid barrier; it has 1024 / L1 rows per group (L2 L1 / 1024 groups, the
- *   value of resident_groups then only switching it on) and needs the kept
- *   row spectra of all rows, the twiddles and the support tables in 64 KB of
- *   LDS (16 kept columns of 256 rows at the paper-scale geometry).  ADMM keeps
- *   the full cooperative form with resident_groups groups.
+ *   cooperative form when it fits: each group publishes its own rows' parts
+ *   of DFT2 of the iterate at the support bins (Omega's nonzeros, eq. (21)),
+ *   and after one grid barrier per iteration every group adds all parts and
+ *   builds its rows' correction from them, so only nsup values per group
+ *   cross between groups; it has 1024 / L1 rows per group (L2 L1 / 1024
+ *   groups, the value of resident_groups then only switching it on) and needs
+ *   its rows' twiddles at the support bins, the row transform areas and the
+ *   support tables in 64 KB of LDS.  ADMM keeps the full cooperative form with
+ *   resident_groups groups.
  *   resident_spread: 1, 2, 4 or 8 -- as row_spread, for the cooperative launch.
  * The configuration changes timing only; results agree to FP32 rounding.
  */

@@ -1,11 +1,11 @@
 """GPU parity of the single-scene cooperative solver (one launch per solve, the
-workgroups meeting at grid barriers between the column and row phases) against
-the two-pass path and the FP64 oracle.
+workgroups meeting at grid barriers) against the two-pass path and the FP64 oracle.
 
-The cooperative kernel does the arithmetic of the passes at E = 4 element for
+The full cooperative form does the arithmetic of the passes at E = 4 element for
 element, so against those passes the iterates agree to FP32 rounding of the
-compiler's contraction choices (rel <= 1e-5 over short runs); over long runs
-both are held to the oracle's objective (rel <= 1e-5).
+compiler's contraction choices; the pruned form replaces the column transforms
+by sums at the support bins.  Both are held to rel <= 1e-5 against the passes
+over short runs and to the oracle's objective (rel <= 1e-5) over long runs.
 """
 import numpy as np
 import pytest
@@ -171,10 +171,9 @@ def test_resident_autotune_and_profile():
 
 @pytest.mark.parametrize("geom", ["tiny", "sweep512", "rect", "paper"])
 def test_resident_pruned_matches_passes(geom):
-    """The pruned cooperative form (kept spectral columns exchanged, the support-bin
-    spectrum rebuilt by every group as direct sums, one barrier per iteration) against
-    the pruned and the full passes, cold and warm started, and the oracle's objective
-    over a long run."""
+    """The pruned cooperative form (per-group parts of DFT2 at the support bins exchanged,
+    every group adding all of them, one barrier per iteration) against the pruned and the
+    full passes, cold and warm started, and the oracle's objective over a long run."""
     sc = GEOMS[geom]()
     P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
