@@ -5,9 +5,12 @@ python bench.py [--gpus 1] [--steps K] [--warmup W]
 One step = one complete FISTA solve of 500 iterations (adjoint/setup plus 500
 fused Gram iterations) on the 16x16-URA, 64-element, L1 = L2 = 256 scene, with
 the snapshot already resident in HBM.  value = FISTA iterations per second over
-the K timed steps.  The JSON line also carries ISTA/ADMM rates on the same
-scene, the live per-pass roofline figures (hipEvent-timed inside this run) and
-the FP64 CPU oracle timed on a bounded sample.
+the K timed steps; the plan is autotuned first, which chooses between the two
+passes per iteration (full or pruned) and the cooperative one-launch solver.
+The JSON line also carries ISTA/ADMM rates on the same scene, the live roofline
+figures of the chosen path's kernels (hipEvent-timed inside this run), the
+batched, large-grid, learned-vs-plain and dense-baseline workloads, the paper's
+regular-vs-fast sweep, and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
