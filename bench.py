@@ -368,9 +368,11 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
-    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep"], default="all",
+    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned"],
+                    default="all",
                     help="subsets: the single-scene solve only, the batched workloads only, a uniform "
-                         "256^2 batch only (profiling), or a plain 1 GiB device copy (counter calibration)")
+                         "256^2 batch only (profiling), a plain 1 GiB device copy (counter calibration), "
+                         "the paper's regular-vs-fast sweep, or learned-vs-plain (--learned-scenes)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
     ap.add_argument("--launch", type=str, default=None,
                     help="JSON plan configuration for the single-scene solve instead of autotuning "
@@ -404,6 +406,9 @@ def main():
         return
     if args.only == "sweep":
         print(json.dumps({"paper_sweep": paper_sweep(B, S)}))
+        return
+    if args.only == "learned":
+        print(json.dumps({"learned_vs_plain": learned_run(B, S, args.learned_scenes)}))
         return
     if args.only == "batch256":
         dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,

@@ -297,8 +297,10 @@ int lista_solve(bccb_lista_t net, const float* params, const bccb_c32* y, const 
  *   bccb_config.support_columns), time the launchable shapes of the fallback
  *   FISTA's pruned passes over the context's whole batch capacity, `reps`
  *   launches each, with the iterate in the sparse form most iterations see,
- *   and keep the fastest; otherwise nothing changes.  The learned layers keep
- *   their shapes.  Timing only: results agree to FP32 rounding.  The context's
+ *   and keep the fastest; otherwise nothing changes.  The pruned learned
+ *   layers (same kernels over the dilated column set) then take the tuned
+ *   element counts, with rows / columns per block reduced where their column
+ *   set needs it.  Timing only: results agree to FP32 rounding.  The context's
  *   buffers hold nothing a later call reads.
  */
 int lista_autotune(bccb_lista_t net, int reps);

@@ -652,6 +652,16 @@ int lista_autotune(bccb_lista_t n, int reps) {
   }
   n->rcfgp = br;
   n->ccfgp = bc;
+  // the pruned learned layers run the same two kernels over the dilated column
+  // set: they take the tuned E, with rows / columns per block cut down to fit it
+  if (n->prune_layers) {
+    PassCfg rd = br, cd = bc;
+    while (!rowp_shape_ok(n->L1, rd, n->ncsd) && rd.rpb > 1) rd.rpb /= 2;
+    cd.W = std::min(n->ncsd, cd.W);
+    while (!colp_shape_ok(n->ncsd, n->L2, cd) && cd.W > 1) cd.W /= 2;
+    if (rowp_shape_ok(n->L1, rd, n->ncsd)) n->rcfgd = rd;
+    if (colp_shape_ok(n->ncsd, n->L2, cd)) n->ccfgd = cd;
+  }
   return BCCB_OK;
 }
 

@@ -212,6 +212,11 @@ def test_kkt_gated_solve():
     c_t, it_t, rk_t, rc = net.solve(None, ys, taus, kkt_target=target, check_every=10, max_iters=4000)
     assert rc == 0 and np.all(np.abs(it_t - plain_iters) <= 10)
     assert np.all(rk_t <= target)
+    # the learned layers take the tuned shapes too: the identity network still follows plain FISTA
+    c_i, it_i, rk_i, rc = net.solve(cases["identity"], ys, taus, kkt_target=target, check_every=10, max_iters=4000)
+    print(f"case kkt solve identity after autotune: iters {it_i.tolist()}", flush=True)
+    assert rc == 0 and np.all(np.abs(it_i + K - plain_iters) <= 20)
+    assert np.all(rk_i <= target)
     assert B.lib.lista_autotune(net._h, 0) == B.BCCB_E_INVALID
     net.close()
 
