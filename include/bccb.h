@@ -379,12 +379,15 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   of DFT2 of the iterate at the support bins (Omega's nonzeros, eq. (21)),
  *   and after one grid barrier per iteration every group adds all parts and
  *   builds its rows' correction from them, so only nsup values per group
- *   cross between groups; it has 1024 / L1 rows per group (L2 L1 / 1024
- *   groups, the value of resident_groups then only switching it on) and needs
+ *   cross between groups; it has 4 resident_block / L1 rows per group of
+ *   resident_block threads (L2 L1 / (4 resident_block) groups, the value of
+ *   resident_groups then only switching it on) and needs
  *   its rows' twiddles at the support bins, the row transform areas and the
  *   support tables in 64 KB of LDS.  ADMM keeps the full cooperative form with
  *   resident_groups groups.
  *   resident_spread: 1, 2, 4 or 8 -- as row_spread, for the cooperative launch.
+ *   resident_block: 256 or 512 (0 = 256) -- threads per group of the pruned
+ *   cooperative form.
  * The configuration changes timing only; results agree to FP32 rounding.
  */
 typedef struct {
@@ -404,6 +407,7 @@ typedef struct {
   int pcol_cols_per_block;
   int resident_groups;
   int resident_spread;
+  int resident_block;
 } bccb_config;
 
 /* Current configuration of a plan (a heuristic until set or tuned). */

@@ -35,7 +35,8 @@ class Config(ctypes.Structure):
                 ("sparse_iterate", ctypes.c_int), ("support_columns", ctypes.c_int),
                 ("prow_elems", ctypes.c_int), ("prow_rows_per_block", ctypes.c_int),
                 ("pcol_elems", ctypes.c_int), ("pcol_cols_per_block", ctypes.c_int),
-                ("resident_groups", ctypes.c_int), ("resident_spread", ctypes.c_int)]
+                ("resident_groups", ctypes.c_int), ("resident_spread", ctypes.c_int),
+                ("resident_block", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -167,18 +167,20 @@ static bool resident_shape_ok(const bccb_plan_s* p, int groups, int spread) {
   return true;
 }
 
-// Groups of the pruned cooperative form: rows of 1024 / L1 per 256-thread group.
-static int resident_pruned_groups(const bccb_plan_s* p) {
-  const int rpc = 1024 / p->L1;
-  return rpc >= 1 && p->L2 % rpc == 0 ? p->L2 / rpc : 0;
+// Groups of the pruned cooperative form: rows of 4 block / L1 per group of
+// `block` threads (256 or 512), 0 if that does not tile the grid.
+static int resident_pruned_groups(const bccb_plan_s* p, int block) {
+  const int rpc = 4 * block / p->L1;
+  return rpc >= 1 && rpc <= p->L2 && p->L2 % rpc == 0 ? p->L2 / rpc : 0;
 }
+static int resident_pruned_groups(const bccb_plan_s* p) { return resident_pruned_groups(p, p->resident_block); }
 
 // ISTA / FISTA take the pruned cooperative form: the solves take the pruned
 // passes otherwise (pruned_on) and that form can be launched with the plan's
 // spread (cached per spread: the check queries the occupancy API).
 static bool resident_pruned_on(bccb_plan_s* p) {
   if (!pruned_on(p) || !p->d_rpart) return false;
-  if (p->res_pruned_spread != p->resident_spread) {
+  if (p->res_pruned_spread != p->resident_spread || p->res_pruned_block != p->resident_block) {
     ResidentArgs a;
     a.groups = resident_pruned_groups(p);
     a.spread = p->resident_spread;
@@ -187,6 +189,7 @@ static bool resident_pruned_on(bccb_plan_s* p) {
     p->res_pruned_ok = a.groups > 0 && launch_resident(p->L1, p->L2, RES_PRUNED_FISTA, a, 1, nullptr) == 0 &&
                        launch_resident(p->L1, p->L2, RES_PRUNED_ISTA, a, 1, nullptr) == 0;
     p->res_pruned_spread = p->resident_spread;
+    p->res_pruned_block = p->resident_block;
   }
   return p->res_pruned_ok;
 }
@@ -505,8 +508,8 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_sync, kResidentSyncWords);
   // the pruned cooperative form's per-group parts of DFT2 at the support bins
-  if (rc == BCCB_OK && p->prune_ok && resident_pruned_groups(p) > 0)
-    rc = dmalloc(&p->d_rpart, static_cast<size_t>(resident_pruned_groups(p)) * p->nsup);
+  if (rc == BCCB_OK && p->prune_ok && resident_pruned_groups(p, 256) > 0)   // the most groups
+    rc = dmalloc(&p->d_rpart, static_cast<size_t>(resident_pruned_groups(p, 256)) * p->nsup);
   if (rc == BCCB_OK) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;
@@ -897,6 +900,7 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   cfg->pcol_cols_per_block = p->cfg_colp.W;
   cfg->resident_groups = p->resident_groups;
   cfg->resident_spread = p->resident_spread;
+  cfg->resident_block = p->resident_block;
   return BCCB_OK;
 }
 
@@ -914,6 +918,7 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   if (!row_shape_ok(p->L1, r, spi) || !col_shape_ok(p->L1, p->L2, c) || !spread_ok(r.spread) || !spread_ok(c.spread) ||
       (spi && p->L1 < 8))
     return BCCB_E_INVALID;
+  if (!(cfg->resident_block == 0 || cfg->resident_block == 256 || cfg->resident_block == 512)) return BCCB_E_INVALID;
   if (cfg->resident_groups < 0 || (cfg->resident_groups > 0 && (!p->has_support ||
                                      !resident_shape_ok(p, cfg->resident_groups, cfg->resident_spread))))
     return BCCB_E_INVALID;
@@ -937,6 +942,7 @@ int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   p->sparse_iterate = spi ? 1 : 0;
   p->resident_groups = cfg->resident_groups;
   p->resident_spread = cfg->resident_groups > 0 ? cfg->resident_spread : 1;
+  p->resident_block = cfg->resident_block == 512 ? 512 : 256;
   drop_graph(p);
   return BCCB_OK;
 }
@@ -1045,12 +1051,13 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
     auto restore = [&]() {
       p->resident_groups = 0;
       p->resident_spread = 1;
+      p->resident_block = 256;
       p->use_prune = pass_prune;
     };
     restore();
     float best_ms = solve_ms();
     if (best_ms < 0.f) return BCCB_E_DEVICE;
-    int bg = 0, bs = 1, bprune = pass_prune;
+    int bg = 0, bs = 1, bb = 256, bprune = pass_prune;
     // per spread: the fastest full cooperative group count (ADMM runs that form)
     float full_ms[9];
     int full_g[9];
@@ -1058,17 +1065,21 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
       full_ms[i] = 1e30f;
       full_g[i] = 0;
     }
-    bool pruned_done[9] = {false, false, false, false, false, false, false, false, false};
+    bool pruned_done[9][2] = {};
     for (int G = 1; G <= kResidentMaxGroups; G *= 2) {
       for (int sp = 1; sp <= 8; sp *= 8) {
         if (!resident_shape_ok(p, G, sp)) continue;
-        for (int pz = 0; pz <= (pr ? 1 : 0); ++pz) {
-          if (pz == 1 && pruned_done[sp]) continue;   // the pruned form's groups do not depend on G
+        // candidates: the full form (pz 0), the pruned form with 256- and 512-thread groups
+        for (int cand = 0; cand < (pr ? 3 : 1); ++cand) {
+          const int pz = cand > 0 ? 1 : 0;
+          const int blk = cand == 2 ? 512 : 256;
+          if (pz == 1 && pruned_done[sp][cand - 1]) continue;   // the pruned form's groups do not depend on G
           p->resident_groups = G;
           p->resident_spread = sp;
+          p->resident_block = blk;
           p->use_prune = pz;
           if (pz == 1) {
-            pruned_done[sp] = true;
+            pruned_done[sp][cand - 1] = true;
             if (!resident_pruned_on(p)) {
               restore();
               continue;
@@ -1085,6 +1096,7 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
             best_ms = ms;
             bg = G;
             bs = sp;
+            bb = blk;
             bprune = pz;
           }
         }
@@ -1092,6 +1104,7 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
     }
     p->resident_groups = bg > 0 ? (full_g[bs] > 0 ? full_g[bs] : bg) : 0;
     p->resident_spread = bg > 0 ? bs : 1;
+    p->resident_block = bb;
     p->use_prune = bprune;
   }
   drop_graph(p);

@@ -83,7 +83,9 @@ struct bccb_plan_s {
   unsigned* d_sync = nullptr;
   long long wall_ticks_per_s = 0;
   float2* d_rpart = nullptr;       // pruned form: [groups][nsup] per-group parts of DFT2 at the bins
-  int res_pruned_spread = -1;      // spread the cached pruned-form check was made for
+  int resident_block = 256;        // threads per group of the pruned cooperative form (256 or 512)
+  int res_pruned_spread = -1;      // spread and block the cached pruned-form check was made for
+  int res_pruned_block = -1;
   bool res_pruned_ok = false;
 
   bccb::PassCfg cfg_row;           // launch shape of the row passes (N = L1)

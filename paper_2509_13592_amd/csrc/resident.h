@@ -341,10 +341,10 @@ int resident_launch_m(const ResidentArgs& a, int check_only, hipStream_t s) {
 // The column transforms of the passes become these sums, so the results agree
 // with the pruned passes to FP32 rounding, not element for element.
 // ---------------------------------------------------------------------------
-template <int N1, int N2>
+template <int N1, int N2, int NT_>
 struct ResidentPrunedShape {
   static constexpr int E = kResidentElems;
-  static constexpr int NT = 256;
+  static constexpr int NT = NT_;   // 256 or 512 threads per group
   static constexpr int T1 = N1 / E;
   static constexpr int RPC = NT / T1;   // rows per group
   static constexpr int AR1 = fft_areas(N1, E), FA1 = fft_area(N1);
@@ -364,9 +364,9 @@ __host__ __device__ constexpr int resident_part_lanes(int nsup, int nt) {
   return q;
 }
 
-template <int N1, int N2, int MODE>
-__global__ __launch_bounds__(256) void k_resident_pruned(ResidentArgs a) {
-  using S = ResidentPrunedShape<N1, N2>;
+template <int N1, int N2, int MODE, int NT_>
+__global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
+  using S = ResidentPrunedShape<N1, N2, NT_>;
   constexpr int E = S::E, NT = S::NT, T1 = S::T1, RPC = S::RPC;
   using FR = Stockham<N1, E, (T1 <= 64)>;
   constexpr bool kFista = (MODE == RES_PRUNED_FISTA);
@@ -522,9 +522,9 @@ __global__ __launch_bounds__(256) void k_resident_pruned(ResidentArgs a) {
   }
 }
 
-template <int N1, int N2, int MODE>
-int resident_launch_p(const ResidentArgs& a, int check_only, hipStream_t s) {
-  using S = ResidentPrunedShape<N1, N2>;
+template <int N1, int N2, int MODE, int NT>
+int resident_launch_pt(const ResidentArgs& a, int check_only, hipStream_t s) {
+  using S = ResidentPrunedShape<N1, N2, NT>;
   if (S::RPC < 1 || S::RPC > N2 || N2 % S::RPC != 0) return -1;
   const int G = N2 / S::RPC;
   if (a.groups != G || G > kResidentMaxGroups) return -1;
@@ -532,7 +532,7 @@ int resident_launch_p(const ResidentArgs& a, int check_only, hipStream_t s) {
   const size_t shm = S::lds_bytes(a.ncs, a.nsup);
   if (shm > 65536) return -1;
   const int spread = a.spread > 1 ? a.spread : 1;
-  const auto kfn = k_resident_pruned<N1, N2, MODE>;
+  const auto kfn = k_resident_pruned<N1, N2, MODE, NT>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S::NT, shm) != hipSuccess) return -4;
   int dev = 0, cus = 0;
@@ -548,6 +548,19 @@ int resident_launch_p(const ResidentArgs& a, int check_only, hipStream_t s) {
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(G * spread), dim3(S::NT), args,
                                                   static_cast<unsigned>(shm), s);
   return e == hipSuccess ? 0 : -4;
+}
+
+// Groups of 256 or 512 threads, told apart by the group count the caller asks
+// for (N2 L1 / 1024 or N2 L1 / 2048).
+template <int N1, int N2, int MODE>
+int resident_launch_p(const ResidentArgs& a, int check_only, hipStream_t s) {
+  constexpr int T1 = N1 / kResidentElems;
+  if (256 / T1 >= 1 && N2 % (256 / T1) == 0 && a.groups == N2 / (256 / T1))
+    return resident_launch_pt<N1, N2, MODE, 256>(a, check_only, s);
+  if constexpr (512 / T1 >= 1 && 512 / T1 <= N2) {
+    if (N2 % (512 / T1) == 0 && a.groups == N2 / (512 / T1)) return resident_launch_pt<N1, N2, MODE, 512>(a, check_only, s);
+  }
+  return -1;
 }
 
 template <int N1, int N2>

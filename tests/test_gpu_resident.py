@@ -169,8 +169,9 @@ def test_resident_autotune_and_profile():
     plan.close()
 
 
+@pytest.mark.parametrize("block", [256, 512])
 @pytest.mark.parametrize("geom", ["tiny", "sweep512", "rect", "paper"])
-def test_resident_pruned_matches_passes(geom):
+def test_resident_pruned_matches_passes(geom, block):
     """The pruned cooperative form (per-group parts of DFT2 at the support bins exchanged,
     every group adding all of them, one barrier per iteration) against the pruned and the
     full passes, cold and warm started, and the oracle's objective over a long run."""
@@ -179,9 +180,9 @@ def test_resident_pruned_matches_passes(geom):
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     shapes = _shapes(plan)
     G, sp = shapes[0]
-    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
     ncols, mode = plan.support_columns()
-    print(f"case {geom}: kept columns {ncols}, support-column mode {mode}", flush=True)
+    print(f"case {geom} block {block}: kept columns {ncols}, support-column mode {mode}", flush=True)
     if mode != 2:
         plan.close()
         pytest.skip("the pruned cooperative form does not fit this geometry")
@@ -194,7 +195,7 @@ def test_resident_pruned_matches_passes(geom):
         fn = plan.fista if solver == "fista" else plan.ista
         for iters in (1, 2, 37):
             for c0 in (None, warm):
-                plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+                plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
                 got = _np(fn(y, tau, iters, c0=c0))
                 plan.set_config(resident_groups=0, support_columns=1)
                 ref_p = _np(fn(y, tau, iters, c0=c0))
@@ -206,7 +207,7 @@ def test_resident_pruned_matches_passes(geom):
                 print(f"  {solver} iters={iters} warm={c0 is not None}: vs pruned passes {dp:.1e}, "
                       f"vs full passes {df:.1e}", flush=True)
                 assert dp <= SHORT_TOL and df <= SHORT_TOL, (solver, iters, dp, df)
-        plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+        plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
         g = _np(fn(y, tau, 300))
         ref = (P.fista if solver == "fista" else P.ista)(300)
         Fr = P.objective(ref)
