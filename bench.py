@@ -42,9 +42,10 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "b9a0e1f0cbac3260": {
-        "resident_pruned": {"bytes_per_iteration": 366602,
-                            "launch": {"resident_groups": 64, "resident_spread": 1, "support_columns": 1}},
+    "4ba6f707a1da5989": {
+        "resident_pruned": {"bytes_per_iteration": 183591,
+                            "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 512,
+                                       "support_columns": 1}},
     },
 }
 
