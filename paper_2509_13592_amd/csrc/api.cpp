@@ -229,8 +229,8 @@ static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, fl
   if (pruned) mode = (mode == RES_FISTA) ? RES_PRUNED_FISTA : RES_PRUNED_ISTA;
   const int groups = pruned ? resident_pruned_groups(p) : p->resident_groups;
   if (mode == RES_FISTA || mode == RES_PRUNED_FISTA) BCCB_TRY(ensure_beta(p, iters));
-  BCCB_TRY(kern(launch_fill_int(reinterpret_cast<int*>(p->d_sync), kResidentArriveOffset + groups * kResidentArriveStride,
-                                0, s)));
+  // a fresh tag per solve: the sync words keep what earlier solves wrote (all below it)
+  const unsigned long long tag = (++p->res_solve) << 32;
   ResidentArgs a;
   a.xy = pruned ? p->d_rpart : p->d_xy;
   a.scol = p->d_scol;
@@ -254,6 +254,7 @@ static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, fl
   a.groups = groups;
   a.spread = p->resident_spread;
   a.sync = p->d_sync;
+  a.tag = tag;
   a.flag = p->d_flag;
   a.timeout_ticks = p->wall_ticks_per_s;   // one second per barrier wait
   return kern(launch_resident(p->L1, p->L2, mode, a, 0, s));
@@ -507,6 +508,8 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   }
   if (rc == BCCB_OK) rc = dmalloc(&p->d_coef, 2);
   if (rc == BCCB_OK) rc = dmalloc(&p->d_sync, kResidentSyncWords);
+  if (rc == BCCB_OK && hipMemset(p->d_sync, 0, kResidentSyncWords * sizeof(unsigned long long)) != hipSuccess)
+    rc = BCCB_E_DEVICE;
   // the pruned cooperative form's per-group parts of DFT2 at the support bins
   if (rc == BCCB_OK && p->prune_ok && resident_pruned_groups(p, 256) > 0)   // the most groups
     rc = dmalloc(&p->d_rpart, static_cast<size_t>(resident_pruned_groups(p, 256)) * p->nsup);

@@ -75,12 +75,13 @@ struct bccb_plan_s {
 
   // single-scene cooperative solver (resident.h): groups > 0 turns it on for ISTA,
   // FISTA and ADMM when the spectral support is in use; FISTA momenta beta_t in
-  // d_beta[t - 1] (capacity beta_cap); d_sync = arrival counter and abort word
+  // d_beta[t - 1] (capacity beta_cap); d_sync = abort and arrival words
   int resident_groups = 0;
   int resident_spread = 1;
   float* d_beta = nullptr;
   int beta_cap = 0;
-  unsigned* d_sync = nullptr;
+  unsigned long long* d_sync = nullptr;
+  unsigned long long res_solve = 0;   // cooperative solves enqueued so far (their tags)
   long long wall_ticks_per_s = 0;
   float2* d_rpart = nullptr;       // pruned form: [groups][nsup] per-group parts of DFT2 at the bins
   int resident_block = 256;        // threads per group of the pruned cooperative form (256 or 512)

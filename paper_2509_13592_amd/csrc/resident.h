@@ -41,25 +41,27 @@ struct ResidentShape {
   static constexpr size_t LDS_BYTES = static_cast<size_t>(N1 + N2 + WORK) * sizeof(float2);
 };
 
-// Grid barrier number k (k = 1, 2, ...).  Every wave waits for its own stores
-// to complete and the block meets; thread 0 publishes the block's stores at
-// agent scope (one L2 write-back per block rather than one per wave) and
-// writes k to the block's arrival word (its own 128-byte line: arrivals do
-// not contend on one address); the first wave then polls all G arrival words
-// at once, one per lane, until every one holds k or more (bounded in
-// wall-clock time; a timeout raises the abort word and the flag, an abort
-// raised elsewhere ends the wait), acquires for the block (its waves share
-// one CU and its L1) and the block meets again.  Returns false when the solve
-// is being abandoned.
+// Grid barrier number k (k = 1, 2, ...) of the solve tagged a.tag.  Every wave
+// waits for its own stores to complete and the block meets; thread 0 publishes
+// the block's stores at agent scope (one L2 write-back per block rather than one
+// per wave) and writes tag | k to the block's arrival word (its own 128-byte
+// line: arrivals do not contend on one address); the first wave then polls all
+// G arrival words at once, one per lane, until every one holds tag | k or more
+// (bounded in wall-clock time; a timeout writes the tag into the abort word and
+// raises the flag, and an abort word holding the tag ends the wait), acquires
+// for the block (its waves share one CU and its L1) and the block meets again.
+// Words are never reset: whatever an earlier solve left is below this solve's
+// tag.  Returns false when the solve is being abandoned.
 __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsigned k, int* s_ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const int tid = threadIdx.x;
   if (tid < 64) {
-    unsigned* arrive = a.sync + kResidentArriveOffset;
+    unsigned long long* arrive = a.sync + kResidentArriveOffset;
+    const unsigned long long want = a.tag | k;
     if (tid == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(arrive + static_cast<size_t>(g) * kResidentArriveStride, k, __ATOMIC_RELAXED,
+      __hip_atomic_store(arrive + static_cast<size_t>(g) * kResidentArriveStride, want, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     int ok = 1;
@@ -68,15 +70,15 @@ __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsi
       bool mine = true;
       for (int i = tid; i < a.groups; i += 64)
         mine = mine && __hip_atomic_load(arrive + static_cast<size_t>(i) * kResidentArriveStride, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) >= k;
+                                         __HIP_MEMORY_SCOPE_AGENT) >= want;
       if (__all(mine)) break;
-      if (__hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      if (__hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.tag) {
         ok = 0;
         break;
       }
       if (wall_clock64() - t0 > a.timeout_ticks) {
         if (tid == 0) {
-          __hip_atomic_store(a.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(a.sync, a.tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ok = 0;

@@ -22,8 +22,8 @@ enum ResidentMode {
 
 constexpr int kResidentMaxChunks = 4;   // 1024-point chunks per workgroup and phase (256 threads)
 constexpr int kResidentMaxGroups = 256;
-constexpr int kResidentArriveOffset = 32;   // sync words: [0] abort, then one arrival word per group
-constexpr int kResidentArriveStride = 32;   // (unsigned) one 128-byte line per arrival word
+constexpr int kResidentArriveOffset = 16;   // 64-bit sync words: [0] abort, then one arrival word per group
+constexpr int kResidentArriveStride = 16;   // (64-bit words) one 128-byte line per arrival word
 constexpr int kResidentSyncWords = kResidentArriveOffset + kResidentMaxGroups * kResidentArriveStride;
 
 struct ResidentArgs {
@@ -42,7 +42,11 @@ struct ResidentArgs {
   int iters = 0;
   int groups = 1;                   // G: workgroups that work
   int spread = 1;                   // launch spread x G workgroups, every spread-th works (see PassCfg)
-  unsigned* sync = nullptr;         // [kResidentSyncWords]: abort word, arrival words; zero at launch
+  // [kResidentSyncWords] 64-bit words: the abort word (the tag of a solve being abandoned)
+  // and the arrival words (tag | barrier number); they are never reset: tags grow from
+  // solve to solve, so what earlier solves left is always below what this one waits for
+  unsigned long long* sync = nullptr;
+  unsigned long long tag = 0;       // this solve's id in the high 32 bits
   int* flag = nullptr;              // |= 1: non-finite warm start; |= 2: a barrier wait timed out
   long long timeout_ticks = 0;      // wall-clock ticks one barrier wait may take
   // pruned forms: xy holds [G][nsup] per-group parts of DFT2 of the iterate at the support

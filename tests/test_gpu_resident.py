@@ -29,6 +29,7 @@ GEOMS = {
     "sweep512": lambda: S.paper_sweep_scene(512, 1),    # L1 = 512, L2 = 32
     "rect": lambda: S.custom_scene(12, 9, 50, 128, 256, K=3, snr_db=20, seed=(21, 0, 0)),
     "paper": lambda: S.paper_scale_scene(2),            # 256 x 256
+    "big": lambda: S.custom_scene(32, 32, 256, 512, 512, K=5, snr_db=20, seed=(22, 0, 0)),   # 512 x 512
 }
 
 
@@ -220,4 +221,58 @@ def test_resident_pruned_matches_passes(geom, block):
     plan.set_config(resident_groups=0)
     zr = _np(plan.admm(y, tau, rho, 37))
     assert np.linalg.norm(z - zr) <= SHORT_TOL * max(np.linalg.norm(zr), 1e-30)
+    plan.close()
+
+
+@pytest.mark.parametrize("block", [256, 512])
+def test_resident_pruned_largest_grid(block):
+    """The pruned cooperative form at 512 x 512 (256 or 128 groups, 256 support bins in
+    32 kept columns) against the pruned and the full passes over short runs."""
+    sc = GEOMS["big"]()
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    G, sp = _shapes(plan)[0]
+    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
+    ncols, mode = plan.support_columns()
+    print(f"case 512x512 block {block}: kept columns {ncols}, support-column mode {mode}", flush=True)
+    assert mode == 2
+    y = B.to_device(sc.y)
+    tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    for solver in ("ista", "fista"):
+        fn = plan.fista if solver == "fista" else plan.ista
+        for iters in (1, 2, 37):
+            plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
+            got = _np(fn(y, tau, iters))
+            plan.set_config(resident_groups=0, support_columns=1)
+            ref_p = _np(fn(y, tau, iters))
+            plan.set_config(resident_groups=0, support_columns=0)
+            ref_f = _np(fn(y, tau, iters))
+            nr = max(np.linalg.norm(ref_f), 1e-30)
+            dp, df = np.linalg.norm(got - ref_p) / nr, np.linalg.norm(got - ref_f) / nr
+            print(f"  {solver} iters={iters}: vs pruned passes {dp:.1e}, vs full passes {df:.1e}", flush=True)
+            assert dp <= SHORT_TOL and df <= SHORT_TOL, (solver, iters, dp, df)
+    plan.close()
+
+
+@pytest.mark.parametrize("geom,block", [("paper", 256), ("paper", 512), ("big", 256), ("big", 512), ("sweep512", 256)])
+def test_resident_repeated_solves_identical(geom, block):
+    """Solves repeated on one plan give bitwise the same result, in both cooperative forms:
+    nothing one solve leaves in the barrier words or the exchange buffers may let a later
+    solve's groups run ahead (a regression test: the barrier words were once cleared by a
+    separate kernel before every solve, and later solves at 256 groups read the previous
+    solve's parts at their first barrier)."""
+    sc = GEOMS[geom]()
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    shapes = _shapes(plan)
+    y = B.to_device(sc.y)
+    tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+    for support_columns, G in ((1, shapes[0][0]), (0, shapes[-1][0])):
+        plan.set_config(support_columns=support_columns, resident_groups=G, resident_spread=1, resident_block=block)
+        for solver in ("ista", "fista"):
+            fn = plan.fista if solver == "fista" else plan.ista
+            for iters in (2, 9):
+                outs = [_np(fn(y, tau, iters)) for _ in range(4)]
+                same = all(np.array_equal(outs[0], o) for o in outs[1:])
+                print(f"case {geom} block {block} support_columns {support_columns} G {G} {solver} {iters}: "
+                      f"mode {plan.support_columns()[1]}, identical {same}", flush=True)
+                assert same
     plan.close()
