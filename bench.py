@@ -42,8 +42,8 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "4ba6f707a1da5989": {
-        "resident_pruned": {"bytes_per_iteration": 183591,
+    "d1732037794371ae": {
+        "resident_pruned": {"bytes_per_iteration": 183705,
                             "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 512,
                                        "support_columns": 1}},
     },
