@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -29,12 +30,12 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration per grid point
 
 # HBM bytes per FISTA iteration (column pass + row pass) from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs, keyed by the kernel source they were measured on, with the
-# launch shape of that run.  When the source or the chosen shape differs the
+# WRITE_SIZE runs, keyed by the kernel code they were measured on (comments aside),
+# with the launch shape of that run.  When the source or the chosen shape differs the
 # figure does not apply and `traffic` is reported as null.
 TRAFFIC = {
     # profiles/fista_passes_256_single_rocprofv3.md (FETCH_SIZE x 2 + WRITE_SIZE, KiB per dispatch)
-    "a18ad61f0a90c6c9": {
+    "2cf614d578f2cd8b": {
         "full": {"bytes_per_iteration": int((297.5 + 559.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
                  "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2}},
         "pruned": {"bytes_per_iteration": int((187.7 + 172.4) * 2 * 1024 + (58.2 + 64.0) * 1024),
@@ -42,7 +43,7 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "d1732037794371ae": {
+    "22d521b832ecf9e1": {
         "resident_pruned": {"bytes_per_iteration": 183705,
                             "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 512,
                                        "support_columns": 1}},
@@ -64,14 +65,21 @@ def _traffic_for(kh, launch):
     return t["bytes_per_iteration"], t["launch"]
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments, trailing blanks and empty lines (the kernels' code)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def _kernel_hash(resident: bool = False) -> str:
-    """Hash of the device sources the single-scene passes (and, with `resident`, the
-    cooperative solver) are built from."""
+    """Hash of the code (comments aside) of the device sources the single-scene passes
+    (and, with `resident`, the cooperative solver) are built from."""
     h = hashlib.sha256()
     for f in ("kernels.h", "kernels.hip", "fft_device.h", "passes.h", "passes_n.hip") + \
             (("resident_api.h", "resident.h", "resident_n.hip", "resident.hip") if resident else ()):
-        with open(os.path.join(ROOT, "paper_2509_13592_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_13592_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

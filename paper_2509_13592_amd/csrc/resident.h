@@ -12,6 +12,9 @@
 // columns), barrier, row phase (IDFT_rows, the proximal / momentum / ADMM
 // update of eqs. (9)-(15), DFT_rows on the owned rows), barrier.  The
 // arithmetic is that of the two-pass path at E = 4 element for element.
+// A pruned form for ISTA / FISTA (k_resident_pruned, further down) exchanges
+// only per-group parts of the spectrum at the support bins and needs one
+// barrier per iteration.
 //
 // The launch is cooperative (all G workgroups co-resident, or the launch
 // fails), and every barrier wait is bounded in wall-clock time: a workgroup
