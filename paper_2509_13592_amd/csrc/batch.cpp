@@ -79,6 +79,10 @@ struct bccb_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = -1;
+  // one stream per size class (default priority) and the events that fork and join them
+  std::vector<hipStream_t> cls_streams;
+  std::vector<hipEvent_t> cls_events;
+  hipEvent_t fork_event = nullptr;
 };
 
 namespace {
@@ -87,6 +91,9 @@ void batch_free(bccb_batch_s* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (hipStream_t cs : b->cls_streams) (void)hipStreamDestroy(cs);
+  for (hipEvent_t ev : b->cls_events) (void)hipEventDestroy(ev);
+  if (b->fork_event) (void)hipEventDestroy(b->fork_event);
   for (BatchClass& c : b->cls) {
     for (void* p : {static_cast<void*>(c.d_omega), static_cast<void*>(c.d_coef), static_cast<void*>(c.d_kscale),
                     static_cast<void*>(c.d_xy), static_cast<void*>(c.d_rhs), static_cast<void*>(c.d_c),
@@ -209,14 +216,16 @@ int class_col(const BatchClass& c, const PassCfg& cfg, int mode, float2* xy, flo
   return kern(launch_col(c.L2, cfg, mode, a, s));
 }
 
-int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
+// The iterations of one size class on stream s (classes share no buffers, so
+// each can run its whole loop independently of the others).
+int fista_loop_class(BatchClass& c, int iters, hipStream_t s) {
   double alpha = 1.0;
   float beta_prev = 0.f;
   for (int t = 1; t <= iters; ++t) {
     const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
     const float beta = static_cast<float>((alpha - 1.0) / alpha_next);
     alpha = alpha_next;
-    for (BatchClass& c : b->cls) {
+    {
       if (c.prune) {
         BCCB_TRY(class_colp(c, c.cfg_colp, s));
         RowArgs a = class_pruned_args(c, t % 3, (t - 1) % 3, (t + 1) % 3);
@@ -224,6 +233,7 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
         a.beta_prev = beta_prev;
         a.last = (t == iters);
         BCCB_TRY(class_row(c, c.cfg_rowp, ROW_PRUNED, a, s));
+        beta_prev = beta;
         continue;
       }
       BCCB_TRY(class_col(c, c.cfg_col, c.sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE, c.d_xy, 1.f, s));
@@ -242,6 +252,34 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
       BCCB_TRY(class_row(c, c.cfg_row, c.sp_iter ? ROW_FISTA_SP : ROW_FISTA, a, s));
     }
     beta_prev = beta;
+  }
+  return BCCB_OK;
+}
+
+// The iterations of every class: with several classes each class's loop goes on
+// a stream of its own, forked from and joined back into s (captured as parallel
+// branches of one graph), so the classes' kernels overlap instead of queueing.
+int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
+  const int nc = static_cast<int>(b->cls.size());
+  if (nc == 1) return fista_loop_class(b->cls[0], iters, s);
+  if (static_cast<int>(b->cls_streams.size()) != nc) {
+    for (int i = static_cast<int>(b->cls_streams.size()); i < nc; ++i) {
+      hipStream_t cs = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BCCB_E_DEVICE;
+      b->cls_streams.push_back(cs);
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BCCB_E_DEVICE;
+      b->cls_events.push_back(ev);
+    }
+    if (!b->fork_event && hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming) != hipSuccess)
+      return BCCB_E_DEVICE;
+  }
+  BCCB_HIP(hipEventRecord(b->fork_event, s));
+  for (int i = 0; i < nc; ++i) {
+    BCCB_HIP(hipStreamWaitEvent(b->cls_streams[i], b->fork_event, 0));
+    BCCB_TRY(fista_loop_class(b->cls[i], iters, b->cls_streams[i]));
+    BCCB_HIP(hipEventRecord(b->cls_events[i], b->cls_streams[i]));
+    BCCB_HIP(hipStreamWaitEvent(s, b->cls_events[i], 0));
   }
   return BCCB_OK;
 }
