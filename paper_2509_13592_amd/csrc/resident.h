@@ -69,15 +69,14 @@ __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsi
     }
     int ok = 1;
     const long long t0 = wall_clock64();
-    while (true) {
-      bool mine = true;
-      for (int i = tid; i < a.groups; i += 64)
-        mine = mine && __hip_atomic_load(arrive + static_cast<size_t>(i) * kResidentArriveStride, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT) >= want;
-      if (__all(mine)) break;
-      if (__hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.tag) {
+    unsigned spins = 0;
+    // a bounded wait step: false (and ok = 0) when the solve is abandoned; the abort
+    // word is read every 64th step only, since waiting for it would also wait for
+    // any poll load still in flight
+    auto keep_waiting = [&]() -> bool {
+      if ((++spins & 63) == 0 && __hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.tag) {
         ok = 0;
-        break;
+        return false;
       }
       if (wall_clock64() - t0 > a.timeout_ticks) {
         if (tid == 0) {
@@ -85,9 +84,37 @@ __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsi
           __hip_atomic_fetch_or(a.flag, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ok = 0;
-        break;
+        return false;
       }
       __builtin_amdgcn_s_sleep(1);
+      return true;
+    };
+    if (a.groups <= 64) {
+      // one word per lane, polled by two rounds of loads in flight at once (two
+      // registers taken in turn, no copy between them), so an arrival is seen
+      // within about half a round trip of landing instead of a whole one
+      const bool has = tid < a.groups;
+      const unsigned long long* mw = arrive + static_cast<size_t>(has ? tid : 0) * kResidentArriveStride;
+      unsigned long long pa = __hip_atomic_load(mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_sleep(2);
+      unsigned long long pb = __hip_atomic_load(mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (true) {
+        if (__all(!has || pa >= want)) break;
+        pa = __hip_atomic_load(mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!keep_waiting()) break;
+        if (__all(!has || pb >= want)) break;
+        pb = __hip_atomic_load(mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!keep_waiting()) break;
+      }
+    } else {
+      while (true) {
+        bool mine = true;
+        for (int i = tid; i < a.groups; i += 64)
+          mine = mine && __hip_atomic_load(arrive + static_cast<size_t>(i) * kResidentArriveStride, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) >= want;
+        if (__all(mine)) break;
+        if (!keep_waiting()) break;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tid == 0) *s_ok = ok;
