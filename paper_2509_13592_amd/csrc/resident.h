@@ -512,7 +512,8 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
 #pragma unroll
         for (int k = 0; k < PB; ++k) {
           const int gg = g0 + k * Q;
-          pv[k] = keep_if(gg < G, part[static_cast<size_t>(gg < G ? gg : 0) * nsup + jj]);
+          pv[k] = zero;
+          if (gg < G) pv[k] = part[static_cast<size_t>(gg) * nsup + jj];   // no load for groups past G
         }
 #pragma unroll
         for (int k = 0; k < PB; ++k) acc = cadd(acc, pv[k]);
