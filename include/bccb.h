@@ -374,17 +374,17 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   (workgroups of 256 threads) or L1 L2 / G = 512 (128 threads), and all
  *   G x resident_spread workgroups co-resident; a barrier that waits longer
  *   than one second abandons the solve and it returns BCCB_E_DEVICE.
- *   With support_columns in effect as well, ISTA and FISTA run the pruned
- *   cooperative form when it fits: each group publishes its own rows' parts
- *   of DFT2 of the iterate at the support bins (Omega's nonzeros, eq. (21)),
+ *   With support_columns in effect as well, ISTA, FISTA and ADMM run the
+ *   pruned cooperative form when it fits: each group publishes its own rows'
+ *   parts of DFT2 of the iterate (ADMM: of z - v) at the support bins (Omega's
+ *   nonzeros, eq. (21); (Omega + rho)^-1 differs from 1 / rho only there),
  *   and after one grid barrier per iteration every group adds all parts and
  *   builds its rows' correction from them, so only nsup values per group
  *   cross between groups; it has 4 resident_block / L1 rows per group of
  *   resident_block threads (L2 L1 / (4 resident_block) groups, the value of
  *   resident_groups then only switching it on) and needs
  *   its rows' twiddles at the support bins, the row transform areas and the
- *   support tables in 64 KB of LDS.  ADMM keeps the full cooperative form with
- *   resident_groups groups.
+ *   support tables in 64 KB of LDS.
  *   resident_spread: 1, 2, 4 or 8 -- as row_spread, for the cooperative launch.
  *   resident_block: 256 or 512 (0 = 256) -- threads per group of the pruned
  *   cooperative form.

@@ -175,9 +175,10 @@ static int resident_pruned_groups(const bccb_plan_s* p, int block) {
 }
 static int resident_pruned_groups(const bccb_plan_s* p) { return resident_pruned_groups(p, p->resident_block); }
 
-// ISTA / FISTA take the pruned cooperative form: the solves take the pruned
+// The solves take the pruned cooperative form when they would take the pruned
 // passes otherwise (pruned_on) and that form can be launched with the plan's
-// spread (cached per spread: the check queries the occupancy API).
+// spread and block for all three solvers (cached per spread and block: the
+// check queries the occupancy API).
 static bool resident_pruned_on(bccb_plan_s* p) {
   if (!pruned_on(p) || !p->d_rpart) return false;
   if (p->res_pruned_spread != p->resident_spread || p->res_pruned_block != p->resident_block) {
@@ -187,7 +188,8 @@ static bool resident_pruned_on(bccb_plan_s* p) {
     a.ncs = p->ncs;
     a.nsup = p->nsup;
     p->res_pruned_ok = a.groups > 0 && launch_resident(p->L1, p->L2, RES_PRUNED_FISTA, a, 1, nullptr) == 0 &&
-                       launch_resident(p->L1, p->L2, RES_PRUNED_ISTA, a, 1, nullptr) == 0;
+                       launch_resident(p->L1, p->L2, RES_PRUNED_ISTA, a, 1, nullptr) == 0 &&
+                       launch_resident(p->L1, p->L2, RES_PRUNED_ADMM, a, 1, nullptr) == 0;
     p->res_pruned_spread = p->resident_spread;
     p->res_pruned_block = p->resident_block;
   }
@@ -220,13 +222,13 @@ static int ensure_beta(bccb_plan_s* p, int iters) {
 
 // Enqueue one cooperative solve on stream s (the right-hand side on the support
 // bins already in d_sup_rhs).  mode: RES_ISTA / RES_FISTA (kappa = mu tau; out_c
-// receives c^(T); the pruned form when the plan takes it) or RES_ADMM (kappa =
-// tau / rho, scale = rho / L; out_z, out_c).
+// receives c^(T)) or RES_ADMM (kappa = tau / rho, scale = rho / L; out_z, out_c),
+// each in the pruned form when the plan takes it.
 static int resident_enqueue(bccb_plan_s* p, int mode, int iters, float kappa, float rho, float scale,
                             const float2* init, float2* out_c, float2* out_z, hipStream_t s) {
   if (2 * static_cast<long long>(iters) + 1 >= (1ll << 31)) return BCCB_E_UNSUPPORTED;   // barrier epochs
-  const bool pruned = mode != RES_ADMM && resident_pruned_on(p);
-  if (pruned) mode = (mode == RES_FISTA) ? RES_PRUNED_FISTA : RES_PRUNED_ISTA;
+  const bool pruned = resident_pruned_on(p);
+  if (pruned) mode = mode == RES_FISTA ? RES_PRUNED_FISTA : (mode == RES_ADMM ? RES_PRUNED_ADMM : RES_PRUNED_ISTA);
   const int groups = pruned ? resident_pruned_groups(p) : p->resident_groups;
   if (mode == RES_FISTA || mode == RES_PRUNED_FISTA) BCCB_TRY(ensure_beta(p, iters));
   // a fresh tag per solve: the sync words keep what earlier solves wrote (all below it)

@@ -12,9 +12,9 @@
 // columns), barrier, row phase (IDFT_rows, the proximal / momentum / ADMM
 // update of eqs. (9)-(15), DFT_rows on the owned rows), barrier.  The
 // arithmetic is that of the two-pass path at E = 4 element for element.
-// A pruned form for ISTA / FISTA (k_resident_pruned, further down) exchanges
-// only per-group parts of the spectrum at the support bins and needs one
-// barrier per iteration.
+// A pruned form of all three solvers (k_resident_pruned, further down)
+// exchanges only per-group parts of the spectrum at the support bins and needs
+// one barrier per iteration.
 //
 // The launch is cooperative (all G workgroups co-resident, or the launch
 // fails), and every barrier wait is bounded in wall-clock time: a workgroup
@@ -355,10 +355,11 @@ int resident_launch_m(const ResidentArgs& a, int check_only, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Pruned form (ISTA / FISTA).  By eq. (21) Omega and DFT2(b) vanish off the
-// support bins, so (I - mu G) z + mu b = z + IDFT2(V) with V = m . DFT2(z) + r
-// living on the support (m = -mu Omega / L, r = mu S, as the pruned column
-// pass).  Group g owns RPC = 1024 / L1 rows (G = L2 / RPC groups of 256
+// Pruned form.  By eq. (21) Omega and DFT2(b) vanish off the support bins, so
+// (I - mu G) z + mu b = z + IDFT2(V) with V = m . DFT2(z) + r living on the
+// support (m = -mu Omega / L, r = mu S, as the pruned column pass).  ADMM's
+// x-update (G + rho I)^-1 (b + rho (z - v)) differs from z - v only on the
+// support as well (the inverse is 1 / rho off it); see the ADMM note below.  Group g owns RPC = 1024 / L1 rows (G = L2 / RPC groups of 256
 // threads) with z_t and c_{t-1} in registers.  DFT2(z_t) at a support bin
 // (k1, k2) is a sum over the rows of DFT_rows(z_t)[l2][k1] e^{-j 2 pi k2 l2 / L2};
 // each group publishes the part of that sum over its own rows for every bin
@@ -370,6 +371,20 @@ int resident_launch_m(const ResidentArgs& a, int check_only, hipStream_t s) {
 //   (zero off the kept columns); u = z_t + that; c_t = S_kappa(u);
 //   z_{t+1} = c_t + beta_t (c_t - c_{t-1}); DFT_rows(z_{t+1}) at the kept
 //   columns; this group's parts of DFT2(z_{t+1}) at the bins -> xy; barrier.
+// ADMM (eqs. (13)-(15)): with rho << Omega the scaled dual v grows to about
+// S / rho on the support modes, far above x, so x formed as (z - v) plus a
+// support correction would cancel in FP32.  The dual is therefore split as
+// v_t = u_t + IDFT2(Psi_t): Psi (nsup values, the same in every group, since
+// every group forms the same sums in the same order) carries the support part
+// and u_t = z_{t-1} - z_t the rest.  With Y = DFT2(z_t - u_t) at the bins,
+//   V'_j = (S_j - rho Psi_j - Omega_j Y_j / L) / (Omega_j + rho),
+//   x_{t+1} = z_t - u_t + IDFT2(V'),  Psi_{t+1} = Psi_t + V',
+//   z_{t+1} = S_{tau/rho}(x_{t+1} + v_t) = S_{tau/rho}(z_t + IDFT2(Psi_{t+1})),
+//   u_{t+1} = z_t - z_{t+1},
+// which is the update of eqs. (13)-(15) rearranged: only small quantities meet
+// in a subtraction, and one row transform per iteration remains (x itself is
+// formed at the last iteration only).  Registers hold z_t and z_{t-1}; the
+// published parts are those of DFT2(2 z_t - z_{t-1}).
 // The column transforms of the passes become these sums, so the results agree
 // with the pruned passes to FP32 rounding, not element for element.
 // ---------------------------------------------------------------------------
@@ -380,11 +395,14 @@ struct ResidentPrunedShape {
   static constexpr int T1 = N1 / E;
   static constexpr int RPC = NT / T1;   // rows per group
   static constexpr int AR1 = fft_areas(N1, E), FA1 = fft_area(N1);
-  // dynamic LDS in bytes for ncs kept columns and nsup support bins
-  static constexpr size_t lds_bytes(int ncs, int nsup) {
+  // dynamic LDS in bytes for ncs kept columns and nsup support bins (ADMM keeps
+  // Psi, V' and -rho / (Omega + rho) per bin as well)
+  static constexpr size_t lds_bytes(int ncs, int nsup, bool admm) {
+    const size_t na = admm ? static_cast<size_t>(nsup) : 0;
     return sizeof(float2) * (static_cast<size_t>(N1) + static_cast<size_t>(RPC) * AR1 * FA1 +
-                             static_cast<size_t>(RPC) * nsup + static_cast<size_t>(RPC) * ncs + 2 * static_cast<size_t>(nsup)) +
-           sizeof(float) * nsup + sizeof(int) * (static_cast<size_t>(nsup) + 2 * static_cast<size_t>(ncs));
+                             static_cast<size_t>(RPC) * nsup + static_cast<size_t>(RPC) * ncs + 2 * static_cast<size_t>(nsup) +
+                             2 * na) +
+           sizeof(float) * (nsup + na) + sizeof(int) * (static_cast<size_t>(nsup) + 2 * static_cast<size_t>(ncs));
   }
 };
 
@@ -402,6 +420,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   constexpr int E = S::E, NT = S::NT, T1 = S::T1, RPC = S::RPC;
   using FR = Stockham<N1, E, (T1 <= 64)>;
   constexpr bool kFista = (MODE == RES_PRUNED_FISTA);
+  constexpr bool kAdmm = (MODE == RES_PRUNED_ADMM);
   constexpr int PB = 16;   // parts loaded per thread and batch
   extern __shared__ float2 lds[];
   __shared__ int s_ok;
@@ -410,10 +429,14 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   float2* area = tw1 + N1;                              // RPC rows x AR1 exchange areas
   float2* cw = area + RPC * S::AR1 * S::FA1;            // [RPC][nsup] e^{+j 2 pi k2_j l2 / L2}, owned rows
   float2* xk = cw + RPC * nsup;                         // [RPC][ncs] owned rows' kept forward spectra
-  float2* vs = xk + RPC * ncs;                          // [nsup] V_j
+  const int na = kAdmm ? nsup : 0;
+  float2* vs = xk + RPC * ncs;                          // [nsup] V_j (ADMM: Psi_{t+1})
   float2* br = vs + nsup;                               // [nsup] r_j
-  float* bm = reinterpret_cast<float*>(br + nsup);      // [nsup] m_j
-  int* bslot = reinterpret_cast<int*>(bm + nsup);       // [nsup] kept slot of bin j
+  float2* ps = br + nsup;                               // [na] ADMM: Psi_j
+  float2* vd = ps + na;                                 // [na] ADMM: V'_j of the last iteration
+  float* bm = reinterpret_cast<float*>(vd + na);        // [nsup] m_j
+  float* bq = bm + nsup;                                // [na] ADMM: -rho / (Omega_j + rho)
+  int* bslot = reinterpret_cast<int*>(bq + na);         // [nsup] kept slot of bin j
   int* sbeg = bslot + nsup;                             // [ncs] bins of slot s: sbeg[s] .. send[s]
   int* send = sbeg + ncs;
 
@@ -430,7 +453,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
 
   for (int j = tid; j < N1; j += NT) tw1[j] = a.tw1[j];
   {
-    const float cb = a.coef[0].y;   // -mu / L
+    const float cb = kAdmm ? -a.scale / a.rho : a.coef[0].y;   // -1 / L (ADMM), -mu / L
     for (int s2 = tid; s2 < ncs; s2 += NT) {
       const int k1 = a.scol[s2];
       const int j0 = k1 >= 0 ? a.sup_ptr[k1] : 0, j1 = k1 >= 0 ? a.sup_ptr[k1 + 1] : 0;
@@ -439,8 +462,17 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
       for (int j = j0; j < j1; ++j) {
         const SupEntry en = a.sup[j];
         bslot[j] = s2;
-        bm[j] = cb * en.omega;
-        br[j] = a.sup_rhs[j];
+        if constexpr (kAdmm) {
+          const float d = 1.f / (en.omega + a.rho);
+          const float2 r = a.sup_rhs[j];
+          bm[j] = cb * en.omega * d;
+          br[j] = make_float2(r.x * d, r.y * d);
+          bq[j] = -a.rho * d;
+          ps[j] = zero;
+        } else {
+          bm[j] = cb * en.omega;
+          br[j] = a.sup_rhs[j];
+        }
         for (int r2 = 0; r2 < RPC; ++r2) {
           const float2 w = a.tw2[(en.k2 * (g * RPC + r2)) & (N2 - 1)];
           cw[r2 * nsup + j] = make_float2(w.x, -w.y);
@@ -471,11 +503,12 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
     }
   };
 
-  // z_1 = c_0 (warm start or zero), c_{-1} = c_0 as the passes take it
+  // z_1 = c_0 (warm start or zero), c_{-1} = c_0 as the passes take it; ADMM
+  // starts from z = v = 0 (u = 0, Psi = 0) and keeps z_t, z_{t-1} in z[], cp[]
   float2 z[E], cp[E];
   {
     float2 v[E];
-    if (a.init) {
+    if (a.init && !kAdmm) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = a.init[base + FR::in_index(rt, e)];
     } else {
@@ -501,6 +534,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   const float kappa = a.kappa;
   for (int t = 1; t <= a.iters; ++t) {
     const float beta = kFista ? a.beta[t - 1] : 0.f;
+    const bool last = (t == a.iters);
     // Z_j: the G parts of every bin, Q threads per bin (adjacent lanes), each
     // over the groups q, q + Q, ... in order, then a fixed butterfly
     for (int j0 = 0; j0 < nsup; j0 += NT / Q) {
@@ -522,11 +556,21 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
         const float ox = __shfl_xor(acc.x, off, 64), oy = __shfl_xor(acc.y, off, 64);
         acc = (q & off) ? make_float2(ox + acc.x, oy + acc.y) : make_float2(acc.x + ox, acc.y + oy);
       }
-      if (q == 0 && j < nsup) vs[j] = make_float2(acc.x * bm[j] + br[j].x, acc.y * bm[j] + br[j].y);
+      if (q == 0 && j < nsup) {
+        if constexpr (kAdmm) {
+          const float2 p0 = ps[j];
+          const float2 vp = make_float2(br[j].x + bq[j] * p0.x + bm[j] * acc.x, br[j].y + bq[j] * p0.y + bm[j] * acc.y);
+          const float2 pn = cadd(p0, vp);
+          ps[j] = pn;
+          vs[j] = pn;
+          if (last) vd[j] = vp;
+        } else {
+          vs[j] = make_float2(acc.x * bm[j] + br[j].x, acc.y * bm[j] + br[j].y);
+        }
+      }
     }
     __syncthreads();
     // the owned rows' kept spectra of IDFT2(V) at this thread's positions
-    const bool last = (t == a.iters);
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -540,15 +584,43 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
     fft_inv<FR>(v, rt, tw1, rA, rB);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const float2 u = cadd(z[e], v[e]);
-      const float2 c = shrink(u, kappa);
-      if (last) a.out_c[base + FR::in_index(rt, e)] = c;
-      const float2 zn = kFista ? make_float2(c.x + beta * (c.x - cp[e].x), c.y + beta * (c.y - cp[e].y)) : c;
-      cp[e] = c;
-      z[e] = zn;
-      v[e] = zn;
+      if constexpr (kAdmm) {   // v[] = IDFT2(Psi_{t+1}): z_{t+1} = S(z_t + v[])
+        const float2 zo = z[e];
+        const float2 zz = shrink(cadd(zo, v[e]), kappa);
+        if (last) a.out_z[base + FR::in_index(rt, e)] = zz;
+        // at the end cp[] keeps z_t - u_t, the spatial part of x_{t+1}
+        cp[e] = last ? make_float2(2.f * zo.x - cp[e].x, 2.f * zo.y - cp[e].y) : zo;
+        z[e] = zz;
+        v[e] = make_float2(2.f * zz.x - zo.x, 2.f * zz.y - zo.y);   // z_{t+1} - u_{t+1}
+      } else {
+        const float2 u = cadd(z[e], v[e]);
+        const float2 c = shrink(u, kappa);
+        if (last) a.out_c[base + FR::in_index(rt, e)] = c;
+        const float2 zn = kFista ? make_float2(c.x + beta * (c.x - cp[e].x), c.y + beta * (c.y - cp[e].y)) : c;
+        cp[e] = c;
+        z[e] = zn;
+        v[e] = zn;
+      }
     }
-    if (last) break;
+    if (last) {
+      if constexpr (kAdmm) {
+        if (a.out_c) {   // x_T = z_{T-1} - u_{T-1} + IDFT2(V'_T)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            float2 acc = zero;
+            if (myslot[e] >= 0) {
+              const int s2 = myslot[e];
+              for (int j = sbeg[s2]; j < send[s2]; ++j) acc = cadd(acc, cmul(vd[j], cw[rr * nsup + j]));
+            }
+            v[e] = acc;
+          }
+          fft_inv<FR>(v, rt, tw1, rA, rB, true);
+#pragma unroll
+          for (int e = 0; e < E; ++e) a.out_c[base + FR::in_index(rt, e)] = cadd(cp[e], v[e]);
+        }
+      }
+      break;
+    }
     fft_fwd_after_inv<FR>(v, rt, tw1, rA, rB);
     publish(v);
     if (!resident_sync(a, g, ++epoch, &s_ok)) return;
@@ -562,7 +634,7 @@ int resident_launch_pt(const ResidentArgs& a, int check_only, hipStream_t s) {
   const int G = N2 / S::RPC;
   if (a.groups != G || G > kResidentMaxGroups) return -1;
   if (a.ncs < 1 || a.ncs > N1 / 2 || a.nsup < 1) return -1;
-  const size_t shm = S::lds_bytes(a.ncs, a.nsup);
+  const size_t shm = S::lds_bytes(a.ncs, a.nsup, MODE == RES_PRUNED_ADMM);
   if (shm > 65536) return -1;
   const int spread = a.spread > 1 ? a.spread : 1;
   const auto kfn = k_resident_pruned<N1, N2, MODE, NT>;
@@ -574,9 +646,11 @@ int resident_launch_pt(const ResidentArgs& a, int check_only, hipStream_t s) {
   if (static_cast<long>(per_cu) * cus < static_cast<long>(G) * spread) return -1;
   if (check_only) return 0;
   if (!a.xy || !a.tw1 || !a.tw2 || !a.sup_ptr || !a.sup || !a.sup_rhs || !a.sync || !a.flag || !a.scol ||
-      !a.colslot || !a.coef || !a.out_c || a.iters < 1)
+      !a.colslot || a.iters < 1)
     return -1;
   if (MODE == RES_PRUNED_FISTA && !a.beta) return -1;
+  if (MODE != RES_PRUNED_ADMM && (!a.coef || !a.out_c)) return -1;
+  if (MODE == RES_PRUNED_ADMM && (!a.out_z || !(a.rho > 0.f))) return -1;
   void* args[] = {const_cast<ResidentArgs*>(&a)};
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(G * spread), dim3(S::NT), args,
                                                   static_cast<unsigned>(shm), s);
@@ -604,6 +678,7 @@ int resident_launch_nn(int mode, const ResidentArgs& a, int check_only, hipStrea
     case RES_ADMM: return resident_launch_m<N1, N2, RES_ADMM>(a, check_only, s);
     case RES_PRUNED_ISTA: return resident_launch_p<N1, N2, RES_PRUNED_ISTA>(a, check_only, s);
     case RES_PRUNED_FISTA: return resident_launch_p<N1, N2, RES_PRUNED_FISTA>(a, check_only, s);
+    case RES_PRUNED_ADMM: return resident_launch_p<N1, N2, RES_PRUNED_ADMM>(a, check_only, s);
     default: return -1;
   }
 }

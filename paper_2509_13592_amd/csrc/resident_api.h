@@ -13,11 +13,12 @@ enum ResidentMode {
   RES_ISTA = 0,
   RES_FISTA = 1,
   RES_ADMM = 2,
-  // pruned forms (ISTA / FISTA): only the kept spectral columns of the row
-  // spectra cross between groups, and every group rebuilds the spectrum on the
-  // support bins from all of them, so an iteration needs one grid barrier
+  // pruned forms: each group's part of the spectrum at the support bins is all
+  // that crosses between groups, and every group adds up all the parts, so an
+  // iteration needs one grid barrier
   RES_PRUNED_ISTA = 3,
   RES_PRUNED_FISTA = 4,
+  RES_PRUNED_ADMM = 5,
 };
 
 constexpr int kResidentMaxChunks = 4;   // 1024-point chunks per workgroup and phase (256 threads)

@@ -22,6 +22,16 @@ B = pytest.importorskip("paper_2509_13592_amd.bccb")
 
 OBJ_TOL = 1e-5
 SHORT_TOL = 1e-5
+U32 = 2.0 ** -24   # FP32 unit roundoff
+
+
+def admm_tol(iters, L):
+    """Bound on one complex64 ADMM path's relative error after `iters` iterations: each
+    iteration applies (G + rho I)^-1 once through transforms of relative error about
+    u log2 L, and the scaled dual of eq. (15) is the running sum of the x-iterates while
+    z stays at zero, so those errors add up instead of dying out."""
+    return iters * U32 * np.log2(L)
+
 
 GEOMS = {
     "tiny": lambda: S.tiny_scene(3),                    # 32 x 32: a single workgroup
@@ -170,12 +180,34 @@ def test_resident_autotune_and_profile():
     plan.close()
 
 
+def _admm_pruned_vs_passes(plan, P, y, rho, cfg):
+    """ADMM's (z, x) through the pruned cooperative form and through the full passes
+    against the FP64 oracle, each within admm_tol, and against each other."""
+    L = P.op.L
+    for iters in (1, 2, 37):
+        zr, xr = P.admm(rho, iters)
+        ref = np.concatenate([zr, xr])
+        nr = max(np.linalg.norm(ref), 1e-30)
+        plan.set_config(**cfg)
+        assert plan.support_columns()[1] == 2
+        got = _solve(plan, "admm", y, P.tau, iters, rho)
+        plan.set_config(resident_groups=0, support_columns=0)
+        pas = _solve(plan, "admm", y, P.tau, iters, rho)
+        eg, ep = np.linalg.norm(got - ref) / nr, np.linalg.norm(pas - ref) / nr
+        d = np.linalg.norm(got - pas) / nr
+        tol = admm_tol(iters, L)
+        print(f"  admm iters={iters}: pruned cooperative vs FP64 {eg:.1e}, passes vs FP64 {ep:.1e}, "
+              f"between them {d:.1e} (bound {tol:.1e} per path)", flush=True)
+        assert eg <= tol and ep <= tol and d <= 2 * tol, (iters, eg, ep, d)
+
+
 @pytest.mark.parametrize("block", [256, 512])
 @pytest.mark.parametrize("geom", ["tiny", "sweep512", "rect", "paper"])
 def test_resident_pruned_matches_passes(geom, block):
     """The pruned cooperative form (per-group parts of DFT2 at the support bins exchanged,
     every group adding all of them, one barrier per iteration) against the pruned and the
-    full passes, cold and warm started, and the oracle's objective over a long run."""
+    full passes, cold and warm started, and the oracle's objective over a long run; ADMM
+    (no pruned passes) against the full passes."""
     sc = GEOMS[geom]()
     P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
@@ -215,19 +247,56 @@ def test_resident_pruned_matches_passes(geom, block):
         rel = abs(P.objective(g) - Fr) / Fr
         print(f"  {solver} 300 iterations: rel F = {rel:.2e}", flush=True)
         assert rel <= OBJ_TOL
-    # ADMM on the same configuration takes the full cooperative form
+    # ADMM in the pruned form: (z, x) against the FP64 oracle and the full passes (each
+    # path within admm_tol of FP64, so two paths within twice that), and the objective
     rho = float(np.count_nonzero(sc.mask))
-    z = _np(plan.admm(y, tau, rho, 37))
-    plan.set_config(resident_groups=0)
-    zr = _np(plan.admm(y, tau, rho, 37))
-    assert np.linalg.norm(z - zr) <= SHORT_TOL * max(np.linalg.norm(zr), 1e-30)
+    _admm_pruned_vs_passes(plan, P, y, rho, dict(support_columns=1, resident_groups=G, resident_spread=sp,
+                                                 resident_block=block))
+    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block)
+    g = _np(plan.admm(y, tau, rho, 300))
+    ref = P.admm(rho, 300)[0]
+    Fr = P.objective(ref)
+    rel = abs(P.objective(g) - Fr) / Fr
+    print(f"  admm 300 iterations: rel F = {rel:.2e}", flush=True)
+    assert rel <= OBJ_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("geom,seed,iters", [("tiny", 0, 200), ("paper", 2, 500)])
+def test_resident_pruned_admm_small_rho(geom, seed, iters):
+    """ADMM with rho = 1, far below Omega on the support, where the scaled dual grows to about
+    S / rho on the support modes: the pruned form keeps that part of the dual as spectral
+    coefficients, so x is never formed by cancelling large terms (forming it as (z - v) plus a
+    support correction missed the objective bound on the first scene).  z and x against FP64
+    within admm_tol, the objective of z within OBJ_TOL."""
+    sc = S.tiny_scene(seed) if geom == "tiny" else S.paper_scale_scene(seed)
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    G, sp = _shapes(plan)[0]
+    plan.set_config(support_columns=1, resident_groups=G, resident_spread=sp)
+    if plan.support_columns()[1] != 2:
+        plan.close()
+        pytest.skip("the pruned cooperative form does not fit this geometry")
+    y = B.to_device(sc.y)
+    z, x = plan.admm(y, P.tau, 1.0, iters, want_c=True)
+    z, x = _np(z), _np(x)
+    zr, xr = P.admm(1.0, iters)
+    tol = admm_tol(iters, P.op.L)
+    ez = np.linalg.norm(z - zr) / max(np.linalg.norm(zr), 1e-30)
+    ex = np.linalg.norm(x - xr) / max(np.linalg.norm(xr), 1e-30)
+    Fr = P.objective(zr)
+    rel = abs(P.objective(z) - Fr) / Fr
+    print(f"case {geom} seed {seed} rho 1 iters {iters}: z vs FP64 {ez:.1e}, x vs FP64 {ex:.1e}, rel F {rel:.1e} "
+          f"(bound {tol:.1e})", flush=True)
+    assert ez <= tol and ex <= tol and rel <= OBJ_TOL
     plan.close()
 
 
 @pytest.mark.parametrize("block", [256, 512])
 def test_resident_pruned_largest_grid(block):
     """The pruned cooperative form at 512 x 512 (256 or 128 groups, 256 support bins in
-    32 kept columns) against the pruned and the full passes over short runs."""
+    32 kept columns) against the pruned and the full passes over short runs (ADMM against
+    the full passes)."""
     sc = GEOMS["big"]()
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     G, sp = _shapes(plan)[0]
@@ -250,6 +319,9 @@ def test_resident_pruned_largest_grid(block):
             dp, df = np.linalg.norm(got - ref_p) / nr, np.linalg.norm(got - ref_f) / nr
             print(f"  {solver} iters={iters}: vs pruned passes {dp:.1e}, vs full passes {df:.1e}", flush=True)
             assert dp <= SHORT_TOL and df <= SHORT_TOL, (solver, iters, dp, df)
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, dense=None)
+    _admm_pruned_vs_passes(plan, P, B.to_device(sc.y), float(np.count_nonzero(sc.mask)),
+                           dict(support_columns=1, resident_groups=G, resident_spread=sp, resident_block=block))
     plan.close()
 
 
@@ -267,10 +339,9 @@ def test_resident_repeated_solves_identical(geom, block):
     tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
     for support_columns, G in ((1, shapes[0][0]), (0, shapes[-1][0])):
         plan.set_config(support_columns=support_columns, resident_groups=G, resident_spread=1, resident_block=block)
-        for solver in ("ista", "fista"):
-            fn = plan.fista if solver == "fista" else plan.ista
+        for solver in ("ista", "fista", "admm"):
             for iters in (2, 9):
-                outs = [_np(fn(y, tau, iters)) for _ in range(4)]
+                outs = [_solve(plan, solver, y, tau, iters, 40.0) for _ in range(4)]
                 same = all(np.array_equal(outs[0], o) for o in outs[1:])
                 print(f"case {geom} block {block} support_columns {support_columns} G {G} {solver} {iters}: "
                       f"mode {plan.support_columns()[1]}, identical {same}", flush=True)
