@@ -355,9 +355,13 @@ int lasso_solve_dense(bccb_dense_t dense, int solver, const bccb_c32* y, float t
  *   support bins (Omega and DFT2(b) vanish elsewhere, eq. (21)): the column pass
  *   transforms only the spectral columns holding support bins, the row pass
  *   exchanges only those columns with it and rebuilds z in the spatial domain
- *   from c^(t-1), c^(t-2) (kept per row as above).  Taken when those columns
- *   are at most L1/2 (after padding to a multiple of 4) and L1 >= 8; otherwise
- *   the full passes run.  0 = always the full passes.
+ *   from c^(t-1), c^(t-2) (kept per row as above).  ADMM takes the same passes
+ *   with its scaled dual split as v_t = (z_{t-1} - z_t) + IDFT2(Psi_t), Psi on
+ *   the support bins and updated by the column pass (eqs. (13)-(15) rearranged
+ *   so that x is never formed by cancelling the large support part of v), and
+ *   one more pair of passes forms x^(T) when it is asked for.  Taken when those
+ *   columns are at most L1/2 (after padding to a multiple of 4) and L1 >= 8;
+ *   otherwise the full passes run.  0 = always the full passes.
  *   prow_elems, prow_rows_per_block: the pruned row pass's shape (as the row
  *   pass; rows * (2 L1 + ...) must fit the 64 KB of LDS a workgroup can hold);
  *   pcol_elems, pcol_cols_per_block: the pruned column pass's shape (columns

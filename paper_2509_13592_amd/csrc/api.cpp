@@ -74,6 +74,8 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_beta);
   dfree(p->d_sync);
   dfree(p->d_rpart);
+  dfree(p->d_psi);
+  dfree(p->d_vlast);
   dfree(p->d_coef);
   dfree(p->d_red);
   dfree(p->d_flag);
@@ -503,6 +505,8 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
                             hipMemset(p->d_pdense[i], 0, p->L * sizeof(float2)) != hipSuccess))
         rc = BCCB_E_DEVICE;
     }
+    if (rc == BCCB_OK) rc = dmalloc(&p->d_psi, p->nsup);
+    if (rc == BCCB_OK) rc = dmalloc(&p->d_vlast, p->nsup);
     if (rc == BCCB_OK && (hipMemcpy(p->d_scol, p->h_scol.data(), p->ncs * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
                           hipMemcpy(p->d_colslot, colslot.data(), L1 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
                           hipMemset(p->d_xyc, 0, static_cast<size_t>(L2) * p->ncs * sizeof(float2)) != hipSuccess))
@@ -648,6 +652,22 @@ static SlotBuf pruned_buf(bccb_plan_s* p, int i, float2* out) {
   return b;
 }
 
+// The pruned column pass's arguments over the plan's kept columns.
+static ColArgs pruned_col_args(bccb_plan_s* p) {
+  ColArgs c;
+  c.xy = p->d_xyc;
+  c.sup_ptr = p->d_sup_ptr;
+  c.sup = p->d_sup;
+  c.sup_rhs = p->d_sup_rhs;
+  c.coef = p->d_coef;
+  c.tw = p->d_tw2;
+  c.L1 = p->L1;
+  c.ncols = p->ncs;
+  c.ldx = p->ncs;
+  c.scol = p->d_scol;
+  return c;
+}
+
 static int enqueue_pruned(bccb_plan_s* p, int mode, int iters, float kappa, const float2* init, float2* out) {
   hipStream_t st = p->stream;
   const bool fista = (mode == ROW_FISTA);
@@ -669,18 +689,8 @@ static int enqueue_pruned(bccb_plan_s* p, int mode, int iters, float kappa, cons
   BCCB_TRY(run_loop(p, key, [&](hipStream_t s) -> int {
     double alpha = 1.0;
     float beta_prev = 0.f;
+    const ColArgs c = pruned_col_args(p);
     for (int t = 1; t <= iters; ++t) {
-      ColArgs c;
-      c.xy = p->d_xyc;
-      c.sup_ptr = p->d_sup_ptr;
-      c.sup = p->d_sup;
-      c.sup_rhs = p->d_sup_rhs;
-      c.coef = p->d_coef;
-      c.tw = p->d_tw2;
-      c.L1 = p->L1;
-      c.ncols = p->ncs;
-      c.ldx = p->ncs;
-      c.scol = p->d_scol;
       BCCB_TRY(kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_AFFINE, c, s)));
       const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
       const float beta = fista ? static_cast<float>((alpha - 1.0) / alpha_next) : 0.f;
@@ -703,6 +713,74 @@ static int enqueue_pruned(bccb_plan_s* p, int mode, int iters, float kappa, cons
     return BCCB_OK;
   }));
   return BCCB_OK;
+}
+
+// Pruned ADMM passes (sparse support, kept columns only; iters >= 1).  The scaled
+// dual is split as v_t = u_t + IDFT2(Psi_t) with u_t = z_{t-1} - z_t and Psi on
+// the support bins (eqs. (13)-(15) rearranged, so that x is never formed by
+// cancelling the large support part of v; the cooperative form does the same):
+// the column pass turns Y = DFT2(z_t - u_t) at the bins into V' and Psi_{t+1} =
+// Psi_t + V', and the pruned row pass with beta_prev = 0 and beta = 1 gives
+// z_{t+1} = S_{tau/rho}(z_t + IDFT2(Psi_{t+1})) and the next DFT_rows of
+// 2 z_{t+1} - z_t.  z_t lives in SlotBuf t mod 3 (buffer 0's dense rows in the
+// scratch grid, so the outputs alias no state); x_T = 2 z_{T-1} - z_{T-2} +
+// IDFT2(V'_T) is one more column and row pass (beta_prev = 1, kappa = 0).
+static int enqueue_pruned_admm(bccb_plan_s* p, int iters, float kappa, float rho, float2* zo, float2* co) {
+  hipStream_t st = p->stream;
+  auto buf = [&](int i) { return pruned_buf(p, i, p->d_tmp); };
+  // z_0 = z_{-1} = 0 (empty rows), Psi_0 = 0, DFT_rows(z_0 - u_0) = 0
+  BCCB_TRY(kern(launch_fill_int(p->d_pcnt[0], p->L2, 0, st)));
+  BCCB_TRY(kern(launch_fill_int(p->d_pcnt[2], p->L2, 0, st)));
+  BCCB_TRY(kern(launch_fill(p->d_psi, p->nsup, st)));
+  RowArgs f;
+  f.xy = p->d_xyc;
+  f.src = nullptr;
+  f.flag = p->d_flag;
+  f.colslot = p->d_colslot;
+  f.ncs = p->ncs;
+  BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED_FWD, f, st));
+  ColArgs c = pruned_col_args(p);
+  c.psi = p->d_psi;
+  c.vlast = p->d_vlast;
+  c.rho = rho;
+  c.scale = static_cast<float>(1.0 / static_cast<double>(p->L));
+  const unsigned long long key[8] = {static_cast<unsigned long long>(ROW_ADMM), static_cast<unsigned long long>(iters),
+                                     reinterpret_cast<unsigned long long>(zo), fbits(kappa),
+                                     reinterpret_cast<unsigned long long>(co), fbits(rho), 1, 4};
+  return run_loop(p, key, [&](hipStream_t s) -> int {
+    for (int t = 1; t <= iters; ++t) {
+      BCCB_TRY(kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_ADMM, c, s)));
+      RowArgs a;
+      a.xy = p->d_xyc;
+      a.colslot = p->d_colslot;
+      a.ncs = p->ncs;
+      a.b1 = buf((t - 1) % 3);
+      a.b0 = buf(t % 3);
+      a.out_c = zo;
+      a.kappa = kappa;
+      a.beta = 1.f;
+      a.beta_prev = 0.f;
+      a.last = (t == iters);
+      BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED, a, s));
+    }
+    if (co) {
+      BCCB_TRY(kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_EXPAND, c, s)));
+      RowArgs a;
+      a.xy = p->d_xyc;
+      a.colslot = p->d_colslot;
+      a.ncs = p->ncs;
+      a.b1 = buf((iters - 1) % 3);
+      a.b2 = buf((iters + 1) % 3);   // (iters - 2) mod 3
+      a.b0 = buf(iters % 3);
+      a.out_c = co;
+      a.kappa = 0.f;
+      a.beta = 0.f;
+      a.beta_prev = 1.f;
+      a.last = true;
+      BCCB_TRY(row_pass_on(p, p->cfg_rowp, ROW_PRUNED, a, s));
+    }
+    return BCCB_OK;
+  });
 }
 
 // The iterations of an ISTA (mode ROW_ISTA) or FISTA (ROW_FISTA) solve with
@@ -807,6 +885,10 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
     BCCB_TRY(resident_enqueue(p, RES_ADMM, iters, tau / rho, rho,
                               static_cast<float>(static_cast<double>(rho) / static_cast<double>(p->L)), nullptr, co, zo,
                               p->stream));
+    return end_call(p);
+  }
+  if (sparse && pruned_on(p) && iters > 0) {
+    BCCB_TRY(enqueue_pruned_admm(p, iters, tau / rho, rho, zo, co));
     return end_call(p);
   }
   BCCB_TRY(kern(launch_fill(p->d_state, p->L, p->stream)));  // v^(0) = 0
@@ -968,21 +1050,6 @@ static RowArgs pruned_work_args(bccb_plan_s* p) {
   a.beta = 0.5f;
   a.beta_prev = 0.5f;
   return a;
-}
-
-static ColArgs pruned_col_args(bccb_plan_s* p) {
-  ColArgs c;
-  c.xy = p->d_xyc;
-  c.sup_ptr = p->d_sup_ptr;
-  c.sup = p->d_sup;
-  c.sup_rhs = p->d_sup_rhs;
-  c.coef = p->d_coef;
-  c.tw = p->d_tw2;
-  c.L1 = p->L1;
-  c.ncols = p->ncs;
-  c.ldx = p->ncs;
-  c.scol = p->d_scol;
-  return c;
 }
 
 int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
@@ -1156,17 +1223,26 @@ int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, dou
                                    : (sparse ? COL_SPARSE_AFFINE : COL_FILTER_AFFINE);
   if (sparse) a.rhs = nullptr;
   const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
-  // ISTA / FISTA on a plan whose solves take the pruned passes: time those
-  const bool pr = solver != 2 && pruned_on(p);
+  // a plan whose solves take the pruned passes: time those (ADMM: beta = 1, the
+  // column pass updating the support part of the dual)
+  const bool pr = pruned_on(p);
   RowArgs ap = pr ? pruned_work_args(p) : RowArgs();
-  if (pr && solver == 0) {
+  if (pr && solver != 1) {
     ap.b2 = SlotBuf();
-    ap.beta = ap.beta_prev = 0.f;
+    ap.beta = solver == 2 ? 1.f : 0.f;
+    ap.beta_prev = 0.f;
   }
-  const ColArgs cp = pr ? pruned_col_args(p) : ColArgs();
+  ColArgs cp = pr ? pruned_col_args(p) : ColArgs();
+  if (pr && solver == 2) {
+    cp.psi = p->d_psi;
+    cp.vlast = p->d_vlast;
+    cp.rho = 1.f;
+    cp.scale = scale;
+  }
+  const int pcol_mode = solver == 2 ? COL_PRUNED_ADMM : COL_PRUNED_AFFINE;
   if (hipEventRecord(e0, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
   for (int i = 0; i < reps && rc == BCCB_OK; ++i)
-    rc = pr ? kern(launch_col(p->L2, p->cfg_colp, COL_PRUNED_AFFINE, cp, p->stream))
+    rc = pr ? kern(launch_col(p->L2, p->cfg_colp, pcol_mode, cp, p->stream))
             : col_pass(p, col_mode, p->d_xy, p->d_coef, 1.f, scale);
   if (rc == BCCB_OK && hipEventRecord(e1, p->stream) != hipSuccess) rc = BCCB_E_DEVICE;
   for (int i = 0; i < reps && rc == BCCB_OK; ++i)

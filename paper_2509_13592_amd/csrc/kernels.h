@@ -92,6 +92,12 @@ enum ColMode {
   COL_PRUNED_AFFINE = 9,// kept columns only: m = 0 off the support, b Omega_j on it; r = rhs_j
   COL_PRUNED_CPLX = 10, // kept columns only, entries from `dil`: m = mulc[bin] - 1/L (complex),
                         // r = dscal[1] * inv_mu * rhs[orig] (0 for orig < 0)
+  // ADMM over the kept columns with the scaled dual split as v = u + IDFT2(Psi),
+  // Psi on the support bins (eqs. (13)-(15) rearranged; u and z stay spatial):
+  // Y = DFT_cols(xy); V'_j = (rhs_j - rho Psi_j - Omega_j scale Y_j) / (Omega_j + rho)
+  // (scale = 1/L); Psi_j += V'_j; vlast_j = V'_j; xy = IDFT_cols(Psi on the support, 0 off it)
+  COL_PRUNED_ADMM = 11,
+  COL_PRUNED_EXPAND = 12,  // kept columns only: xy = IDFT_cols(vlast on the support, 0 off it)
 };
 
 // One bin of a dilated support list: spectral row k2, and the entry of the
@@ -138,6 +144,9 @@ struct ColArgs {
   const DilEntry* dil = nullptr;
   const float* dscal = nullptr;
   float inv_mu = 1.f;
+  // COL_PRUNED_ADMM / COL_PRUNED_EXPAND: per support entry, indexed as sup_rhs
+  float2* psi = nullptr;         // Psi_j, read and updated (ADMM)
+  float2* vlast = nullptr;       // V'_j of the pass: written (ADMM), read (EXPAND)
 };
 
 // Spectral right-hand side on the support bins, per scene:

@@ -656,10 +656,11 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
 
   constexpr bool kSparse = (MODE == COL_SPARSE_AFFINE || MODE == COL_SPARSE_ADMM || MODE == COL_PRUNED_AFFINE);
   constexpr bool kDil = (MODE == COL_PRUNED_CPLX);
+  constexpr bool kPsi = (MODE == COL_PRUNED_ADMM || MODE == COL_PRUNED_EXPAND);
   constexpr bool kFwd = (MODE == COL_FWD || MODE == COL_FILTER_AFFINE || MODE == COL_FILTER_ADMM ||
-                         MODE == COL_FILTER_CPLX || kSparse || kDil);
+                         MODE == COL_FILTER_CPLX || kSparse || kDil || MODE == COL_PRUNED_ADMM);
   constexpr bool kInv = (MODE != COL_FWD);
-  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV && !kSparse && !kDil);
+  constexpr bool kMul = (MODE != COL_FWD && MODE != COL_INV && !kSparse && !kDil && !kPsi);
   constexpr bool kCplx = (MODE == COL_FILTER_CPLX);
 
   // all global loads first (iterate, spectral multiplier, twiddles)
@@ -667,6 +668,9 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
   if constexpr (kFwd) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::in_index(t, e)) * ldx];
+  } else if constexpr (MODE == COL_PRUNED_EXPAND) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = make_float2(0.f, 0.f);
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = g[static_cast<size_t>(F::out_index(t, e)) * ldx];
@@ -733,6 +737,40 @@ __global__ __launch_bounds__(256) void k_col(ColArgs a, int W) {
             const float d = 1.f / (en.omega + a.rho);
             const float m = a.scale * d;
             v[e] = make_float2(src[e].x * m + r.x * d, src[e].y * m + r.y * d);
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (kPsi) {
+    // the column carries Psi_{t+1} (ADMM) or vlast (EXPAND) on its support bins,
+    // zero elsewhere; each bin is held by one thread, which alone touches its entry
+    float2 src[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      src[e] = v[e];
+      v[e] = make_float2(0.f, 0.f);
+    }
+    const int* ptr = a.sup_ptr + scene * a.sup_ptr_stride + (k1 >= 0 ? k1 : 0);
+    const int j0 = ptr[0], j1 = k1 >= 0 ? ptr[1] : j0;   // padding columns: no entries
+    const size_t sb = static_cast<size_t>(scene) * a.sup_rhs_stride;
+    for (int j = j0; j < j1; ++j) {
+      const SupEntry en = a.sup[j];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (F::out_index(t, e) == en.k2) {
+          if constexpr (MODE == COL_PRUNED_EXPAND) {
+            v[e] = a.vlast[sb + j];
+          } else {
+            const float d = 1.f / (en.omega + a.rho);
+            const float om = en.omega * a.scale;
+            const float2 r = a.sup_rhs[sb + j], p0 = a.psi[sb + j];
+            const float2 vp = make_float2((r.x - a.rho * p0.x - om * src[e].x) * d, (r.y - a.rho * p0.y - om * src[e].y) * d);
+            const float2 pn = make_float2(p0.x + vp.x, p0.y + vp.y);
+            a.psi[sb + j] = pn;
+            a.vlast[sb + j] = vp;
+            v[e] = pn;
           }
         }
       }
@@ -825,8 +863,12 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
   constexpr int T = Stockham<N, E>::T;
   const int ncols = a.ncols ? a.ncols : a.L1;
   if (W < 1 || W * T > 256 || ncols % W != 0) return -1;
-  if ((mode == COL_PRUNED_AFFINE || mode == COL_PRUNED_CPLX) != (a.scol != nullptr)) return -1;
+  const bool pruned = mode == COL_PRUNED_AFFINE || mode == COL_PRUNED_CPLX || mode == COL_PRUNED_ADMM ||
+                      mode == COL_PRUNED_EXPAND;
+  if (pruned != (a.scol != nullptr)) return -1;
   if (mode == COL_PRUNED_CPLX && (!a.dil || !a.dscal || !a.mulc || !a.sup_rhs)) return -1;
+  if ((mode == COL_PRUNED_ADMM || mode == COL_PRUNED_EXPAND) && (!a.sup_ptr || !a.sup || !a.vlast)) return -1;
+  if (mode == COL_PRUNED_ADMM && (!a.psi || !a.sup_rhs || !(a.rho > 0.f))) return -1;
   const int blocks = (ncols / W) * a.nscenes;
   if (blocks <= 0) return 0;
   const size_t shm = (static_cast<size_t>(fft_areas(N, E)) * W * fft_area(N) + N) * sizeof(float2);
@@ -845,6 +887,8 @@ int col_launch_e(int mode, const ColArgs& a, int W, hipStream_t s) {
     case COL_SPARSE_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_SPARSE_ADMM>), grid, block, shm, s, a, W); break;
     case COL_PRUNED_AFFINE: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_AFFINE>), grid, block, shm, s, a, W); break;
     case COL_PRUNED_CPLX: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_CPLX>), grid, block, shm, s, a, W); break;
+    case COL_PRUNED_ADMM: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_ADMM>), grid, block, shm, s, a, W); break;
+    case COL_PRUNED_EXPAND: hipLaunchKernelGGL((k_col<N, E, COL_PRUNED_EXPAND>), grid, block, shm, s, a, W); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;

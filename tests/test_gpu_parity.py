@@ -349,7 +349,8 @@ def test_support_columns_path_matches_full_path(geom):
     """The pruned iteration (kept spectral columns only, identity part in the spatial
     domain) and the full passes solve the same problem: both within tolerance of the
     oracle, and of each other, for ISTA and FISTA, cold and warm started, at iteration
-    counts from 0 up; a plan whose support spans too many columns runs the full passes."""
+    counts from 0 up, and for ADMM at two rho; a plan whose support spans too many
+    columns runs the full passes."""
     sc = {"tiny": S.tiny_scene(7),
           "ragged": S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(17, 1, 0)),
           "wide": S.custom_scene(20, 6, 40, 32, 8, K=2, snr_db=20, seed=(18, 1, 0)),
@@ -385,6 +386,57 @@ def test_support_columns_path_matches_full_path(geom):
                     else:            # long runs: FP32 trajectories drift apart, the objective does not
                         Fr = P.objective(ref)
                         assert abs(P.objective(res[sc_on]) - Fr) / Fr <= OBJ_TOL
+    # ADMM: the pruned passes keep the support part of the scaled dual as spectral
+    # coefficients; (z, x) of both paths against FP64 within the bound of a complex64 run
+    for rho, iters in ((4.0, 1), (4.0, 2), (4.0, 9), (4.0, 150), (1.0, 150)):
+        res = {}
+        for sc_on in (1, 0):
+            plan.set_config(support_columns=sc_on)
+            z, x = plan.admm(y, P.tau, rho, iters, want_c=True)
+            res[sc_on] = np.concatenate([_np(z), _np(x)])
+        zr, xr = P.admm(rho, iters)
+        ref = np.concatenate([zr, xr])
+        nr = max(np.linalg.norm(ref), 1e-30)
+        errs = {k: np.linalg.norm(v - ref) / nr for k, v in res.items()}
+        tol = admm_tol(iters, sc.L1 * sc.L2)
+        print(f"  admm rho={rho} iters={iters}: pruned vs FP64 {errs[1]:.1e}, full vs FP64 {errs[0]:.1e} "
+              f"(bound {tol:.1e})", flush=True)
+        assert errs[1] <= tol and errs[0] <= tol
+        Fr = P.objective(zr)
+        if Fr > 0 and np.any(zr):
+            assert abs(P.objective(res[1][:sc.L1 * sc.L2]) - Fr) / Fr <= OBJ_TOL
+    plan.close()
+
+
+def admm_tol(iters, L):
+    """Bound on one complex64 ADMM run's relative error after `iters` iterations: each
+    iteration applies (G + rho I)^-1 once through transforms of relative error about
+    u log2 L (u = 2^-24), and the scaled dual of eq. (15) is a running sum of the
+    x-iterates while z stays at zero, so those errors add up instead of dying out."""
+    return iters * 2.0 ** -24 * np.log2(L)
+
+
+@pytest.mark.parametrize("idx", [0, 3])
+def test_pruned_admm_small_rho(idx):
+    """ADMM with rho = 1 on the tiny scenes through the pruned passes: with rho far below
+    Omega the scaled dual grows to about S / rho on the support modes; the pruned passes
+    keep that part as spectral coefficients, so x never comes from cancelling it (the
+    form that did -- x as (z - v) plus a support correction -- missed the objective bound
+    on the first scene)."""
+    sc = S.tiny_scene(idx)
+    P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y)
+    plan = B.Plan(sc.mask, sc.L1, sc.L2)
+    plan.set_config(support_columns=1)
+    assert plan.support_columns()[1] >= 1
+    y = B.to_device(sc.y)
+    z, x = plan.admm(y, P.tau, 1.0, 200, want_c=True)
+    z, x = _np(z), _np(x)
+    zr, xr = P.admm(1.0, 200)
+    ez = np.linalg.norm(z - zr) / max(np.linalg.norm(zr), 1e-30)
+    ex = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    rel = abs(P.objective(z) - P.objective(zr)) / P.objective(zr)
+    print(f"case tiny {idx} rho 1: z vs FP64 {ez:.1e}, x vs FP64 {ex:.1e}, rel F {rel:.1e}", flush=True)
+    assert ez <= admm_tol(200, P.op.L) and ex <= admm_tol(200, P.op.L) and rel <= OBJ_TOL
     plan.close()
 
 
