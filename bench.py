@@ -43,8 +43,8 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "a4b9efa963ff0433": {
-        "resident_pruned": {"bytes_per_iteration": 183651,
+    "64505f03c4d40e7c": {
+        "resident_pruned": {"bytes_per_iteration": 183664,
                             "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 512,
                                        "support_columns": 1}},
     },
