@@ -516,9 +516,10 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
   if (rc == BCCB_OK) rc = dmalloc(&p->d_sync, kResidentSyncWords);
   if (rc == BCCB_OK && hipMemset(p->d_sync, 0, kResidentSyncWords * sizeof(unsigned long long)) != hipSuccess)
     rc = BCCB_E_DEVICE;
-  // the pruned cooperative form's per-group parts of DFT2 at the support bins
+  // the pruned cooperative form's per-group parts of DFT2 at the support bins (two
+  // buffers, by iteration parity)
   if (rc == BCCB_OK && p->prune_ok && resident_pruned_groups(p, 256) > 0)   // the most groups
-    rc = dmalloc(&p->d_rpart, static_cast<size_t>(resident_pruned_groups(p, 256)) * p->nsup);
+    rc = dmalloc(&p->d_rpart, 2 * static_cast<size_t>(resident_pruned_groups(p, 256)) * p->nsup);
   if (rc == BCCB_OK) {
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;

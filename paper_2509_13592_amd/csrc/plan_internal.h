@@ -83,7 +83,7 @@ struct bccb_plan_s {
   unsigned long long* d_sync = nullptr;
   unsigned long long res_solve = 0;   // cooperative solves enqueued so far (their tags)
   long long wall_ticks_per_s = 0;
-  float2* d_rpart = nullptr;       // pruned form: [groups][nsup] per-group parts of DFT2 at the bins
+  float2* d_rpart = nullptr;       // pruned form: [2][groups][nsup] per-group parts of DFT2 at the bins
   float2* d_psi = nullptr;         // pruned ADMM passes: [nsup] support part Psi of the scaled dual
   float2* d_vlast = nullptr;       // pruned ADMM passes: [nsup] the last column pass's V' per bin
   int resident_block = 256;        // threads per group of the pruned cooperative form (256 or 512)

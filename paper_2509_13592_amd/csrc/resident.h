@@ -54,7 +54,12 @@ struct ResidentShape {
 // raises the flag, and an abort word holding the tag ends the wait), acquires
 // for the block (its waves share one CU and its L1) and the block meets again.
 // Words are never reset: whatever an earlier solve left is below this solve's
-// tag.  Returns false when the solve is being abandoned.
+// tag.  Returns false when the solve is being abandoned.  kFences = false leaves
+// out the agent-scope release and acquire (the L2 write-back and invalidate): for
+// a caller whose exchanged data are written with store_through (complete once
+// the wait above returns) and read back only with agent-scope loads issued after
+// the barrier, which see the coherent copy as the arrival words do.
+template <bool kFences = true>
 __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsigned k, int* s_ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -63,7 +68,7 @@ __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsi
     unsigned long long* arrive = a.sync + kResidentArriveOffset;
     const unsigned long long want = a.tag | k;
     if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if constexpr (kFences) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(arrive + static_cast<size_t>(g) * kResidentArriveStride, want, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -116,11 +121,18 @@ __device__ __forceinline__ bool resident_sync(const ResidentArgs& a, int g, unsi
         if (!keep_waiting()) break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if constexpr (kFences) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tid == 0) *s_ok = ok;
   }
   __syncthreads();
   return *s_ok != 0;
+}
+
+// Agent-scope load of exchanged data: reads the coherent copy, never a stale
+// line of this die's L2.
+__device__ __forceinline__ float2 load_coherent(float2* p) {
+  return __builtin_bit_cast(float2, __hip_atomic_load(reinterpret_cast<unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
 }
 
 // Store of exchanged data, written through to the agent-coherent level at once
@@ -449,7 +461,11 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   float2* rB = rA + (S::AR1 - 1) * S::FA1;
   const size_t base = static_cast<size_t>(row) * N1;
   const float2 zero = make_float2(0.f, 0.f);
-  float2* part = a.xy;   // [G][nsup] parts of DFT2(z) at the bins, one row block per group
+  // [2][G][nsup] parts of DFT2(z) at the bins, one row block per group, in the
+  // buffer of the iteration's parity: a group can refill a buffer only after the
+  // next barrier, which every reader of its previous contents has passed
+  float2* const parts = a.xy;
+  const size_t pstride = static_cast<size_t>(G) * nsup;
 
   for (int j = tid; j < N1; j += NT) tw1[j] = a.tw1[j];
   {
@@ -486,7 +502,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
 
   // this group's parts of DFT2(v) at the bins, from the kept forward row spectra
   // v[] of its rows (forward-output layout); the block meets inside
-  auto publish = [&](const float2* v) {
+  auto publish = [&](const float2* v, float2* part) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (myslot[e] >= 0) xk[rr * ncs + myslot[e]] = v[e];
@@ -525,16 +541,17 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
     if (!ok) __hip_atomic_fetch_or(a.flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();   // twiddles and bin tables in place
     fft_fwd<FR>(v, rt, tw1, rA, rB, false);
-    publish(v);
+    publish(v, parts + pstride);   // read at iteration 1
   }
   unsigned epoch = 1;
-  if (!resident_sync(a, g, epoch, &s_ok)) return;
+  if (!resident_sync<false>(a, g, epoch, &s_ok)) return;
 
   const int Q = resident_part_lanes(nsup, NT);
   const float kappa = a.kappa;
   for (int t = 1; t <= a.iters; ++t) {
     const float beta = kFista ? a.beta[t - 1] : 0.f;
     const bool last = (t == a.iters);
+    float2* const part = parts + (t & 1) * pstride;
     // Z_j: the G parts of every bin, Q threads per bin (adjacent lanes), each
     // over the groups q, q + Q, ... in order, then a fixed butterfly
     for (int j0 = 0; j0 < nsup; j0 += NT / Q) {
@@ -547,7 +564,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
         for (int k = 0; k < PB; ++k) {
           const int gg = g0 + k * Q;
           pv[k] = zero;
-          if (gg < G) pv[k] = part[static_cast<size_t>(gg) * nsup + jj];   // no load for groups past G
+          if (gg < G) pv[k] = load_coherent(part + static_cast<size_t>(gg) * nsup + jj);   // none past G
         }
 #pragma unroll
         for (int k = 0; k < PB; ++k) acc = cadd(acc, pv[k]);
@@ -622,8 +639,8 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
       break;
     }
     fft_fwd_after_inv<FR>(v, rt, tw1, rA, rB);
-    publish(v);
-    if (!resident_sync(a, g, ++epoch, &s_ok)) return;
+    publish(v, parts + ((t + 1) & 1) * pstride);
+    if (!resident_sync<false>(a, g, ++epoch, &s_ok)) return;
   }
 }
 

@@ -29,6 +29,7 @@ constexpr int kResidentSyncWords = kResidentArriveOffset + kResidentMaxGroups * 
 
 struct ResidentArgs {
   float2* xy = nullptr;             // [L2][L1] row spectra exchanged between the phases
+                                    // (pruned forms: [2][groups][nsup] per-group parts)
   const float2* init = nullptr;     // ISTA/FISTA warm start c^(0) (nullable = 0)
   float2* out_c = nullptr;          // ISTA/FISTA c^(T); ADMM c^(T) (nullable)
   float2* out_z = nullptr;          // ADMM z^(T)
