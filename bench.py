@@ -43,9 +43,9 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "64505f03c4d40e7c": {
-        "resident_pruned": {"bytes_per_iteration": 183664,
-                            "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 512,
+    "75f002369e8c1b4f": {
+        "resident_pruned": {"bytes_per_iteration": 42729,
+                            "launch": {"resident_groups": 32, "resident_spread": 8, "resident_block": 512,
                                        "support_columns": 1}},
     },
 }
@@ -54,14 +54,14 @@ TRAFFIC = {
 def _traffic_for(kh, launch):
     """(bytes per iteration, the launch shape they were counted on) for the path the solve runs
     (cooperative, pruned or full passes), or (None, None) when the device sources changed since
-    the count or none was taken for that path."""
+    the count, none was taken for that path, or it was taken on another launch shape."""
     if launch.get("resident_groups"):
         path = "resident_pruned" if launch.get("support_columns") else "resident"
     else:
         path = "pruned" if launch.get("support_columns") else "full"
     t = TRAFFIC.get(kh, {}).get(path)
-    if not t:
-        return None, None
+    if not t or any(launch.get(k) != v for k, v in t["launch"].items()):
+        return None, None   # another launch shape moves other bytes (e.g. one die's L2 or all eight)
     return t["bytes_per_iteration"], t["launch"]
 
 
