@@ -79,10 +79,6 @@ struct bccb_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = -1;
-  // one stream per size class (default priority) and the events that fork and join them
-  std::vector<hipStream_t> cls_streams;
-  std::vector<hipEvent_t> cls_events;
-  hipEvent_t fork_event = nullptr;
 };
 
 namespace {
@@ -91,9 +87,6 @@ void batch_free(bccb_batch_s* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  for (hipStream_t cs : b->cls_streams) (void)hipStreamDestroy(cs);
-  for (hipEvent_t ev : b->cls_events) (void)hipEventDestroy(ev);
-  if (b->fork_event) (void)hipEventDestroy(b->fork_event);
   for (BatchClass& c : b->cls) {
     for (void* p : {static_cast<void*>(c.d_omega), static_cast<void*>(c.d_coef), static_cast<void*>(c.d_kscale),
                     static_cast<void*>(c.d_xy), static_cast<void*>(c.d_rhs), static_cast<void*>(c.d_c),
@@ -256,31 +249,9 @@ int fista_loop_class(BatchClass& c, int iters, hipStream_t s) {
   return BCCB_OK;
 }
 
-// The iterations of every class: with several classes each class's loop goes on
-// a stream of its own, forked from and joined back into s (captured as parallel
-// branches of one graph), so the classes' kernels overlap instead of queueing.
+// The iterations of every class, one class after the other on stream s.
 int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
-  const int nc = static_cast<int>(b->cls.size());
-  if (nc == 1) return fista_loop_class(b->cls[0], iters, s);
-  if (static_cast<int>(b->cls_streams.size()) != nc) {
-    for (int i = static_cast<int>(b->cls_streams.size()); i < nc; ++i) {
-      hipStream_t cs = nullptr;
-      hipEvent_t ev = nullptr;
-      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return BCCB_E_DEVICE;
-      b->cls_streams.push_back(cs);
-      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BCCB_E_DEVICE;
-      b->cls_events.push_back(ev);
-    }
-    if (!b->fork_event && hipEventCreateWithFlags(&b->fork_event, hipEventDisableTiming) != hipSuccess)
-      return BCCB_E_DEVICE;
-  }
-  BCCB_HIP(hipEventRecord(b->fork_event, s));
-  for (int i = 0; i < nc; ++i) {
-    BCCB_HIP(hipStreamWaitEvent(b->cls_streams[i], b->fork_event, 0));
-    BCCB_TRY(fista_loop_class(b->cls[i], iters, b->cls_streams[i]));
-    BCCB_HIP(hipEventRecord(b->cls_events[i], b->cls_streams[i]));
-    BCCB_HIP(hipStreamWaitEvent(s, b->cls_events[i], 0));
-  }
+  for (BatchClass& c : b->cls) BCCB_TRY(fista_loop_class(c, iters, s));
   return BCCB_OK;
 }
 
