@@ -304,15 +304,16 @@ def dense_run(B, plan, y, tau, iters=5):
             "build_s": round(t_build, 3), "iters_timed": iters}
 
 
-def large_admm_run(B, S, iters=300, reps=3):
-    """Single 1024^2 scene, ADMM rho = 0.5, 300 iterations."""
+def large_admm_run(B, S, iters=300, reps=3, launch=None):
+    """Single 1024^2 scene, ADMM rho = 0.5, 300 iterations (launch: a pinned plan
+    configuration instead of autotuning)."""
     import numpy as np
     import torch
     sc = S.large_admm_scene(0)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
     y = B.to_device(sc.y)
     tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
-    tuned = plan.autotune(reps=20)
+    tuned = plan.set_config(**launch) if launch else plan.autotune(reps=20)
     out = plan.grid()
     plan.admm(y, tau, 0.5, iters, z_out=out)
     torch.cuda.synchronize()
@@ -377,11 +378,12 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
-    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned"],
+    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned", "large"],
                     default="all",
                     help="subsets: the single-scene solve only, the batched workloads only, a uniform "
                          "256^2 batch only (profiling), a plain 1 GiB device copy (counter calibration), "
-                         "the paper's regular-vs-fast sweep, or learned-vs-plain (--learned-scenes)")
+                         "the paper's regular-vs-fast sweep, learned-vs-plain (--learned-scenes), or the "
+                         "1024^2 ADMM scene (--launch pins its shape)")
     ap.add_argument("--batch-scenes", type=int, default=4096)
     ap.add_argument("--launch", type=str, default=None,
                     help="JSON plan configuration for the single-scene solve instead of autotuning "
@@ -418,6 +420,9 @@ def main():
         return
     if args.only == "learned":
         print(json.dumps({"learned_vs_plain": learned_run(B, S, args.learned_scenes)}))
+        return
+    if args.only == "large":
+        print(json.dumps({"large_admm": large_admm_run(B, S, launch=json.loads(args.launch) if args.launch else None)}))
         return
     if args.only == "batch256":
         dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
