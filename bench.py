@@ -35,10 +35,10 @@ ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration p
 # figure does not apply and `traffic` is reported as null.
 TRAFFIC = {
     # profiles/fista_passes_256_single_rocprofv3.md (FETCH_SIZE x 2 + WRITE_SIZE, KiB per dispatch)
-    "2cf614d578f2cd8b": {
-        "full": {"bytes_per_iteration": int((297.5 + 559.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
+    "89879c138cba15d1": {
+        "full": {"bytes_per_iteration": int((302.0 + 554.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
                  "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2}},
-        "pruned": {"bytes_per_iteration": int((187.7 + 172.4) * 2 * 1024 + (58.2 + 64.0) * 1024),
+        "pruned": {"bytes_per_iteration": int((176.9 + 177.3) * 2 * 1024 + (64.0 + 53.4) * 1024),
                    "launch": {"prow_elems": 4, "prow_rows_per_block": 2, "pcol_elems": 4, "pcol_cols_per_block": 2}},
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
