@@ -51,6 +51,31 @@ TRAFFIC = {
 }
 
 
+# Counted HBM bytes per grid point of one late FISTA iteration of a batch (pruned row pass +
+# pruned column pass, FETCH_SIZE x 2 + WRITE_SIZE), keyed by the kernel code and the class's
+# launch shape (row E, rows per block, column E, columns per block) they were taken on.
+BATCH_TRAFFIC = {
+    # profiles/fista_pruned_passes_256_batch_rocprofv3.md: 256 paper-scale scenes, default shapes
+    "89879c138cba15d1": {(16, 8, 16, 16): 4.9},
+}
+
+
+def pruned_bytes_per_iteration(L1, L2, ncs, row_nnz):
+    """Algorithmic bytes of one pruned FISTA iteration of one scene (the form the batches run).
+
+    Kept row spectra (complex64, ncs of the L1 spectral columns, L2 rows): the column pass reads
+    and writes them, the row pass reads them and writes the next iteration's, 4 x 8 ncs L2.
+    Iterate: the row pass reads c_{t-1} and c_{t-2} and writes c_t, each row as a 4-byte count
+    plus a 2-byte index and an 8-byte value per nonzero while it has at most L1/8 nonzeros, else
+    as the dense row (8 L1).  row_nnz: nonzeros per row of the iterate (any shape, L2 rows per
+    scene); the final iterate's counts stand in for every iteration (early iterations are denser).
+    """
+    import numpy as np
+    nnz = np.asarray(row_nnz).reshape(-1)
+    per_row = np.where(nnz <= L1 // 8, 4 + 10 * nnz, 4 + 8 * L1)
+    return 32 * ncs * L2 + 3 * int(per_row.sum())
+
+
 def _traffic_for(kh, launch):
     """(bytes per iteration, the launch shape they were counted on) for the path the solve runs
     (cooperative, pruned or full passes), or (None, None) when the device sources changed since
@@ -244,14 +269,26 @@ def _batch_rate(B, scenes, iters, reps, tune=True):
         batch.fista(ys, taus, iters, outs=outs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    classes = [{"L1": L1, "L2": L2, "scenes": n,
-                "launch": dict(zip(("row_E", "rows_per_block", "col_E", "cols_per_block", "pruned",
-                                    "columns_transformed"), cfg))}
-               for (L1, L2, n), cfg in zip(batch.classes(), batch.class_configs())]
+    classes = []
+    algo = 0
+    for (L1, L2, n), cfg in zip(batch.classes(), batch.class_configs()):
+        launch = dict(zip(("row_E", "rows_per_block", "col_E", "cols_per_block", "pruned", "columns_transformed"),
+                          cfg))
+        members = [i for i, sc in enumerate(scenes) if (sc.L1, sc.L2) == (L1, L2)]
+        if launch["pruned"]:
+            b_all = sum(pruned_bytes_per_iteration(L1, L2, launch["columns_transformed"],
+                                                   (outs[i].reshape(L2, L1) != 0).sum(dim=1).cpu().numpy())
+                        for i in members)
+        else:
+            b_all = ALGO_BYTES_PER_POINT["fista"] * L1 * L2 * len(members)
+        b = b_all // max(1, len(members))
+        algo += b_all
+        classes.append({"L1": L1, "L2": L2, "scenes": n, "launch": launch,
+                        "algorithmic_bytes_per_scene_iteration": int(b)})
     batch.close()
     for p in plans:
         p.close()
-    return dt, classes
+    return dt, classes, algo
 
 
 def batched_runs(args):
@@ -264,22 +301,33 @@ def batched_runs(args):
     scenes = [S.batched_scene(i) for i in range(n)]
     pts = sum(sc.L1 * sc.L2 for sc in scenes)
     iters = 300
-    dt, classes = _batch_rate(B, scenes, iters, reps=3)
-    algo = ALGO_BYTES_PER_POINT["fista"] * pts * iters
+    dt, classes, algo = _batch_rate(B, scenes, iters, reps=3)
     out["uneven"] = {"workload": f"{n} scenes, grids 64^2/128^2/256^2 mixed, own masks, FISTA {iters} iterations",
                      "scenes_per_s": round(n / dt, 1), "scene_iters_per_s": round(n * iters / dt, 1),
-                     "s_per_solve": round(dt, 5), "classes": classes,
-                     "algorithmic_GBps": round(algo / dt / 1e9, 1),
-                     "frac_hbm_peak": round(algo / dt / 1e9 / HBM_PEAK_GBS, 4)}
+                     "s_per_solve": round(dt, 5), "classes": classes, **_batch_roofline(algo * iters, dt)}
     n2 = 1024
+    it2 = 100
     sc0 = [S.paper_scale_scene(i) for i in range(n2)]
-    dt2, _ = _batch_rate(B, sc0, 100, reps=3)
-    algo2 = ALGO_BYTES_PER_POINT["fista"] * 65536 * n2 * 100
-    out["uniform_256"] = {"workload": f"{n2} paper-scale 256^2 scenes, FISTA 100 iterations",
-                          "scene_iters_per_s": round(n2 * 100 / dt2, 1),
-                          "algorithmic_GBps": round(algo2 / dt2 / 1e9, 1),
-                          "frac_hbm_peak": round(algo2 / dt2 / 1e9 / HBM_PEAK_GBS, 4)}
+    dt2, cls2, algo2 = _batch_rate(B, sc0, it2, reps=3)
+    out["uniform_256"] = {"workload": f"{n2} paper-scale 256^2 scenes, FISTA {it2} iterations",
+                          "scene_iters_per_s": round(n2 * it2 / dt2, 1), "classes": cls2,
+                          **_batch_roofline(algo2 * it2, dt2)}
+    launch = cls2[0]["launch"]
+    key = (launch["row_E"], launch["rows_per_block"], launch["col_E"], launch["cols_per_block"])
+    counted = BATCH_TRAFFIC.get(_kernel_hash(), {}).get(key) if launch["pruned"] else None
+    out["uniform_256"]["counted_bytes_per_point"] = counted
+    out["uniform_256"]["frac_counted"] = (round(counted * 65536 * n2 * it2 / dt2 / 1e9 / HBM_PEAK_GBS, 4)
+                                          if counted else None)
     return out
+
+
+def _batch_roofline(algo_bytes, seconds):
+    """HBM fraction of a batched solve against the algorithmic bytes of the form it runs
+    (pruned_bytes_per_iteration, or 36 B per point for the full passes)."""
+    gbps = algo_bytes / seconds / 1e9
+    return {"algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4),
+            "bytes_model": "pruned classes: kept row spectra (4 x 8 B x columns x rows) + iterate rows in slot form "
+                           "(count + 10 B per nonzero, read twice, written once); full classes: 36 B per point"}
 
 
 def dense_run(B, plan, y, tau, iters=5):
@@ -425,8 +473,8 @@ def main():
         print(json.dumps({"large_admm": large_admm_run(B, S, launch=json.loads(args.launch) if args.launch else None)}))
         return
     if args.only == "batch256":
-        dt, classes = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
-                                  tune=not args.no_tune)
+        dt, classes, _ = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
+                                     tune=not args.no_tune)
         print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": args.batch_iters, "classes": classes}))
         return
     sc = S.paper_scale_scene(0)
@@ -491,12 +539,18 @@ def main():
                    "iters_per_step": T, "launch_config": tuned},
         "other_rates": {"ista_iters_per_s": round(side_steps * T / dt_i, 1),
                         "admm_iters_per_s": round(side_steps * T / dt_a, 1)},
-        "roofline": {"bound": "hbm", "kernel": kernel,
+        "roofline": {"bound": "latency" if resident else "hbm", "ceiling": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                     "traffic_counted_on": traffic_launch, **timing,
+                     "traffic_counted_on": traffic_launch,
+                     "frac_counted": (round(traffic / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+                                      if traffic else None), **timing,
                      "algorithmic_bytes_per_iteration": ALGO_BYTES_PER_POINT["fista"] * L,
-                     "note": "single 256^2 scene: 2.4 MB per iteration, cache resident and latency bound"},
+                     "note": ("single 256^2 scene, one cooperative launch per solve: each iteration waits on one "
+                              "grid barrier and one round trip of the exchanged spectra, the 2.4 MB of "
+                              "algorithmic traffic stays in the caches; frac = 36 B/pt algorithmic bytes, "
+                              "frac_counted = counted HBM bytes (traffic), both over the live iteration time")
+                             if resident else "single 256^2 scene, two passes per iteration"},
     }
     if args.only == "single":
         plan.close()

@@ -160,6 +160,23 @@ int bccb_objective_kkt(bccb_plan_t plan, const bccb_c32* y, float tau, const bcc
                        double* objective, double* r_kkt, double* max_e_over_tau);
 
 /*
+ * bccb_kkt -- the two monitors of a coefficient grid c under the names of the
+ *   call list: *r_kkt = ||e||_2 / ||D_s^H y||_2 (the LASSO stationarity defect
+ *   e of eq. (8) with the factor 1/2, as in bccb_objective_kkt) and *obj =
+ *   1/2 ||y - D_s c||^2 + tau ||c||_1.  Same arguments, checks and arithmetic as
+ *   bccb_objective_kkt; either output may be NULL.
+ */
+int bccb_kkt(bccb_plan_t plan, const bccb_c32* y, float tau, const bccb_c32* c, double* r_kkt, double* obj);
+
+/*
+ * bccb_plan_omega_device -- copy the plan's FP32 eigenvalue grid Omega (eq. (21),
+ *   [L2][L1], the same values bccb_plan_info returns to the host) into the
+ *   caller's device buffer omega_dev (L1*L2 floats), on the plan's stream;
+ *   returns after the copy.  BCCB_E_INVALID for a null plan or buffer.
+ */
+int bccb_plan_omega_device(bccb_plan_t plan, float* omega_dev);
+
+/*
  * Batched solves -- many independent snapshots, each with its own plan (its
  * own array mask and grid size; plans may repeat), solved together.
  *

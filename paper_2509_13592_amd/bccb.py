@@ -82,6 +82,8 @@ _SIGS = {
     "lasso_solve_fista": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
     "lasso_solve_admm": (_i, [_vp, _vp, _f, _f, _i, _vp, _vp]),
     "bccb_objective_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd, _pd]),
+    "bccb_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd]),
+    "bccb_plan_omega_device": (_i, [_vp, _vp]),
     "bccb_profile_passes": (_i, [_vp, _i, _i, _pd, _pd]),
     "bccb_profile_resident": (_i, [_vp, _i, _i, _i, _pd]),
     "bccb_plan_get_config": (_i, [_vp, _vp]),
@@ -134,24 +136,53 @@ def check(code: int, where: str) -> int:
     return code
 
 
-def _ptr(t) -> int | None:
+def _ptr(t, numel: int | None = None, what: str = "tensor") -> int | None:
+    """Device address of a contiguous complex64 GPU tensor of exactly `numel` elements.
+
+    Every size is checked here, before the library is called: an undersized output would
+    make the kernels write past its allocation."""
     if t is None:
         return None
     if not isinstance(t, torch.Tensor):
-        raise TypeError("expected a torch tensor")
-    if not t.is_cuda:
-        raise ValueError("tensor must live on the GPU")
+        raise TypeError(f"{what}: expected a torch tensor")
     if t.dtype != torch.complex64:
-        raise TypeError(f"expected complex64, got {t.dtype}")
+        raise TypeError(f"{what}: expected complex64, got {t.dtype}")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must live on the GPU")
     return t.data_ptr()
+
+
+def _ptrs(*specs) -> list:
+    """Addresses of several arguments, each (tensor or None, numel, name): every type and
+    size is checked before any device check, so a wrong size is always reported as one."""
+    for t, n, what in specs:
+        _check_host_side(t, n, what, torch.complex64)
+    return [_ptr(t, n, what) for t, n, what in specs]
+
+
+def _check_host_side(t, numel, what, dtype):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
 
 
 def _raw_ptr(t) -> int:
     """Device address of a contiguous GPU tensor of any dtype."""
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+    if not isinstance(t, torch.Tensor) or not t.is_contiguous():
         raise ValueError("expected a contiguous GPU tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
     return t.data_ptr()
 
 
@@ -195,6 +226,13 @@ class Plan:
         except Exception:
             pass
 
+    def _args(self, y, **grids):
+        """Addresses of a snapshot (complex64 [M]) and of coefficient grids (complex64
+        [L2][L1], None passes through), all sizes checked first."""
+        if y is None:
+            raise ValueError("y: a snapshot is required")
+        return _ptrs((y, self.M, "y"), *[(t, self.L, k) for k, t in grids.items()])
+
     def set_stream(self, stream: int):
         check(lib.bccb_set_stream(self._h, stream), "bccb_set_stream")
 
@@ -208,28 +246,33 @@ class Plan:
 
     def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         out = self.grid(y.device) if out is None else out
-        check(lib.bccb_adjoint(self._h, _ptr(y), _ptr(out)), "bccb_adjoint")
+        py, po = self._args(y, out=out)
+        check(lib.bccb_adjoint(self._h, py, po), "bccb_adjoint")
         return out
 
     def adjoint_maxabs(self, y: torch.Tensor) -> float:
         m = ctypes.c_double()
-        check(lib.bccb_adjoint_maxabs(self._h, _ptr(y), ctypes.byref(m)), "bccb_adjoint_maxabs")
+        (py,) = self._args(y)
+        check(lib.bccb_adjoint_maxabs(self._h, py, ctypes.byref(m)), "bccb_adjoint_maxabs")
         return m.value
 
     def gram_apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         out = self.grid(x.device) if out is None else out
-        check(lib.bccb_gram_apply(self._h, _ptr(x), _ptr(out)), "bccb_gram_apply")
+        px, po = _ptrs((x, self.L, "x"), (out, self.L, "out"))
+        check(lib.bccb_gram_apply(self._h, px, po), "bccb_gram_apply")
         return out
 
     def ista(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
         out = self.grid(y.device) if out is None else out
-        check(lib.lasso_solve_ista(self._h, _ptr(y), float(tau), int(iters), _ptr(c0), _ptr(out)),
+        py, pc, po = self._args(y, c0=c0, out=out)
+        check(lib.lasso_solve_ista(self._h, py, float(tau), int(iters), pc, po),
               "lasso_solve_ista")
         return out
 
     def fista(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
         out = self.grid(y.device) if out is None else out
-        check(lib.lasso_solve_fista(self._h, _ptr(y), float(tau), int(iters), _ptr(c0), _ptr(out)),
+        py, pc, po = self._args(y, c0=c0, out=out)
+        check(lib.lasso_solve_fista(self._h, py, float(tau), int(iters), pc, po),
               "lasso_solve_fista")
         return out
 
@@ -237,16 +280,30 @@ class Plan:
         z_out = self.grid(y.device) if z_out is None else z_out
         if want_c and c_out is None:
             c_out = self.grid(y.device)
-        check(lib.lasso_solve_admm(self._h, _ptr(y), float(tau), float(rho), int(iters), _ptr(z_out),
-                                   _ptr(c_out)), "lasso_solve_admm")
+        py, pz, pc = self._args(y, z_out=z_out, c_out=c_out)
+        check(lib.lasso_solve_admm(self._h, py, float(tau), float(rho), int(iters), pz, pc), "lasso_solve_admm")
         return (z_out, c_out) if want_c else z_out
 
     def objective_kkt(self, y, tau: float, c) -> tuple[float, float, float]:
         obj, r, mx = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        check(lib.bccb_objective_kkt(self._h, _ptr(y), float(tau), _ptr(c), ctypes.byref(obj), ctypes.byref(r),
+        py, pc = self._args(y, c=c)
+        check(lib.bccb_objective_kkt(self._h, py, float(tau), pc, ctypes.byref(obj), ctypes.byref(r),
                                      ctypes.byref(mx)), "bccb_objective_kkt")
         return obj.value, r.value, mx.value
 
+
+    def kkt(self, y, tau: float, c) -> tuple[float, float]:
+        """(r_kkt, objective) of c through bccb_kkt."""
+        r, obj = ctypes.c_double(), ctypes.c_double()
+        py, pc = self._args(y, c=c)
+        check(lib.bccb_kkt(self._h, py, float(tau), pc, ctypes.byref(r), ctypes.byref(obj)), "bccb_kkt")
+        return r.value, obj.value
+
+    def omega_device(self, out=None) -> torch.Tensor:
+        """The FP32 eigenvalue grid Omega [L2][L1] copied into a device tensor."""
+        out = torch.empty((self.L2, self.L1), dtype=torch.float32, device="cuda") if out is None else out
+        check(lib.bccb_plan_omega_device(self._h, _fptr(out, self.L, "out")), "bccb_plan_omega_device")
+        return out
 
     def get_config(self) -> dict:
         c = Config()
@@ -358,8 +415,12 @@ class Batch:
         n = self.n
         if outs is None:
             outs = [p.grid(ys[i].device) for i, p in enumerate(self.plans)]
-        ya = (_vp * n)(*[_ptr(t) for t in ys])
-        oa = (_vp * n)(*[_ptr(t) for t in outs])
+        if len(ys) != n or len(outs) != n or len(taus) != n:
+            raise ValueError(f"expected {n} snapshots, outputs and weights, got {len(ys)}, {len(outs)}, {len(taus)}")
+        ptrs = _ptrs(*[(t, p.M, f"ys[{i}]") for i, (t, p) in enumerate(zip(ys, self.plans))],
+                     *[(t, p.L, f"outs[{i}]") for i, (t, p) in enumerate(zip(outs, self.plans))])
+        ya = (_vp * n)(*ptrs[:n])
+        oa = (_vp * n)(*ptrs[n:])
         ta = (ctypes.c_float * n)(*[float(t) for t in taus])
         check(lib.lasso_solve_batch_fista(self._h, ya, ta, int(iters), oa), "lasso_solve_batch_fista")
         return outs
@@ -368,11 +429,13 @@ class Batch:
 LISTA_PER_LAYER = 52
 
 
-def _fptr(t):
+def _fptr(t, numel: int | None = None, what: str = "tensor"):
+    """Device address of a contiguous float32 GPU tensor of exactly `numel` elements."""
     if t is None:
         return None
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float32 GPU tensor")
+    _check_host_side(t, numel, what, torch.float32)
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must live on the GPU")
     return t.data_ptr()
 
 
@@ -392,6 +455,7 @@ class Lista:
         self.layers = layers
         self.max_batch = max_batch
         self._h = _vp()
+        self._batch = 0       # batch of the last forward (what lista_backward differentiates)
         check(lib.lista_create(plan.handle, layers, max_batch, 1 if train else 0, ctypes.byref(self._h)),
               "lista_create")
 
@@ -407,25 +471,52 @@ class Lista:
             pass
 
     @staticmethod
-    def _taus(tau):
-        arr = np.ascontiguousarray(np.asarray(tau, dtype=np.float32))
+    def _taus(tau, B):
+        arr = np.ascontiguousarray(np.asarray(tau, dtype=np.float32).reshape(-1))
+        if arr.size != B:
+            raise ValueError(f"taus: expected {B} weights, got {arr.size}")
         return arr, arr.ctypes.data
+
+    def _batch_of(self, ys):
+        if not isinstance(ys, torch.Tensor) or ys.dim() != 2 or ys.shape[1] != self.plan.M:
+            raise ValueError(f"ys: expected complex64 [batch][{self.plan.M}]")
+        B = int(ys.shape[0])
+        if not 1 <= B <= self.max_batch:
+            raise ValueError(f"ys: expected a batch of 1..{self.max_batch} scenes, got {B}")
+        return B
+
+    def _host_checks(self, params, grad=None, **grids):
+        """Every size of a learned call, checked before any device check."""
+        n = self.layers * LISTA_PER_LAYER
+        _check_host_side(params, n, "params", torch.float32)
+        _check_host_side(grad, n, "grad", torch.float32)
+        for k, (t, numel) in grids.items():
+            _check_host_side(t, numel, k, torch.complex64)
+
+    def _params(self, params, what="params"):
+        return _fptr(params, self.layers * LISTA_PER_LAYER, what)
 
     def forward(self, params, ys, taus, out=None):
         """ys: complex64 [batch][M] device; taus: host floats [batch]."""
-        B = ys.shape[0]
+        B = self._batch_of(ys)
         if out is None:
             out = torch.empty((B, self.plan.L2, self.plan.L1), dtype=torch.complex64, device=ys.device)
-        arr, tp = self._taus(taus)
-        check(lib.lista_forward(self._h, _fptr(params), _ptr(ys), tp, B, _ptr(out)), "lista_forward")
+        arr, tp = self._taus(taus, B)
+        self._host_checks(params, ys=(ys, B * self.plan.M), out=(out, B * self.plan.L))
+        check(lib.lista_forward(self._h, self._params(params), _ptr(ys, B * self.plan.M, "ys"), tp, B,
+                                _ptr(out, B * self.plan.L, "out")), "lista_forward")
+        self._batch = B
         return out
 
     def backward(self, params, labels, grad=None):
         if grad is None:
             grad = torch.zeros_like(params)
+        if self._batch < 1:
+            raise ValueError("backward needs a training-mode forward first")
         loss = ctypes.c_double()
-        check(lib.lista_backward(self._h, _fptr(params), _ptr(labels), _fptr(grad), ctypes.byref(loss)),
-              "lista_backward")
+        self._host_checks(params, grad=grad, labels=(labels, self._batch * self.plan.L))
+        check(lib.lista_backward(self._h, self._params(params), _ptr(labels, self._batch * self.plan.L, "labels"),
+                                 self._params(grad, "grad"), ctypes.byref(loss)), "lista_backward")
         return grad, loss.value
 
     def autotune(self, reps: int = 5):
@@ -435,15 +526,17 @@ class Lista:
     def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None, restart=False):
         """KKT-gated solve (params=None: plain FISTA from zero); restart=True restarts the
         fallback momentum instead of continuing the unrolled FISTA.  Returns (c, iters, rkkt, status)."""
-        B = ys.shape[0]
+        B = self._batch_of(ys)
         if out is None:
             out = torch.empty((B, self.plan.L2, self.plan.L1), dtype=torch.complex64, device=ys.device)
-        arr, tp = self._taus(taus)
+        arr, tp = self._taus(taus, B)
         iters = np.zeros(B, dtype=np.int32)
         rk = np.zeros(B, dtype=np.float64)
-        rc = check(lib.lista_solve(self._h, _fptr(params) if params is not None else None, _ptr(ys), tp, B,
+        self._host_checks(params, ys=(ys, B * self.plan.M), out=(out, B * self.plan.L))
+        rc = check(lib.lista_solve(self._h, self._params(params) if params is not None else None,
+                                   _ptr(ys, B * self.plan.M, "ys"), tp, B,
                                    float(kkt_target), int(check_every), int(max_iters), 1 if restart else 0,
-                                   _ptr(out),
+                                   _ptr(out, B * self.plan.L, "out"),
                                    iters.ctypes.data, rk.ctypes.data), "lista_solve")
         return out, iters, rk, rc
 
@@ -468,8 +561,12 @@ class Adam:
 
     def step(self, grad):
         self.t += 1
-        check(lib.lista_adam(_fptr(self.p), _fptr(grad), _fptr(self.m), _fptr(self.v), self.p.numel(), self.t,
-                             self.lr, self.b1, self.b2, self.eps, _fptr(self.lr_scale), current_stream()),
+        n = self.p.numel()
+        for t, what in ((grad, "grad"), (self.m, "m"), (self.v, "v"), (self.lr_scale, "lr_scale")):
+            _check_host_side(t, n, what, torch.float32)
+        check(lib.lista_adam(_fptr(self.p, n, "params"), _fptr(grad, n, "grad"), _fptr(self.m, n), _fptr(self.v, n),
+                             n, self.t, self.lr, self.b1, self.b2, self.eps, _fptr(self.lr_scale, n, "lr_scale"),
+                             current_stream()),
               "lista_adam")
 
 
@@ -495,11 +592,13 @@ class Dense:
 
     def apply(self, x, out=None):
         out = self.plan.grid(x.device) if out is None else out
-        check(lib.bccb_dense_apply(self._h, _ptr(x), _ptr(out)), "bccb_dense_apply")
+        px, po = _ptrs((x, self.plan.L, "x"), (out, self.plan.L, "out"))
+        check(lib.bccb_dense_apply(self._h, px, po), "bccb_dense_apply")
         return out
 
     def solve(self, solver: str, y, tau: float, iters: int, out=None):
         code = {"ista": 0, "fista": 1, "admm": 2}[solver]
         out = self.plan.grid(y.device) if out is None else out
-        check(lib.lasso_solve_dense(self._h, code, _ptr(y), float(tau), int(iters), _ptr(out)), "lasso_solve_dense")
+        py, po = self.plan._args(y, out=out)
+        check(lib.lasso_solve_dense(self._h, code, py, float(tau), int(iters), po), "lasso_solve_dense")
         return out

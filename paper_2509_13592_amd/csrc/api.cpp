@@ -970,6 +970,17 @@ int bccb_objective_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c
   return rc;
 }
 
+int bccb_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c32* c, double* r_kkt, double* obj) {
+  return bccb_objective_kkt(p, y, tau, c, obj, r_kkt, nullptr);
+}
+
+int bccb_plan_omega_device(bccb_plan_t p, float* omega_dev) {
+  if (!p || !omega_dev) return BCCB_E_INVALID;
+  BCCB_HIP(hipMemcpyAsync(omega_dev, p->d_omega, p->L * sizeof(float), hipMemcpyDeviceToDevice, p->stream));
+  BCCB_HIP(hipStreamSynchronize(p->stream));
+  return BCCB_OK;
+}
+
 int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
   if (!p || !cfg) return BCCB_E_INVALID;
   cfg->row_elems = p->cfg_row.E;

@@ -9,10 +9,10 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
 #include <new>
 #include <vector>
 
+#include "batch_layout.h"
 #include "bccb.h"
 #include "kernels.h"
 #include "plan_internal.h"
@@ -270,22 +270,33 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
   b->stream = static_cast<hipStream_t>(stream);
   b->plans.assign(plans, plans + nscenes);
 
-  std::map<std::pair<int, int>, int> index;
+  // host tables of every scene (views of the plans), and the size classes
+  std::vector<std::pair<int, int>> grids(nscenes);
+  std::vector<bccb_layout::SceneTables<SupEntry>> tables(nscenes);
   for (int i = 0; i < nscenes; ++i) {
-    const auto key = std::make_pair(plans[i]->L1, plans[i]->L2);
-    auto it = index.find(key);
-    if (it == index.end()) {
-      BatchClass c;
-      c.L1 = key.first;
-      c.L2 = key.second;
-      c.L = static_cast<long>(c.L1) * c.L2;
-      c.tw1 = plans[i]->d_tw1;
-      c.tw2 = plans[i]->d_tw2;
-      index[key] = static_cast<int>(b->cls.size());
-      b->cls.push_back(c);
-      it = index.find(key);
-    }
-    b->cls[it->second].scenes.push_back(i);
+    const bccb_plan_s* p = plans[i];
+    grids[i] = std::make_pair(p->L1, p->L2);
+    bccb_layout::SceneTables<SupEntry>& t = tables[i];
+    t.L1 = p->L1;
+    t.L2 = p->L2;
+    t.sparse = sparse_on(p);
+    t.sup_ptr = &p->h_sup_ptr;
+    t.sup = &p->h_sup;
+    t.src_ptr = &p->h_src_ptr;
+    t.src = &p->h_src;
+    t.prune_ok = p->prune_ok;
+    t.nscol = p->nscol;
+    t.scol = &p->h_scol;
+  }
+  for (const bccb_layout::Class& g : bccb_layout::group_by_grid(grids)) {
+    BatchClass c;
+    c.L1 = g.L1;
+    c.L2 = g.L2;
+    c.L = static_cast<long>(c.L1) * c.L2;
+    c.tw1 = plans[g.scenes[0]]->d_tw1;
+    c.tw2 = plans[g.scenes[0]]->d_tw2;
+    c.scenes = g.scenes;
+    b->cls.push_back(c);
   }
   int rc = BCCB_OK;
   for (BatchClass& c : b->cls) {
@@ -294,27 +305,26 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
     default_batch_cfg(c);
     const size_t pts = static_cast<size_t>(c.n) * c.L;
     c.sparse = true;
-    for (int k = 0; k < c.n; ++k) c.sparse = c.sparse && sparse_on(plans[c.scenes[k]]);
+    for (int k = 0; k < c.n; ++k) c.sparse = c.sparse && tables[c.scenes[k]].sparse;
+    bccb_layout::Class members;
+    members.L1 = c.L1;
+    members.L2 = c.L2;
+    members.scenes = c.scenes;
     if (rc == BCCB_OK && !c.sparse) rc = dalloc(&c.d_omega, pts);  // sparse classes read Omega from the lists
     if (rc == BCCB_OK) rc = dalloc(&c.d_coef, c.n);
     if (rc == BCCB_OK) rc = dalloc(&c.d_kscale, c.n);
     if (rc == BCCB_OK) rc = dalloc(&c.d_xy, pts);
     if (rc == BCCB_OK && !c.sparse) rc = dalloc(&c.d_rhs, pts);
     if (rc == BCCB_OK && c.sparse) {
-      std::vector<int> sp, spp(1, 0), src;
-      std::vector<SupEntry> sup;
-      for (int k = 0; k < c.n; ++k) {
-        const bccb_plan_s* p = plans[c.scenes[k]];
-        const int eoff = static_cast<int>(sup.size());
-        const int soff = static_cast<int>(src.size());
-        c.entry_off.push_back(eoff);
-        c.max_entries = std::max(c.max_entries, p->nsup);
-        for (int v : p->h_sup_ptr) sp.push_back(v + eoff);
-        sup.insert(sup.end(), p->h_sup.begin(), p->h_sup.end());
-        for (size_t j = 1; j < p->h_src_ptr.size(); ++j) spp.push_back(p->h_src_ptr[j] + soff);
-        src.insert(src.end(), p->h_src.begin(), p->h_src.end());
-      }
-      rc = dalloc(&c.d_sup_ptr, sp.size());
+      bccb_layout::ClassSupport<SupEntry> cs;
+      if (!bccb_layout::concat_support(tables, members, &cs)) rc = BCCB_E_INVALID;
+      const std::vector<int>& sp = cs.sup_ptr;
+      const std::vector<int>& spp = cs.src_ptr;
+      const std::vector<int>& src = cs.src;
+      const std::vector<SupEntry>& sup = cs.sup;
+      c.entry_off = cs.entry_off;
+      c.max_entries = cs.max_entries;
+      if (rc == BCCB_OK) rc = dalloc(&c.d_sup_ptr, sp.size());
       if (rc == BCCB_OK) rc = dalloc(&c.d_sup, sup.size());
       if (rc == BCCB_OK) rc = dalloc(&c.d_src_ptr, spp.size());
       if (rc == BCCB_OK) rc = dalloc(&c.d_src, src.size());
@@ -341,23 +351,13 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
       c.sp_iter = true;
       while (!row_shape_ok(c.L1, c.cfg_row, true) && c.cfg_row.rpb > 1) c.cfg_row.rpb /= 2;
     }
-    c.can_prune = c.sparse;
-    for (int k = 0; k < c.n && c.can_prune; ++k) {
-      const bccb_plan_s* p = plans[c.scenes[k]];
-      c.can_prune = p->prune_ok;
-      c.ncs = std::max(c.ncs, p->ncs);
-    }
-    if (c.can_prune && c.ncs > c.L1 / 2) c.can_prune = false;
+    bccb_layout::KeptColumns kc;
+    c.can_prune = c.sparse && bccb_layout::kept_columns(tables, members, &kc) && kc.ncs <= c.L1 / 2;
+    if (c.can_prune) c.ncs = kc.ncs;
     if (rc == BCCB_OK && c.can_prune) {
       const size_t rows = static_cast<size_t>(c.n) * c.L2;
-      std::vector<int> scol(static_cast<size_t>(c.n) * c.ncs, -1), colslot(static_cast<size_t>(c.n) * c.L1, -1);
-      for (int k = 0; k < c.n; ++k) {
-        const bccb_plan_s* p = plans[c.scenes[k]];
-        for (int j = 0; j < p->nscol; ++j) {
-          scol[static_cast<size_t>(k) * c.ncs + j] = p->h_scol[j];
-          colslot[static_cast<size_t>(k) * c.L1 + p->h_scol[j]] = j;
-        }
-      }
+      const std::vector<int>& scol = kc.scol;
+      const std::vector<int>& colslot = kc.colslot;
       rc = dalloc(&c.d_xyc, rows * c.ncs);
       if (rc == BCCB_OK) rc = dalloc(&c.d_scol, scol.size());
       if (rc == BCCB_OK) rc = dalloc(&c.d_colslot, colslot.size());

@@ -10,7 +10,12 @@ B = pytest.importorskip("paper_2509_13592_amd.bccb")
 
 def test_header_symbols_exported():
     names = B.declared_functions()
-    assert "bccb_plan" in names and "lasso_solve_fista" in names
+    # the calls of the boundary: plan, adjoint, Gram product, the three solvers, the
+    # monitors, the batched solve and the learned network with its gated solve
+    for n in ("bccb_plan", "bccb_plan_destroy", "bccb_plan_info", "bccb_adjoint", "bccb_gram_apply",
+              "lasso_solve_ista", "lasso_solve_fista", "lasso_solve_admm", "lasso_solve_batch_fista",
+              "bccb_kkt", "lista_forward", "lista_backward", "lista_solve", "bccb_status_string"):
+        assert n in names, n
     for n in names:
         assert hasattr(B.lib, n), f"{n} declared in include/bccb.h but not exported"
 
@@ -52,6 +57,8 @@ def test_calls_reject_null_plan():
     assert B.lib.bccb_adjoint_maxabs(None, None, ctypes.byref(d)) == B.BCCB_E_INVALID
     assert B.lib.bccb_objective_kkt(None, None, 0.1, None, None, None, None) == B.BCCB_E_INVALID
     assert B.lib.bccb_plan_info(None, None, None, None) == B.BCCB_E_INVALID
+    assert B.lib.bccb_kkt(None, None, 0.1, None, None, None) == B.BCCB_E_INVALID
+    assert B.lib.bccb_plan_omega_device(None, None) == B.BCCB_E_INVALID
     assert B.lib.bccb_set_stream(None, None) == B.BCCB_E_INVALID
     assert B.lib.bccb_plan_destroy(None) == B.BCCB_OK
     assert B.lib.bccb_plan_support_columns(None, None, None) == B.BCCB_E_INVALID

@@ -55,3 +55,32 @@ def test_algorithmic_bytes(solver, bytes_per_point):
     # complex64 grids: ISTA reads c, mu b, Omega and writes c (8+8+4+8); FISTA also reads
     # c_{t-1} (+8); ADMM reads z, v, w, the multiplier and writes z, v (8*5+4)
     assert bench.ALGO_BYTES_PER_POINT[solver] == bytes_per_point
+
+
+def test_pruned_byte_model():
+    """Algorithmic bytes of one pruned FISTA iteration: kept spectra moved four times, iterate
+    rows as slot rows (count + index + value) while sparse and as dense rows otherwise."""
+    import numpy as np
+    L1 = L2 = 256
+    ncs = 16
+    empty = bench.pruned_bytes_per_iteration(L1, L2, ncs, np.zeros(L2, int))
+    assert empty == 32 * ncs * L2 + 3 * 4 * L2
+    one = np.zeros(L2, int)
+    one[3] = 5
+    assert bench.pruned_bytes_per_iteration(L1, L2, ncs, one) == empty + 3 * 50
+    dense = np.full(L2, L1, int)
+    assert bench.pruned_bytes_per_iteration(L1, L2, ncs, dense) == 32 * ncs * L2 + 3 * L2 * (4 + 8 * L1)
+    # a row just over L1/8 nonzeros is stored dense
+    edge = np.zeros(L2, int)
+    edge[0] = L1 // 8 + 1
+    assert bench.pruned_bytes_per_iteration(L1, L2, ncs, edge) == empty + 3 * 8 * L1
+    # never more than the full passes move per point (48 B with the row-spectral exchange)
+    assert bench.pruned_bytes_per_iteration(L1, L2, ncs, dense) <= 48 * L1 * L2 * 2
+
+
+def test_batch_fraction_is_a_fraction():
+    """A rate at exactly the HBM peak gives frac 1; the bytes model is stated on the line."""
+    r = bench._batch_roofline(bench.HBM_PEAK_GBS * 1e9 * 2.0, 2.0)
+    assert abs(r["frac_hbm_peak"] - 1.0) < 1e-9 and "bytes_model" in r
+    r = bench._batch_roofline(1e9, 1.0)
+    assert 0 < r["frac_hbm_peak"] < 1

@@ -113,12 +113,16 @@ def test_backward_matches_oracle():
     lab = B.to_device(np.stack(labels).astype(np.complex64))
     g, loss = net.backward(pt, lab)
     g = g.cpu().numpy().astype(np.float64)
-    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
-    print(f"case lista backward: loss {loss:.6e} vs {loss_ref:.6e}; max grad err / max grad = {err:.2e}", flush=True)
+    print(f"case lista backward: loss {loss:.6e} vs {loss_ref:.6e}", flush=True)
     for k in range(K):
         print("   layer", k, "ds", g[k, 0], g_ref[k, 0], "dtheta", g[k, 1], g_ref[k, 1])
     assert abs(loss - loss_ref) <= 1e-4 * loss_ref
-    assert err <= 1e-3
+    # each parameter group against its own largest gradient: the 50 tap gradients per layer
+    # are far smaller than the step and threshold gradients
+    for name, cols in (("steps", slice(0, 1)), ("thresholds", slice(1, 2)), ("taps", slice(2, None))):
+        err = np.abs(g[:, cols] - g_ref[:, cols]).max() / np.abs(g_ref[:, cols]).max()
+        print(f"   {name}: max err / max grad = {err:.2e}", flush=True)
+        assert err <= 1e-3, (name, err)
     net.close()
 
 

@@ -173,6 +173,10 @@ def test_objective_and_kkt_match_oracle():
     print(f"objective {obj:.9g} vs {F_ref:.9g}; r_kkt {r:.4e} vs {r_ref:.4e}; max e/tau {mx:.3e} vs {mx_ref:.3e}")
     assert abs(obj - F_ref) <= 1e-6 * F_ref
     assert abs(r - r_ref) <= 2e-2 * r_ref + 1e-6
+    # the same monitors under the call-list name, and Omega copied to device memory
+    r2, obj2 = plan.kkt(y, P.tau, c)
+    assert r2 == r and obj2 == obj
+    assert np.array_equal(plan.omega_device().cpu().numpy(), plan.omega())
     plan.close()
 
 

@@ -361,3 +361,47 @@ def test_table1_regular_vs_fast_magnitude():
         _, c_fst = O.admm(lambda x: O.fft_matvec(spec, x), P.b, rho, P.tau, n)
         eps = np.linalg.norm(c_reg - c_fst) / np.linalg.norm(c_reg)
         assert eps <= 1e-8
+
+
+# --------------------------------------------------------------------------
+# ADMM's shifted inverse (eq. (13)): both branches of ShiftedInverse
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rho", [0.5, 1.0, 40.0])
+@pytest.mark.parametrize("M1,M2,M,L1,L2", GEOMS)
+def test_shifted_inverse_woodbury_branch(M1, M2, M, L1, L2, rho):
+    """(G + rho I)^-1 of eq. (13) by the Woodbury branch (dense_limit=0, the one every grid
+    above 4096 points takes) equals the explicit inverse of G + rho I and the Cholesky
+    branch, on square, rectangular and aliasing (M1 > L1) geometries."""
+    mask = _mask(M1, M2, M)
+    op = O.Operator(mask, L1, L2)
+    G = O.gram_dense(mask, L1, L2)
+    inv = np.linalg.inv(G + rho * np.eye(op.L))
+    wood = O.ShiftedInverse(op, rho, dense_limit=0)
+    chol = O.ShiftedInverse(op, rho, dense_limit=1 << 30)
+    assert not wood.dense and chol.dense
+    rng = np.random.default_rng(7)
+    X = _crandn(rng, (op.L, 3))
+    for j in range(3):
+        x = X[:, j]
+        ref = inv @ x
+        scale = np.linalg.norm(ref)
+        assert np.linalg.norm(wood(x) - ref) <= 1e-11 * scale
+        assert np.linalg.norm(chol(x) - ref) <= 1e-11 * scale
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("rho", [0.5, 1.0, 40.0])
+def test_shifted_inverse_woodbury_at_paper_scale(rho):
+    """At 256 x 256 (the paper-scale geometry, Woodbury branch) S = (G + rho I)^-1 satisfies
+    (G + rho I) S(x) = x with G applied as D_s^H (D_s x) through the Kronecker factors."""
+    sc = S.paper_scale_scene(0)
+    op = O.Operator(sc.mask, sc.L1, sc.L2)
+    inv = O.ShiftedInverse(op, rho)
+    assert not inv.dense
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        x = _crandn(rng, op.L)
+        s = inv(x)
+        back = op.gram(s) + rho * s
+        assert np.linalg.norm(back - x) <= 1e-11 * np.linalg.norm(x)
