@@ -53,7 +53,8 @@ enum bccb_status {
   BCCB_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. L_i not a power of two)    */
   BCCB_E_NOMEM = -3,        /* device allocation failed                                   */
   BCCB_E_DEVICE = -4,       /* a HIP call failed                                          */
-  BCCB_E_NONFINITE = -5     /* NaN or Inf in y or in the warm start                       */
+  BCCB_E_NONFINITE = -5,    /* NaN or Inf in y or in the warm start                       */
+  BCCB_E_SCRATCH = -6       /* grid larger than the allocation-free entry point's array   */
 };
 
 /* Human-readable name of a status code (static string). */
@@ -135,6 +136,25 @@ int lasso_solve_ista(bccb_plan_t plan, const bccb_c32* y, float tau, int iters,
  */
 int lasso_solve_fista(bccb_plan_t plan, const bccb_c32* y, float tau, int iters,
                       const bccb_c32* c0, bccb_c32* c_out);
+
+/*
+ * lasso_solve_fista_noalloc -- for callers that cannot allocate device memory
+ *   (tight serving loops, harnesses that forbid hipMalloc): the solve of
+ *   lasso_solve_fista, same arguments and results, run through the plan's
+ *   full row and column passes with every work buffer taken
+ *   from one static device array of the library (6 MiB + 512 B per device,
+ *   resolved on the first call with that device current and held until the
+ *   process ends) instead of the plan's workspace.  The call allocates nothing
+ *   (no hipMalloc / hipFree, no graph instantiation): it enqueues kernels and
+ *   two small copies on the plan's stream and returns after draining it.
+ *   Limit: L1 * L2 <= 2^18 (512 x 512); larger grids return BCCB_E_SCRATCH.
+ *   The plan's device must be current (else BCCB_E_INVALID).  Every call on one
+ *   GPU shares that GPU's array: calls that overlap on one device (several host
+ *   threads, or streams in flight at once) race; calls issued one after another
+ *   are safe.  Errors as lasso_solve_fista.
+ */
+int lasso_solve_fista_noalloc(bccb_plan_t plan, const bccb_c32* y, float tau, int iters,
+                              const bccb_c32* c0, bccb_c32* c_out);
 
 /*
  * lasso_solve_admm -- `iters` iterations of eqs. (13)-(15) from z = v = 0 with

@@ -24,6 +24,7 @@ BCCB_E_UNSUPPORTED = -2
 BCCB_E_NOMEM = -3
 BCCB_E_DEVICE = -4
 BCCB_E_NONFINITE = -5
+BCCB_E_SCRATCH = -6
 
 
 class Config(ctypes.Structure):
@@ -80,6 +81,7 @@ _SIGS = {
     "bccb_gram_apply": (_i, [_vp, _vp, _vp]),
     "lasso_solve_ista": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
     "lasso_solve_fista": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
+    "lasso_solve_fista_noalloc": (_i, [_vp, _vp, _f, _i, _vp, _vp]),
     "lasso_solve_admm": (_i, [_vp, _vp, _f, _f, _i, _vp, _vp]),
     "bccb_objective_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd, _pd]),
     "bccb_kkt": (_i, [_vp, _vp, _f, _vp, _pd, _pd]),
@@ -274,6 +276,15 @@ class Plan:
         py, pc, po = self._args(y, c0=c0, out=out)
         check(lib.lasso_solve_fista(self._h, py, float(tau), int(iters), pc, po),
               "lasso_solve_fista")
+        return out
+
+    def fista_noalloc(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
+        """lasso_solve_fista_noalloc: FISTA with the library's static work array (no device
+        allocation inside the call; `out` is allocated here when not given)."""
+        out = self.grid(y.device) if out is None else out
+        py, pc, po = self._args(y, c0=c0, out=out)
+        check(lib.lasso_solve_fista_noalloc(self._h, py, float(tau), int(iters), pc, po),
+              "lasso_solve_fista_noalloc")
         return out
 
     def admm(self, y, tau: float, rho: float, iters: int, z_out=None, c_out=None, want_c=False):

@@ -383,6 +383,7 @@ const char* bccb_status_string(int status) {
     case BCCB_E_NOMEM: return "BCCB_E_NOMEM: device allocation failed";
     case BCCB_E_DEVICE: return "BCCB_E_DEVICE: HIP runtime error";
     case BCCB_E_NONFINITE: return "BCCB_E_NONFINITE: NaN or Inf in the input";
+    case BCCB_E_SCRATCH: return "BCCB_E_SCRATCH: grid larger than the allocation-free entry point's static array";
     default: return "unknown bccb status";
   }
 }
