@@ -37,6 +37,8 @@ __all__ = [
     "learned_scene",
     "learned_fixed_mask",
     "custom_scene",
+    "spaced_scene",
+    "angle_scene",
     "CONFIG_ITERS",
 ]
 
@@ -99,9 +101,19 @@ def _random_mask(rng: np.random.Generator, M1: int, M2: int, M: int,
 
 
 def _snapshot(rng: np.random.Generator, mask: np.ndarray, K: int, modulus,
-              snr_db: float):
-    """Draw K targets and the noisy sparse-array snapshot (eqs. (1)-(3), (6))."""
-    freqs = rng.uniform(-0.5, 0.5, size=(K, 2))  # f = omega / (2 pi), omega ~ U[-pi, pi)
+              snr_db: float, gammas=None, freqs=None):
+    """Draw K targets and the noisy sparse-array snapshot (eqs. (1)-(3), (6)).
+
+    gammas = (gamma1, gamma2): element spacings in wavelengths; the harmonics are then drawn
+    from [-gamma1, gamma1) x [-gamma2, gamma2) (Sec. II-A) instead of [-1/2, 1/2)^2.
+    freqs: [K][2] harmonics given by the caller (nothing drawn for them)."""
+    if freqs is not None:
+        freqs = np.asarray(freqs, dtype=np.float64).reshape(K, 2)
+    elif gammas is None:
+        freqs = rng.uniform(-0.5, 0.5, size=(K, 2))  # f = omega / (2 pi), omega ~ U[-pi, pi)
+    else:
+        g = np.asarray(gammas, dtype=np.float64)
+        freqs = rng.uniform(-g, g, size=(K, 2))
     if modulus is None:
         mod = np.ones(K)
     else:
@@ -130,6 +142,45 @@ def custom_scene(M1: int, M2: int, M: int, L1: int, L2: int, K: int, snr_db: flo
     y, freqs, amps, sigma2 = _snapshot(rng, mask, K, modulus, snr_db)
     return Scene(mask, L1, L2, y, freqs, amps, sigma2, snr_db, cfg=seed[0],
                  split=seed[1], idx=seed[2])
+
+
+def spaced_scene(gamma1: float, gamma2: float, M1: int, M2: int, M: int, L1: int, L2: int, K: int,
+                 snr_db: float, seed=(7, 0, 0), modulus=(0.5, 1.0)) -> Scene:
+    """An array with element spacing (gamma1 lambda, gamma2 lambda): M of the M1 x M2 URA
+    elements kept (corners included, aperture preserved), K targets with harmonics uniform in
+    [-gamma_i, gamma_i), |c_k| ~ U[modulus].  The snapshot model is that of eq. (3):
+    element (m1, m2) sees exp(-j 2 pi (m1 f1 + m2 f2))."""
+    rng = _rng(*seed)
+    mask = _random_mask(rng, M1, M2, M, keep_corners=M >= 4 and M1 > 1 and M2 > 1)
+    y, freqs, amps, sigma2 = _snapshot(rng, mask, K, modulus, snr_db, gammas=(gamma1, gamma2))
+    return Scene(mask, L1, L2, y, freqs, amps, sigma2, snr_db, cfg=seed[0], split=seed[1], idx=seed[2],
+                 meta={"gamma": (gamma1, gamma2)})
+
+
+def angle_scene(gamma1: float, gamma2: float, M1: int, M2: int, M: int, L1: int, L2: int, K: int,
+                snr_db: float, seed=(8, 0, 0), modulus=(0.5, 1.0), min_sep: float = 0.0) -> Scene:
+    """Targets drawn as directions: azimuth phi ~ U[-pi, pi), elevation theta ~ U[0, pi/2)
+    (the ranges of Sec. II-A), each mapped to its harmonics by the steering model of eq. (2),
+    (f1, f2) = (gamma1 cos(phi) sin(theta), gamma2 sin(phi) sin(theta)).  min_sep > 0 redraws
+    a direction whose harmonics lie closer than min_sep (max-norm, in cycles) to an earlier
+    target's.  meta['angles'] holds the [K][2] (phi, theta) drawn."""
+    rng = _rng(*seed)
+    mask = _random_mask(rng, M1, M2, M, keep_corners=M >= 4 and M1 > 1 and M2 > 1)
+    angles = np.empty((K, 2))
+    freqs = np.empty((K, 2))
+    k = 0
+    while k < K:
+        phi = rng.uniform(-np.pi, np.pi)
+        theta = rng.uniform(0.0, np.pi / 2)
+        f = np.array([gamma1 * np.cos(phi) * np.sin(theta), gamma2 * np.sin(phi) * np.sin(theta)])
+        if k and min_sep > 0 and np.abs(freqs[:k] - f).max(axis=1).min() < min_sep:
+            continue
+        angles[k] = (phi, theta)
+        freqs[k] = f
+        k += 1
+    y, freqs, amps, sigma2 = _snapshot(rng, mask, K, modulus, snr_db, freqs=freqs)
+    return Scene(mask, L1, L2, y, freqs, amps, sigma2, snr_db, cfg=seed[0], split=seed[1], idx=seed[2],
+                 meta={"gamma": (gamma1, gamma2), "angles": angles})
 
 
 def tiny_scene(idx: int = 0) -> Scene:
