@@ -87,6 +87,46 @@ int bccb_stream_copy(const void* src, void* dst, size_t bytes, int variant, void
  */
 int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream, bccb_plan_t* out);
 
+/*
+ * bccb_plan_spaced -- a plan for a uniform harmonic grid at element spacing
+ *   (gamma1 lambda, gamma2 lambda) (Sec. II-A: the harmonics lie in
+ *   [-gamma_i, gamma_i), sampled at f_{i,l} = -gamma_i + l 2 gamma_i / L_i,
+ *   eq. (16)) and for grid lengths that are not powers of two.  On that grid
+ *   the Gram D_s^H D_s is block Toeplitz with Toeplitz blocks (circulant only
+ *   at gamma_i = 1/2, Sec. III-A): the plan embeds it in the leading
+ *   L1 x L2 window of a P1 x P2 BCCB (P_i the smallest power of two
+ *   >= max(8, 2 L_i - 1)) and computes every Gram product by eq. (23) on the
+ *   padded grid, the iterate held at zero outside the window.  The step is
+ *   mu = 1/sigma_max(D_s)^2 (eq. (9)): at gamma = 1/2 the largest eigenvalue
+ *   L1 L2 x (most elements folding onto one bin) of eq. (21), otherwise the
+ *   largest eigenvalue of D_s D_s^H found by Lanczos in FP64.
+ *   mask: host [M2][M1] (as bccb_plan); L1, L2 in [2, 512], any integers;
+ *   gamma1, gamma2 in (0, 1].  gamma1 = gamma2 = 1/2 with L_i powers of two
+ *   in [8, 1024] returns an ordinary plan (bccb_plan).  With gamma != 1/2 at
+ *   most 2048 kept elements (BCCB_E_UNSUPPORTED beyond).
+ *   Grids passed to the calls below stay the caller's [L2][L1] grids.
+ *   A plan made here serves bccb_plan_info (M and mu; omega_host must be
+ *   NULL), bccb_adjoint, bccb_adjoint_maxabs, bccb_gram_apply,
+ *   lasso_solve_ista, lasso_solve_fista, bccb_objective_kkt, bccb_kkt and,
+ *   at gamma1 = gamma2 = 1/2 only, lasso_solve_admm ((G + rho I)^-1 is then
+ *   the BCCB of spectrum 1/(Omega + rho), Sec. III-A (ii), embedded the same
+ *   way; the inverse of a Toeplitz Gram is not Toeplitz); every other call
+ *   returns BCCB_E_UNSUPPORTED for it.  Memory: about 70 bytes per point of
+ *   the P1 x P2 grid.
+ */
+int bccb_plan_spaced(const uint8_t* mask, int M1, int M2, int L1, int L2, double gamma1, double gamma2,
+                     void* stream, bccb_plan_t* out);
+
+/*
+ * bccb_plan_embedding -- of a plan made by bccb_plan_spaced with a padded
+ *   embedding: the transform grid P1 x P2 and (omega_host, nullable, host
+ *   float [P2][P1]) the FP32 eigenvalues of the embedded Gram, Omega_e =
+ *   DFT2 of the first column holding t(d1, d2) = G[(d1, d2), (0, 0)] (and
+ *   t(-d) = conj t(d)) at (d1 mod P1, d2 mod P2), zero elsewhere.
+ *   BCCB_E_UNSUPPORTED for an ordinary plan.
+ */
+int bccb_plan_embedding(bccb_plan_t plan, int* P1, int* P2, float* omega_host);
+
 /* Free a plan and everything it owns (NULL is accepted). */
 int bccb_plan_destroy(bccb_plan_t plan);
 
@@ -195,6 +235,38 @@ int bccb_kkt(bccb_plan_t plan, const bccb_c32* y, float tau, const bccb_c32* c, 
  *   returns after the copy.  BCCB_E_INVALID for a null plan or buffer.
  */
 int bccb_plan_omega_device(bccb_plan_t plan, float* omega_dev);
+
+/*
+ * Harmonics and directions of recovered coefficient grids (Sec. II-A: the support of c
+ * marks the harmonic tuples (f_{1,l1}, f_{2,l2}) present; eq. (2) maps a tuple to a
+ * direction, f1 = gamma1 cos(phi) sin(theta), f2 = gamma2 sin(phi) sin(theta)).
+ */
+typedef struct {
+  int index;        /* grid index l1 + l2*L1 of the local maximum                        */
+  float mag2;       /* |c|^2 there (FP32: re*re + im*im, each operation rounded)         */
+  float f1, f2;     /* refined harmonic tuple (cycles per element)                        */
+  float phi, theta; /* direction by eq. (2); theta = NaN outside the visible region       */
+  bccb_c32 amp;     /* sum of the coefficients of the 3 x 3 neighbourhood                 */
+} bccb_peak;
+
+/*
+ * bccb_extract_peaks -- for each of `batch` grids c (device [batch][L2][L1], the plan's
+ *   grid; for a bccb_plan_spaced plan its L1 x L2), the strongest local maxima of |c|:
+ *   grid points whose |c|^2 (FP32 as above) exceeds min_mag2 and beats all 8 neighbours
+ *   (equal |c|^2: the smaller index ranks higher; the grid wraps when gamma1 = gamma2 =
+ *   1/2, where f = -1/2 and f = 1/2 coincide), at most max_peaks (1..1024) by decreasing
+ *   |c|^2 (ties: smaller index first).  Each is refined to the |c|-weighted mean of its
+ *   3 x 3 neighbourhood's grid offsets, f_i = -gamma_i + (l_i + offset_i) 2 gamma_i / L_i
+ *   (eq. (16); wrapped into [-1/2, 1/2) at half spacing), and mapped to (phi, theta) by
+ *   inverting eq. (2): phi = atan2(f2/gamma2, f1/gamma1) in [-pi, pi), theta =
+ *   asin(sqrt((f1/gamma1)^2 + (f2/gamma2)^2)), NaN when that exceeds 1.
+ *   peaks: device [batch][max_peaks] (entries past counts[s] untouched); counts: device
+ *   int [batch], the peaks written per grid, or -1 when more than 4096 local maxima exceed
+ *   min_mag2 (nothing written for that grid: raise the threshold).  batch in 1..65535.
+ *   Work buffers (32 KB per grid) are kept by the plan.  Returns after the stream drains.
+ */
+int bccb_extract_peaks(bccb_plan_t plan, const bccb_c32* c, int batch, int max_peaks, float min_mag2,
+                       bccb_peak* peaks, int* counts);
 
 /*
  * Batched solves -- many independent snapshots, each with its own plan (its

@@ -74,6 +74,9 @@ _SIGS = {
     "bccb_status_string": (ctypes.c_char_p, [_i]),
     "bccb_plan": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
     "bccb_plan_destroy": (_i, [_vp]),
+    "bccb_plan_spaced": (_i, [_vp, _i, _i, _i, _i, _d, _d, _vp, ctypes.POINTER(_vp)]),
+    "bccb_plan_embedding": (_i, [_vp, _pi, _pi, _vp]),
+    "bccb_extract_peaks": (_i, [_vp, _vp, _i, _i, _f, _vp, _vp]),
     "bccb_set_stream": (_i, [_vp, _vp]),
     "bccb_plan_info": (_i, [_vp, _pi, _pd, _vp]),
     "bccb_adjoint": (_i, [_vp, _vp, _vp]),
@@ -205,13 +208,16 @@ class Plan:
         self.L = self.L1 * self.L2
         self._h = _vp()
         s = current_stream() if stream is None else stream
-        check(lib.bccb_plan(mask.ctypes.data, self.M1, self.M2, self.L1, self.L2, s, ctypes.byref(self._h)),
-              "bccb_plan")
+        self._create(mask, s)
         M = ctypes.c_int()
         mu = ctypes.c_double()
         check(lib.bccb_plan_info(self._h, ctypes.byref(M), ctypes.byref(mu), None), "bccb_plan_info")
         self.M = M.value
         self.mu = mu.value
+
+    def _create(self, mask, s):
+        check(lib.bccb_plan(mask.ctypes.data, self.M1, self.M2, self.L1, self.L2, s, ctypes.byref(self._h)),
+              "bccb_plan")
 
     @property
     def handle(self):
@@ -277,6 +283,9 @@ class Plan:
         check(lib.lasso_solve_fista(self._h, py, float(tau), int(iters), pc, po),
               "lasso_solve_fista")
         return out
+
+    def extract_peaks(self, c, max_peaks: int, min_mag2: float = 0.0):
+        return extract_peaks(self, c, max_peaks, min_mag2)
 
     def fista_noalloc(self, y, tau: float, iters: int, c0=None, out=None) -> torch.Tensor:
         """lasso_solve_fista_noalloc: FISTA with the library's static work array (no device
@@ -365,6 +374,52 @@ def stream_copy(src: torch.Tensor, dst: torch.Tensor, variant: int = 0, stream: 
     s = current_stream() if stream is None else stream
     check(lib.bccb_stream_copy(_vp(_raw_ptr(src)), _vp(_raw_ptr(dst)), ctypes.c_size_t(nbytes), int(variant), s),
           "bccb_stream_copy")
+
+
+# bccb_peak (include/bccb.h), 32 bytes
+PEAK_DTYPE = np.dtype([("index", np.int32), ("mag2", np.float32), ("f1", np.float32), ("f2", np.float32),
+                       ("phi", np.float32), ("theta", np.float32), ("amp_re", np.float32), ("amp_im", np.float32)])
+
+
+def extract_peaks(plan: "Plan", c: torch.Tensor, max_peaks: int, min_mag2: float = 0.0):
+    """bccb_extract_peaks over c ([L2][L1] or [batch][L2][L1], complex64 on the GPU, the plan's
+    grid): a list per grid of PEAK_DTYPE records, strongest first (None for a grid with more
+    than 4096 local maxima above min_mag2)."""
+    batch = 1 if c.dim() == 2 else int(c.shape[0])
+    (pc,) = _ptrs((c, batch * plan.L, "c"))
+    peaks = torch.empty(batch * int(max_peaks) * PEAK_DTYPE.itemsize, dtype=torch.uint8, device=c.device)
+    counts = torch.empty(batch, dtype=torch.int32, device=c.device)
+    check(lib.bccb_extract_peaks(plan.handle, pc, batch, int(max_peaks), float(min_mag2), _raw_ptr(peaks),
+                                 _raw_ptr(counts)), "bccb_extract_peaks")
+    rec = peaks.cpu().numpy().view(PEAK_DTYPE).reshape(batch, int(max_peaks))
+    n = counts.cpu().numpy()
+    return [None if n[i] < 0 else rec[i, :n[i]].copy() for i in range(batch)]
+
+
+class SpacedPlan(Plan):
+    """bccb_plan_spaced: element spacing (gamma1, gamma2) wavelengths and any grid lengths
+    L1, L2 in [2, 512] (the Gram is block Toeplitz; products through a padded embedding)."""
+
+    def __init__(self, mask, L1: int, L2: int, gamma1: float = 0.5, gamma2: float = 0.5,
+                 stream: int | None = None):
+        self.gamma1, self.gamma2 = float(gamma1), float(gamma2)
+        super().__init__(mask, L1, L2, stream)
+
+    def _create(self, mask, s):
+        check(lib.bccb_plan_spaced(mask.ctypes.data, self.M1, self.M2, self.L1, self.L2, self.gamma1,
+                                   self.gamma2, s, ctypes.byref(self._h)), "bccb_plan_spaced")
+
+    def embedding(self):
+        """(P1, P2, Omega_e [P2][P1] float32) of the padded embedding, or None for a plan that
+        needs none (gamma = 1/2 on power-of-two grids)."""
+        P1, P2 = ctypes.c_int(), ctypes.c_int()
+        rc = lib.bccb_plan_embedding(self._h, ctypes.byref(P1), ctypes.byref(P2), None)
+        if rc == BCCB_E_UNSUPPORTED:
+            return None
+        check(rc, "bccb_plan_embedding")
+        om = np.empty((P2.value, P1.value), dtype=np.float32)
+        check(lib.bccb_plan_embedding(self._h, None, None, om.ctypes.data), "bccb_plan_embedding")
+        return P1.value, P2.value, om
 
 
 def to_device(y: np.ndarray, device="cuda") -> torch.Tensor:

@@ -11,6 +11,7 @@
 
 #include "kernels.h"
 #include "plan_internal.h"
+#include "spaced_api.h"
 #include "plan_math.h"
 
 using bccb::ColArgs;
@@ -44,11 +45,18 @@ static void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
-void drop_graph(bccb_plan_s* p);
-
 void plan_free(bccb_plan_s* p) {
   if (!p) return;
   drop_graph(p);
+  dfree(p->d_W1);
+  dfree(p->d_W2);
+  dfree(p->d_emb_u);
+  dfree(p->d_emb_c);
+  dfree(p->d_emb_c2);
+  dfree(p->d_omega_rho);
+  dfree(p->d_emb_coef);
+  dfree(p->d_cand);
+  dfree(p->d_ccount);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_omega);
   dfree(p->d_sensor_of);
@@ -288,46 +296,6 @@ void drop_graph(bccb_plan_s* p) {
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   p->graph_exec = nullptr;
   for (auto& k : p->graph_key) k = 0;
-}
-
-// Run `enqueue` (the iteration loop of a solve) on the plan's stream, through a
-// cached hipGraph when enabled: the loop is captured on a private stream (the
-// plan's stream may be the null stream, which cannot capture) and replayed
-// while the key -- every argument the captured launches depend on -- repeats.
-template <typename F>
-int run_loop(bccb_plan_s* p, const unsigned long long (&key)[8], F&& enqueue) {
-  if (!p->use_graph) return enqueue(p->stream);
-  bool hit = p->graph_exec != nullptr;
-  for (int i = 0; i < 8 && hit; ++i) hit = p->graph_key[i] == key[i];
-  if (!hit) {
-    drop_graph(p);
-    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-      p->cap_stream = nullptr;
-      return BCCB_E_DEVICE;
-    }
-    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return BCCB_E_DEVICE;
-    const int rc = enqueue(p->cap_stream);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
-    if (rc != BCCB_OK || ec != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc != BCCB_OK ? rc : BCCB_E_DEVICE;
-    }
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) return BCCB_E_DEVICE;
-    p->graph_exec = ex;
-    for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
-  }
-  BCCB_HIP(hipGraphLaunch(p->graph_exec, p->stream));
-  return BCCB_OK;
-}
-
-static unsigned long long fbits(float f) {
-  unsigned int u;
-  std::memcpy(&u, &f, sizeof(u));
-  return u;
 }
 
 // b (or scale*b) = D_s^H y into dst, using p->d_tmp as the spectral scratch.
@@ -581,6 +549,7 @@ int bccb_set_stream(bccb_plan_t plan, void* stream) {
 
 int bccb_plan_info(bccb_plan_t plan, int* M, double* mu, float* omega_host) {
   if (!plan) return BCCB_E_INVALID;
+  if (plan->emb && omega_host) return BCCB_E_UNSUPPORTED;   // see bccb_plan_embedding
   if (M) *M = plan->M;
   if (mu) *mu = plan->mu;
   if (omega_host) std::memcpy(omega_host, plan->omega32.data(), plan->L * sizeof(float));
@@ -596,6 +565,7 @@ int bccb_stream_copy(const void* src, void* dst, size_t bytes, int variant, void
 
 int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned) {
   if (!plan) return BCCB_E_INVALID;
+  if (plan->emb) return BCCB_E_UNSUPPORTED;
   if (ncols) *ncols = plan->nscol;
   if (pruned) *pruned = pruned_on(plan) ? (resident_on(plan) && resident_pruned_on(plan) ? 2 : 1) : 0;
   return BCCB_OK;
@@ -603,6 +573,7 @@ int bccb_plan_support_columns(bccb_plan_t plan, int* ncols, int* pruned) {
 
 int bccb_adjoint(bccb_plan_t p, const bccb_c32* y, bccb_c32* b) {
   if (!p || !y || !b) return BCCB_E_INVALID;
+  if (p->emb) return spaced_adjoint(p, reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(b));
   BCCB_TRY(begin_call(p));
   BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), 1.f, reinterpret_cast<float2*>(b)));
   return end_call(p);
@@ -610,6 +581,7 @@ int bccb_adjoint(bccb_plan_t p, const bccb_c32* y, bccb_c32* b) {
 
 int bccb_adjoint_maxabs(bccb_plan_t p, const bccb_c32* y, double* maxabs) {
   if (!p || !y || !maxabs) return BCCB_E_INVALID;
+  if (p->emb) return spaced_adjoint_maxabs(p, reinterpret_cast<const float2*>(y), maxabs);
   BCCB_TRY(begin_call(p));
   BCCB_TRY(adjoint_into(p, reinterpret_cast<const float2*>(y), 1.f, p->d_rhs));
   int nb = 0;
@@ -624,6 +596,7 @@ int bccb_adjoint_maxabs(bccb_plan_t p, const bccb_c32* y, double* maxabs) {
 
 int bccb_gram_apply(bccb_plan_t p, const bccb_c32* x, bccb_c32* gx) {
   if (!p || !x || !gx) return BCCB_E_INVALID;
+  if (p->emb) return spaced_gram_apply(p, reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(gx));
   BCCB_TRY(begin_call(p));
   RowArgs a;
   a.xy = p->d_xy;
@@ -842,6 +815,9 @@ static int enqueue_prox_grad(bccb_plan_s* p, int mode, int iters, float kappa, c
 static int solve_prox_grad(bccb_plan_t p, int mode, const bccb_c32* y, float tau, int iters, const bccb_c32* c0,
                            bccb_c32* c_out) {
   BCCB_TRY(check_solve(p, y, tau, iters, c_out));
+  if (p->emb)
+    return spaced_prox_grad(p, mode, reinterpret_cast<const float2*>(y), tau, iters, reinterpret_cast<const float2*>(c0),
+                            reinterpret_cast<float2*>(c_out));
   float2* out = reinterpret_cast<float2*>(c_out);
   const float2* init = reinterpret_cast<const float2*>(c0);
   BCCB_TRY(begin_call(p));
@@ -865,6 +841,9 @@ int lasso_solve_admm(bccb_plan_t p, const bccb_c32* y, float tau, float rho, int
                      bccb_c32* c_out) {
   BCCB_TRY(check_solve(p, y, tau, iters, z_out));
   if (!(rho > 0.f) || !std::isfinite(rho)) return BCCB_E_INVALID;
+  if (p->emb)
+    return spaced_admm(p, reinterpret_cast<const float2*>(y), tau, rho, iters, reinterpret_cast<float2*>(z_out),
+                       reinterpret_cast<float2*>(c_out));
   float2* zo = reinterpret_cast<float2*>(z_out);
   float2* co = reinterpret_cast<float2*>(c_out);
   BCCB_TRY(begin_call(p));
@@ -930,6 +909,9 @@ int bccb_objective_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c
                        double* r_kkt, double* max_e_over_tau) {
   if (!p || !y || !c) return BCCB_E_INVALID;
   if (!(tau >= 0.f) || !std::isfinite(tau)) return BCCB_E_INVALID;
+  if (p->emb)
+    return spaced_objective_kkt(p, reinterpret_cast<const float2*>(y), tau, reinterpret_cast<const float2*>(c),
+                                objective, r_kkt, max_e_over_tau);
   const float2* cc = reinterpret_cast<const float2*>(c);
   BCCB_TRY(begin_call(p));
   // spec = DFT2(c); D_s c = (-1)^(m1+m2) spec at the kept elements' bins
@@ -977,6 +959,7 @@ int bccb_kkt(bccb_plan_t p, const bccb_c32* y, float tau, const bccb_c32* c, dou
 
 int bccb_plan_omega_device(bccb_plan_t p, float* omega_dev) {
   if (!p || !omega_dev) return BCCB_E_INVALID;
+  if (p->emb) return BCCB_E_UNSUPPORTED;
   BCCB_HIP(hipMemcpyAsync(omega_dev, p->d_omega, p->L * sizeof(float), hipMemcpyDeviceToDevice, p->stream));
   BCCB_HIP(hipStreamSynchronize(p->stream));
   return BCCB_OK;
@@ -1006,6 +989,7 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
 
 int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   if (!p || !cfg) return BCCB_E_INVALID;
+  if (p->emb) return BCCB_E_UNSUPPORTED;
   PassCfg r, c;
   r.E = cfg->row_elems;
   r.rpb = cfg->row_rows_per_block;
@@ -1067,6 +1051,7 @@ static RowArgs pruned_work_args(bccb_plan_s* p) {
 
 int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
   if (!p || reps < 1) return BCCB_E_INVALID;
+  if (p->emb) return BCCB_E_UNSUPPORTED;
   hipStream_t st = p->stream;
   RowArgs a;
   a.xy = p->d_xy;
@@ -1199,7 +1184,7 @@ int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
 
 int bccb_profile_resident(bccb_plan_t p, int solver, int iters, int reps, double* ms) {
   if (!p || reps < 1 || iters < 1 || solver < 0 || solver > 2 || !ms) return BCCB_E_INVALID;
-  if (!resident_on(p)) return BCCB_E_UNSUPPORTED;
+  if (p->emb || !resident_on(p)) return BCCB_E_UNSUPPORTED;
   const int mode = solver == 0 ? RES_ISTA : (solver == 1 ? RES_FISTA : RES_ADMM);
   const float scale = static_cast<float>(1.0 / static_cast<double>(p->L));
   const float m = time_launches(p->stream, reps, [&] {
@@ -1213,6 +1198,7 @@ int bccb_profile_resident(bccb_plan_t p, int solver, int iters, int reps, double
 
 int bccb_profile_passes(bccb_plan_t p, int solver, int reps, double* col_ms, double* row_ms) {
   if (!p || reps < 1 || solver < 0 || solver > 2 || !col_ms || !row_ms) return BCCB_E_INVALID;
+  if (p->emb) return BCCB_E_UNSUPPORTED;
   hipEvent_t e0, e1, e2;
   BCCB_HIP(hipEventCreate(&e0));
   BCCB_HIP(hipEventCreate(&e1));

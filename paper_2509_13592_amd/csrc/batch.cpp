@@ -262,8 +262,10 @@ extern "C" {
 int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_batch_t* out) {
   if (!plans || nscenes < 1 || !out) return BCCB_E_INVALID;
   *out = nullptr;
-  for (int i = 0; i < nscenes; ++i)
+  for (int i = 0; i < nscenes; ++i) {
     if (!plans[i]) return BCCB_E_INVALID;
+    if (plans[i]->emb) return BCCB_E_UNSUPPORTED;   // padded-embedding plans solve one scene at a time
+  }
   bccb_batch_s* b = new (std::nothrow) bccb_batch_s();
   if (!b) return BCCB_E_NOMEM;
   b->n = nscenes;

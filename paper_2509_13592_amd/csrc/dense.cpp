@@ -42,6 +42,7 @@ int bccb_dense_create(bccb_plan_t p, int kind, float rho, bccb_dense_t* out) {
   if (!p || !out || (kind != 0 && kind != 1)) return BCCB_E_INVALID;
   if (kind == 1 && (!(rho > 0.f) || !std::isfinite(rho))) return BCCB_E_INVALID;
   *out = nullptr;
+  if (p->emb) return BCCB_E_UNSUPPORTED;
   const long L = p->L;
   if (L % 8 != 0) return BCCB_E_UNSUPPORTED;
   // first column of the iteration matrix, FP64 on the host

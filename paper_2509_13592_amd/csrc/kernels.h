@@ -70,6 +70,10 @@ struct RowArgs {
   SlotBuf b0, b1, b2;
   float beta_prev = 0.f;
   float2* keep_c = nullptr;        // ROW_PRUNED, not last: also store c_t densely here (nullable)
+  // ROW_ISTA / ROW_FISTA / ROW_ADMM over a zero-padded embedding: only the first act_cols
+  // elements of the first act_rows rows of each scene are coefficients; the update there is
+  // as above and every other element is held at zero (c = 0).  0 = the whole grid.
+  int act_cols = 0, act_rows = 0;
   // ROW_PRUNED: dscal (nullable) overrides kappa with dscal[0]; at the last iteration out_prev
   // (nullable) receives c_{t-1} densely; out_prev is also honoured by ROW_FISTA
 };

@@ -327,6 +327,7 @@ extern "C" {
 int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_lista_t* out) {
   if (!plan || layers < 1 || layers > 256 || max_batch < 1 || !out) return BCCB_E_INVALID;
   *out = nullptr;
+  if (plan->emb) return BCCB_E_UNSUPPORTED;
   bccb_lista_s* n = new (std::nothrow) bccb_lista_s();
   if (!n) return BCCB_E_NOMEM;
   n->plan = plan;

@@ -58,6 +58,7 @@ extern "C" int lasso_solve_fista_noalloc(bccb_plan_t p, const bccb_c32* y, float
                                          bccb_c32* c_out) {
   if (!p || !y || !c_out) return BCCB_E_INVALID;
   if (!(tau >= 0.f) || !std::isfinite(tau) || iters < 0) return BCCB_E_INVALID;
+  if (p->emb) return BCCB_E_UNSUPPORTED;   // padded-embedding plans keep their own work grids
   if (p->L > kMaxPoints) return BCCB_E_SCRATCH;
   int dev = -1;
   BCCB_HIP(hipGetDevice(&dev));

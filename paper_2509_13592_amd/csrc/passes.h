@@ -147,15 +147,18 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
   float2* sm = lds + AR * r * FA;      // exchange area (and slot expansion)
   float2* sm2 = sm + (AR - 1) * FA;    // second exchange area (two-area transforms)
   // logical row -> physical row of the arenas (scene compaction through scene_map)
-  int scene = 0, prow = 0;
+  int scene = 0, prow = 0, within = 0;
   if (active) {
     scene = row / a.rows_per_scene;
-    const int within = row - scene * a.rows_per_scene;
+    within = row - scene * a.rows_per_scene;
     if (a.scene_map) scene = a.scene_map[scene];
     prow = scene * a.rows_per_scene + within;
   }
   const size_t base = static_cast<size_t>(prow) * N;
   const float2 zero = make_float2(0.f, 0.f);
+  // zero-padded embedding: rows at or past act_rows hold no coefficient
+  const bool masked = a.act_cols > 0;
+  const bool row_in = !masked || within < a.act_rows;
 
   // Every global load of the pass is issued before the first barrier so the
   // latencies of the iterate, the right-hand side, the state and the twiddle
@@ -267,8 +270,10 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const size_t idx = base + F::in_index(t, e);
+      // inside the coefficient window of a padded embedding (always, without one)
+      const bool in = !masked || (row_in && F::in_index(t, e) < a.act_cols);
       if constexpr (MODE == ROW_ISTA) {
-        const float2 c = shrink(make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y), kappa);
+        const float2 c = keep_if(in, shrink(make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y), kappa));
         if (a.last && active) a.out_c[idx] = c;
         v[e] = c;
       } else if constexpr (kSp) {
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         v[e] = shrink(u, kappa);
       } else if constexpr (MODE == ROW_FISTA) {
         const float2 u = make_float2(v[e].x + rs * rhs[e].x, v[e].y + rs * rhs[e].y);
-        const float2 c = shrink(u, kappa);
+        const float2 c = keep_if(in, shrink(u, kappa));
         const float2 cp = st[e];
         if (active) {
           a.state[idx] = c;
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(256) void k_row(RowArgs a, int rpb) {
         }
         v[e] = make_float2(c.x + a.beta * (c.x - cp.x), c.y + a.beta * (c.y - cp.y));
       } else {  // ROW_ADMM
-        const float2 c = cadd(rhs[e], v[e]);
+        const float2 c = keep_if(in, cadd(rhs[e], v[e]));
         const float2 vv = st[e];
         const float2 z = shrink(cadd(c, vv), kappa);
         const float2 vn = csub(cadd(vv, c), z);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <vector>
 
 #include "bccb.h"
@@ -95,6 +96,30 @@ struct bccb_plan_s {
   bccb::PassCfg cfg_col;           // launch shape of the column passes (N = L2)
   int use_graph = 1;
 
+  // plans on a zero-padded embedding (bccb_plan_spaced): the caller's grid is A1 x A2 and
+  // sits in the leading window of the L1 x L2 transform grid (L_i >= 2 A_i - 1, powers of
+  // two); d_omega holds the eigenvalues of the circulant embedding of the Gram, and the row
+  // pass keeps every element outside the window at zero
+  bool emb = false;
+  int A1 = 0, A2 = 0;
+  long AL = 0;
+  double gamma1 = 0.5, gamma2 = 0.5;
+  bool emb_circulant = false;      // gamma = 1/2 on both axes: G is the A1 x A2 BCCB (ADMM available)
+  std::vector<double> emb_omega;   // circulant: the A1 x A2 eigenvalue grid of G (eq. (21))
+  float2* d_W1 = nullptr;          // [M1][A1] e^{-j 2 pi f_{1,l} m1}
+  float2* d_W2 = nullptr;          // [M2][A2]
+  float2* d_emb_u = nullptr;       // separable-product scratch, max(M2 A1, A2 M1)
+  float2* d_emb_c = nullptr;       // [L] padded iterate (c^(t-1), or the ADMM z)
+  float2* d_emb_c2 = nullptr;      // [L] padded ADMM c
+  float* d_omega_rho = nullptr;    // [L] eigenvalues of the embedding of (G + rho I)^-1
+  float2* d_emb_coef = nullptr;    // [2] multiplier coefficients of the ADMM passes
+  float emb_rho = -1.f;            // rho d_omega_rho was built for
+
+  // peak extraction (bccb_extract_peaks): candidate keys [cand_batch][4096] and counts
+  unsigned long long* d_cand = nullptr;
+  int* d_ccount = nullptr;
+  int cand_batch = 0;
+
   // one cached hipGraph of a solve's iteration loop, replayed while its key repeats
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -127,6 +152,54 @@ bool rowp_shape_ok(int L1, const PassCfg& c, int ncs);    // pruned row pass ove
 bool colp_shape_ok(int ncs, int L2, const PassCfg& c);    // pruned column pass over ncs columns
 bool pruned_on(const bccb_plan_s* p);
 bool resident_on(const bccb_plan_s* p);
+void default_config(bccb_plan_s* p);
+void drop_graph(bccb_plan_s* p);
+void plan_free(bccb_plan_s* p);
+int row_pass_on(bccb_plan_s* p, const PassCfg& cfg, int mode, RowArgs a, hipStream_t s);
+int col_pass_on(bccb_plan_s* p, const PassCfg& cfg, int mode, float2* xy, const float2* coef, float rho,
+                float scale, hipStream_t s);
+int row_pass(bccb_plan_s* p, int mode, RowArgs a);
+int col_pass(bccb_plan_s* p, int mode, float2* xy, const float2* coef, float rho, float scale);
+
+// Run `enqueue` (the iteration loop of a solve) on the plan's stream, through a
+// cached hipGraph when enabled: the loop is captured on a private stream (the
+// plan's stream may be the null stream, which cannot capture) and replayed
+// while the key -- every argument the captured launches depend on -- repeats.
+template <typename F>
+int run_loop(bccb_plan_s* p, const unsigned long long (&key)[8], F&& enqueue) {
+  if (!p->use_graph) return enqueue(p->stream);
+  bool hit = p->graph_exec != nullptr;
+  for (int i = 0; i < 8 && hit; ++i) hit = p->graph_key[i] == key[i];
+  if (!hit) {
+    drop_graph(p);
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      p->cap_stream = nullptr;
+      return BCCB_E_DEVICE;
+    }
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return BCCB_E_DEVICE;
+    const int rc = enqueue(p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
+    if (rc != BCCB_OK || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != BCCB_OK ? rc : BCCB_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return BCCB_E_DEVICE;
+    p->graph_exec = ex;
+    for (int i = 0; i < 8; ++i) p->graph_key[i] = key[i];
+  }
+  BCCB_HIP(hipGraphLaunch(p->graph_exec, p->stream));
+  return BCCB_OK;
+}
+
+inline unsigned long long fbits(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, sizeof(u));
+  return u;
+}
 
 // Time `reps` launches of `launch()` on stream s with hipEvents; ms per launch, or < 0 on error.
 template <typename F>

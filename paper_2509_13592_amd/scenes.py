@@ -39,6 +39,7 @@ __all__ = [
     "custom_scene",
     "spaced_scene",
     "angle_scene",
+    "coefficient_grids",
     "CONFIG_ITERS",
 ]
 
@@ -181,6 +182,26 @@ def angle_scene(gamma1: float, gamma2: float, M1: int, M2: int, M: int, L1: int,
     y, freqs, amps, sigma2 = _snapshot(rng, mask, K, modulus, snr_db, freqs=freqs)
     return Scene(mask, L1, L2, y, freqs, amps, sigma2, snr_db, cfg=seed[0], split=seed[1], idx=seed[2],
                  meta={"gamma": (gamma1, gamma2), "angles": angles})
+
+
+def coefficient_grids(seed, batch: int, L1: int, L2: int, n_blobs: int = 6, n_scatter: int = 40) -> np.ndarray:
+    """complex64 [batch][L2][L1] grids shaped like sparse recovered coefficient grids: each holds
+    n_blobs 3 x 3 blobs (a random centre value, neighbours scaled by U[0, 0.8]) and n_scatter
+    isolated small entries (|c| <= 0.3), all at random positions (wrapping at the edges)."""
+    rng = _rng(*seed)
+    out = np.zeros((batch, L2, L1), dtype=np.complex64)
+    for b in range(batch):
+        g = out[b]
+        for _ in range(n_blobs):
+            c1, c2 = int(rng.integers(L1)), int(rng.integers(L2))
+            centre = rng.uniform(0.5, 1.0) * np.exp(1j * rng.uniform(0, 2 * np.pi))
+            for d2 in (-1, 0, 1):
+                for d1 in (-1, 0, 1):
+                    f = 1.0 if d1 == 0 and d2 == 0 else rng.uniform(0.0, 0.8)
+                    g[(c2 + d2) % L2, (c1 + d1) % L1] = centre * f * np.exp(1j * rng.uniform(-0.3, 0.3))
+        pos = rng.choice(L1 * L2, size=min(n_scatter, L1 * L2), replace=False)
+        g.reshape(-1)[pos] = (0.3 * rng.uniform(0, 1, len(pos)) * np.exp(1j * rng.uniform(0, 2 * np.pi, len(pos))))
+    return out
 
 
 def tiny_scene(idx: int = 0) -> Scene:
