@@ -219,6 +219,21 @@ def fft_matvec(Omega: np.ndarray, x: np.ndarray) -> np.ndarray:
     return np.fft.ifft2(Omega * np.fft.fft2(C)).reshape(L1 * L2)
 
 
+def fft_matvec_columns(Omega: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """eq. (23) applied to each column of X ([L][n]): column j is fft_matvec(Omega, X[:, j])."""
+    L2, L1 = Omega.shape
+    C = np.asarray(X, dtype=np.complex128).reshape(L2, L1, -1)
+    return np.fft.ifft2(Omega[:, :, None] * np.fft.fft2(C, axes=(0, 1)), axes=(0, 1)).reshape(L1 * L2, -1)
+
+
+def shifted_inverse_dense(op: "Operator", rho: float) -> np.ndarray:
+    """The explicit L x L matrix (G + rho I)^-1 of eq. (13), formed by the Woodbury identity
+    (1/rho)(I - D_s^H (rho I_M + D_s D_s^H)^-1 D_s) from the explicit D_s."""
+    Ds = sparse_dictionary(op.mask, op.L1, op.L2)
+    K = rho * np.eye(op.M) + Ds @ Ds.conj().T
+    return (np.eye(op.L) - Ds.conj().T @ np.linalg.solve(K, Ds)) / rho
+
+
 def dft_matrix(N: int) -> np.ndarray:
     k = np.arange(N)
     return np.exp(-1j * TWO_PI * np.outer(k, k) / N)
@@ -248,13 +263,17 @@ def step_size(op: Operator) -> float:
     return 1.0 / float(np.linalg.eigvalsh(op.outer_gram())[-1])
 
 
-def soft_threshold(z: np.ndarray, kappa: float) -> np.ndarray:
-    """S_kappa(z) = exp(j arg z) max(|z| - kappa, 0), and 0 where |z| <= kappa (R3)."""
+def soft_threshold(z: np.ndarray, kappa) -> np.ndarray:
+    """S_kappa(z) = exp(j arg z) max(|z| - kappa, 0), and 0 where |z| <= kappa (R3).
+
+    kappa may be an array broadcasting against z (e.g. one threshold per column when the
+    columns of z are independent problems); each element is thresholded by its own kappa."""
     z = np.asarray(z, dtype=np.complex128)
     a = np.abs(z)
     out = np.zeros_like(z)
     keep = a > kappa
-    out[keep] = z[keep] * (1.0 - kappa / a[keep])
+    k = np.broadcast_to(kappa, z.shape)[keep] if np.ndim(kappa) else kappa
+    out[keep] = z[keep] * (1.0 - k / a[keep])
     return out
 
 
