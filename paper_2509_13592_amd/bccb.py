@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import torch
@@ -191,6 +192,19 @@ def _raw_ptr(t) -> int:
     return t.data_ptr()
 
 
+def _release(obj) -> None:
+    """Finalizer of the handle classes: frees the library object, except while the interpreter
+    is shutting down -- then the HIP runtime, torch's streams and the library may already be
+    torn down in any order, so nothing is called into and the process exit reclaims the device
+    memory.  Explicit close() calls are unaffected."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
 def current_stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
@@ -229,10 +243,7 @@ class Plan:
             self._h = _vp()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
     def _args(self, y, **grids):
         """Addresses of a snapshot (complex64 [M]) and of coefficient grids (complex64
@@ -445,10 +456,7 @@ class Batch:
             self._h = _vp()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
     def classes(self):
         nc = ctypes.c_int()
@@ -531,10 +539,7 @@ class Lista:
             self._h = _vp()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
     @staticmethod
     def _taus(tau, B):
@@ -651,10 +656,7 @@ class Dense:
             self._h = _vp()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release(self)
 
     def apply(self, x, out=None):
         out = self.plan.grid(x.device) if out is None else out
