@@ -40,6 +40,7 @@ __all__ = [
     "spaced_scene",
     "angle_scene",
     "coefficient_grids",
+    "paper_sweep_trials",
     "CONFIG_ITERS",
 ]
 
@@ -222,6 +223,21 @@ def paper_sweep_scene(L1: int, idx: int = 0) -> Scene:
     K = int(rng.integers(1, 11))
     y, freqs, amps, sigma2 = _snapshot(rng, mask, K, None, 15.0)
     return Scene(mask, L1, 32, y, freqs, amps, sigma2, 15.0, 6, L1, idx)
+
+
+def paper_sweep_trials(L1: int, n: int = 10) -> list:
+    """n trials of the paper's runtime sweep geometry (Sec. III-C) on ONE array: the 51 x 16 URA
+    with 40 elements kept including the corners (drawn once for the whole sweep), L2 = 32,
+    L1 = the sweep value; each trial draws its own K ~ U{1..10} unit-modulus targets, harmonics
+    and 15 dB noise."""
+    mask = _random_mask(_rng(6, 0, 999), 51, 16, 40, keep_corners=True)
+    out = []
+    for idx in range(n):
+        rng = _rng(6, 1000 + L1, idx)
+        K = int(rng.integers(1, 11))
+        y, freqs, amps, sigma2 = _snapshot(rng, mask, K, None, 15.0)
+        out.append(Scene(mask, L1, 32, y, freqs, amps, sigma2, 15.0, 6, 1000 + L1, idx))
+    return out
 
 
 def paper_scale_scene(idx: int = 0) -> Scene:
