@@ -108,27 +108,54 @@ def _kernel_hash(resident: bool = False) -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(sc, tau, budget_s=12.0):
-    """FP64 oracle FISTA (steering-vector Gram, no FFT) on the host cores."""
-    import numpy as np
-    from oracle import bccb_oracle as O
+def host_info():
+    """CPU model, usable cores and RAM of the host the benchmark runs on."""
+    info = {"usable_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_GiB"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(sc, tau, budget_s=8.0, runs=5):
+    """FP64 oracle FISTA (steering-vector Gram, no FFT) on the host cores: the median rate of
+    `runs` timed runs (a bounded sample of about budget_s seconds), once with every usable core
+    and once with 16 BLAS threads (the paper's 16-core host)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import bccb_oracle as O
     P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=tau, dense=False)
-    iters = 20
-    t0 = time.perf_counter()
-    P.fista(iters)
-    dt = time.perf_counter() - t0
-    n = max(20, int(iters * budget_s / max(dt, 1e-6)))
-    n = min(n, 20000)
-    t0 = time.perf_counter()
-    P.fista(n)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} FP64 FISTA iterations on the 256x256 scene (factored D_s^H D_s, numpy)"}
+    usable = host_info()["usable_cores"]
+    res = {}
+    for threads in sorted({usable, 16}, reverse=True):
+        with threadpool_limits(limits=threads):
+            P.fista(10)
+            t0 = time.perf_counter()
+            P.fista(20)
+            per = (time.perf_counter() - t0) / 20
+            n = max(10, min(4000, int(budget_s / runs / max(per, 1e-6))))
+            rates = []
+            for _ in range(runs):
+                t0 = time.perf_counter()
+                P.fista(n)
+                rates.append(n / (time.perf_counter() - t0))
+        res[threads] = (float(np.median(rates)), n)
+    v, n = res[usable]
+    return {"value": round(v, 1), "unit": "iters/s", "cores": int(usable), "kind": "oracle",
+            "sample": f"median of {runs} runs of {n} FP64 FISTA iterations on the 256x256 scene "
+                      "(factored D_s^H D_s, numpy), all usable cores",
+            "sixteen_threads": {"value": round(res[16][0], 1), "iters_per_run": res[16][1]},
+            "host": host_info()}
 
 
 def cpu_fft_reference(B, plan, y, tau, budget_s=4.0):
@@ -171,32 +198,35 @@ def cpu_fft_reference(B, plan, y, tau, budget_s=4.0):
     return out
 
 
-def paper_sweep(B, S, reps=3):
+def paper_sweep(B, S, reps=3, trials=10):
     """The paper's runtime comparison (Sec. III-C) on this GPU: regular (explicit L x L matrix) vs
-    fast (BCCB passes) ISTA / FISTA / ADMM at its sweep geometry, and its Table I accuracy figure
-    eps_r = |c_reg - c_fast| / |c_reg| for each solver at 50..400 iterations."""
+    fast (BCCB passes) ISTA / FISTA / ADMM at its sweep geometry (one array, 10 trials per L1),
+    rates timed on the first trial, and its Table I accuracy figure eps_r = |c_reg - c_fast| /
+    |c_reg| for each solver at 50..400 iterations, the mean over the trials."""
     import numpy as np
     import torch
     rows = []
     for L1 in (64, 128, 256, 512):
-        sc = S.paper_sweep_scene(L1)
-        plan = B.Plan(sc.mask, sc.L1, sc.L2)
-        y = B.to_device(sc.y)
-        tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+        scs = S.paper_sweep_trials(L1, trials)
+        plan = B.Plan(scs[0].mask, L1, scs[0].L2)
+        ys = [B.to_device(sc.y) for sc in scs]
+        taus = [float(np.float32(0.1 * plan.adjoint_maxabs(y))) for y in ys]
         plan.autotune(50)
-        rho = float(np.count_nonzero(sc.mask))      # the Gram's diagonal; rho = 1 leaves z = 0 here
-        row = {"L1": L1, "L2": sc.L2, "L": sc.L1 * sc.L2}
+        rho = float(np.count_nonzero(scs[0].mask))      # the Gram's diagonal; rho = 1 leaves z = 0 here
+        row = {"L1": L1, "L2": scs[0].L2, "L": L1 * scs[0].L2, "trials": trials}
         for solver in ("ista", "fista", "admm"):
             dense = B.Dense(plan, kind=1 if solver == "admm" else 0, rho=rho)
-            fast = (lambda n: plan.admm(y, tau, rho, n)) if solver == "admm" else \
-                   (lambda n: getattr(plan, solver)(y, tau, n))
+
+            def fast(n, y, tau):
+                return plan.admm(y, tau, rho, n) if solver == "admm" else getattr(plan, solver)(y, tau, n)
+
             rate = {}
-            for name, fn, n in (("fast", fast, 400), ("regular", lambda n: dense.solve(solver, y, tau, n), 50)):
-                fn(n)
+            for name, fn, n in (("fast", fast, 400), ("regular", lambda n, y, t: dense.solve(solver, y, t, n), 50)):
+                fn(n, ys[0], taus[0])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(reps):
-                    fn(n)
+                    fn(n, ys[0], taus[0])
                 torch.cuda.synchronize()
                 rate[name] = reps * n / (time.perf_counter() - t0)
             row[solver] = {"fast_iters_per_s": round(rate["fast"], 1), "regular_iters_per_s": round(rate["regular"], 1),
@@ -206,20 +236,138 @@ def paper_sweep(B, S, reps=3):
             else:
                 col_ms, row_ms = plan.profile_passes(solver, 200)
                 row[solver].update({"col_pass_us": round(col_ms * 1e3, 2), "row_pass_us": round(row_ms * 1e3, 2)})
-            eps = {}
-            for n in (50, 100, 200, 400):
-                a = dense.solve(solver, y, tau, n).cpu().numpy().reshape(-1)
-                b = fast(n).cpu().numpy().reshape(-1)
-                eps[n] = float(np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-30))
-            row[solver]["eps_r_reg_vs_fast"] = {str(k): float(f"{v:.3g}") for k, v in eps.items()}
+            eps = {n: [] for n in (50, 100, 200, 400)}
+            for y, tau in zip(ys, taus):
+                for n in eps:
+                    a = dense.solve(solver, y, tau, n).cpu().numpy().reshape(-1)
+                    b = fast(n, y, tau).cpu().numpy().reshape(-1)
+                    eps[n].append(float(np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-30)))
+            row[solver]["eps_r_reg_vs_fast"] = {str(k): float(f"{np.mean(v):.3g}") for k, v in eps.items()}
             dense.close()
         row["launch_config"] = plan.get_config()
         plan.close()
         rows.append(row)
-    return {"workload": "51x16 URA, 40 elements (aperture kept), L2 = 32, K ~ U{1..10}, 15 dB; "
-                        "regular = explicit L x L complex64 matrix, fast = BCCB passes; ADMM rho = 40 "
-                        "(the number of kept elements)",
+    return {"workload": "51x16 URA, 40 elements (aperture kept, one array for every trial), L2 = 32, "
+                        "K ~ U{1..10}, 15 dB, 10 trials per L1; regular = explicit L x L complex64 matrix, "
+                        "fast = BCCB passes; ADMM rho = 40 (the number of kept elements); eps_r = mean over "
+                        "the trials (FP32 on both sides)",
             "rows": rows}
+
+
+def host_sweep(S, budget_s=1.5):
+    """The paper's own comparison on the host (its CPU formulation, Sec. III-C): FISTA with every
+    Gram product through the explicit L x L complex64 matrix (numpy BLAS) against the 2D FFT
+    product of eq. (23) (scipy.fft), per L1 of the sweep, with every usable core and with 16
+    threads.  Iterations per second per formulation (median of 3 timed runs) and the ratio."""
+    import numpy as np
+    import scipy.fft as sf
+    from threadpoolctl import threadpool_limits
+    usable = host_info()["usable_cores"]
+    rows = []
+    for L1 in (64, 128, 256, 512):
+        sc = S.paper_sweep_trials(L1, 1)[0]
+        L2 = sc.L2
+        m2, m1 = np.nonzero(sc.mask)
+        # D_s on the grid f_l = -1/2 + l/L (eqs. (5), (16)), phases from integer residues
+        e1 = np.exp(-2j * np.pi * (((np.arange(L1)[None, :] - L1 // 2) * m1[:, None]) % L1) / L1)
+        e2 = np.exp(-2j * np.pi * (((np.arange(L2)[None, :] - L2 // 2) * m2[:, None]) % L2) / L2)
+        Ds = (e2[:, :, None] * e1[:, None, :]).reshape(len(m1), L1 * L2)
+        G = (Ds.conj().T @ Ds).astype(np.complex64)
+        fold = np.zeros((L2, L1))
+        np.add.at(fold, (m2 % L2, m1 % L1), 1.0)
+        om = (L1 * L2 * fold).astype(np.float32)
+        b = (Ds.conj().T @ sc.y.astype(np.complex128)).astype(np.complex64)
+        mu = np.float32(1.0 / om.max())
+        kap = np.float32(mu * 0.1 * np.abs(b).max())
+        row = {"L1": L1, "L": L1 * L2}
+        for threads in sorted({usable, 16}, reverse=True):
+            res = {}
+            for name in ("regular", "fast"):
+                def step(z, c_prev, a):
+                    if name == "regular":
+                        g = G @ z
+                    else:
+                        g = sf.ifft2(om * sf.fft2(z.reshape(L2, L1), workers=threads), workers=threads).reshape(-1)
+                    u = z - mu * g + mu * b
+                    mag = np.abs(u)
+                    c = u * np.maximum(1.0 - kap / np.maximum(mag, 1e-30), 0.0)
+                    an = (1.0 + np.sqrt(1.0 + 4.0 * a * a)) / 2.0
+                    return c + np.float32((a - 1.0) / an) * (c - c_prev), c, an
+
+                with threadpool_limits(limits=threads):
+                    z = np.zeros(L1 * L2, dtype=np.complex64)
+                    c, a = z.copy(), 1.0
+                    t0 = time.perf_counter()
+                    z, c, a = step(z, c, a)
+                    per = time.perf_counter() - t0
+                    n = max(2, min(2000, int(budget_s / 3 / max(per, 1e-6))))
+                    rates = []
+                    for _ in range(3):
+                        t0 = time.perf_counter()
+                        for _ in range(n):
+                            z, c, a = step(z, c, a)
+                        rates.append(n / (time.perf_counter() - t0))
+                res[name] = float(np.median(rates))
+            row[f"threads_{threads}"] = {"regular_iters_per_s": round(res["regular"], 1),
+                                         "fast_iters_per_s": round(res["fast"], 1),
+                                         "speedup": round(res["fast"] / res["regular"], 1)}
+        rows.append(row)
+        del G
+    return {"workload": "FISTA on the host at the sweep geometry (51x16 URA, 40 kept, L2 = 32), complex64: "
+                        "regular = explicit L x L matrix (numpy BLAS), fast = scipy.fft 2D FFT product",
+            "host": host_info(), "rows": rows}
+
+
+def spaced_run(B, S, iters=300, reps=5):
+    """Padded-embedding plans on this GPU: FISTA on a Toeplitz Gram (element spacing 0.4, 16x16
+    URA with 64 kept, 256x256 grid, embedded in 512x512) and on a half-spacing grid whose length
+    is not a power of two (384x384, embedded in 1024x1024); iterations per second, and the bytes
+    an iteration of the full passes moves on the padded grid (36 B per padded point)."""
+    import numpy as np
+    import torch
+    rows = []
+    for name, g, L in (("toeplitz gamma 0.4, 256x256", 0.4, 256), ("half spacing, 384x384", 0.5, 384)):
+        sc = S.spaced_scene(g, g, 16, 16, 64, L, L, K=5, snr_db=20.0, seed=(7, 9, L))
+        plan = B.SpacedPlan(sc.mask, L, L, g, g)
+        plan.autotune(20)
+        P1, P2, _ = plan.embedding()
+        y = B.to_device(sc.y)
+        tau = float(np.float32(0.1 * plan.adjoint_maxabs(y)))
+        out = plan.grid()
+        plan.fista(y, tau, iters, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.fista(y, tau, iters, out=out)
+        torch.cuda.synchronize()
+        rate = reps * iters / (time.perf_counter() - t0)
+        gbps = ALGO_BYTES_PER_POINT["fista"] * P1 * P2 * rate / 1e9
+        rows.append({"workload": name, "grid": [L, L], "embedding": [P1, P2], "fista_iters_per_s": round(rate, 1),
+                     "padded_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)})
+        plan.close()
+    return rows
+
+
+def extract_run(B, S, batch=1024, L=256, max_peaks=16, reps=5):
+    """bccb_extract_peaks over `batch` synthetic 256x256 coefficient grids (6 blobs and 40 isolated
+    entries each): grids per second, and the grid bytes read once per launch against HBM peak."""
+    import numpy as np
+    import torch
+    plan = B.Plan(np.ones((4, 4), dtype=np.uint8), L, L)
+    grids = S.coefficient_grids((9, 0, L), batch, L, L)
+    c = B.to_device(grids)
+    del grids
+    peaks, counts = B.extract_peaks_device(plan, c, max_peaks, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):      # each call returns after its stream has drained
+        B.extract_peaks_device(plan, c, max_peaks, 0.0, peaks, counts)
+    dt = (time.perf_counter() - t0) / reps
+    gbps = batch * L * L * 8 / dt / 1e9
+    plan.close()
+    return {"workload": f"{batch} grids of {L}x{L}, up to {max_peaks} peaks each, results left on the device",
+            "grids_per_s": round(batch / dt, 1), "grid_GBps": round(gbps, 1),
+            "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)}
 
 
 def copy_ceiling(B, gib=4.0, reps=5):
@@ -426,7 +574,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
-    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned", "large"],
+    ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned", "large",
+                                       "extras"],
                     default="all",
                     help="subsets: the single-scene solve only, the batched workloads only, a uniform "
                          "256^2 batch only (profiling), a plain 1 GiB device copy (counter calibration), "
@@ -464,7 +613,10 @@ def main():
         print(json.dumps({"batched": batched_runs(args)}))
         return
     if args.only == "sweep":
-        print(json.dumps({"paper_sweep": paper_sweep(B, S)}))
+        print(json.dumps({"paper_sweep": paper_sweep(B, S), "host_sweep": host_sweep(S)}))
+        return
+    if args.only == "extras":
+        print(json.dumps({"spaced_plans": spaced_run(B, S), "extract_peaks": extract_run(B, S)}))
         return
     if args.only == "learned":
         print(json.dumps({"learned_vs_plain": learned_run(B, S, args.learned_scenes)}))
@@ -566,9 +718,13 @@ def main():
         rec["large_admm"] = large_admm_run(B, S)
     if not args.no_learned:
         rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes)
+    rec["spaced_plans"] = spaced_run(B, S)
+    rec["extract_peaks"] = extract_run(B, S)
     rec["hbm_copy_ceiling"] = copy_ceiling(B)
     if not args.no_dense:
         rec["paper_sweep"] = paper_sweep(B, S)
+    if not args.no_cpu_baseline:
+        rec["host_sweep"] = host_sweep(S)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, tau)
         plan2 = B.Plan(sc.mask, sc.L1, sc.L2)

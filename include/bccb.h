@@ -107,11 +107,14 @@ int bccb_plan(const uint8_t* mask, int M1, int M2, int L1, int L2, void* stream,
  *   Grids passed to the calls below stay the caller's [L2][L1] grids.
  *   A plan made here serves bccb_plan_info (M and mu; omega_host must be
  *   NULL), bccb_adjoint, bccb_adjoint_maxabs, bccb_gram_apply,
- *   lasso_solve_ista, lasso_solve_fista, bccb_objective_kkt, bccb_kkt and,
- *   at gamma1 = gamma2 = 1/2 only, lasso_solve_admm ((G + rho I)^-1 is then
- *   the BCCB of spectrum 1/(Omega + rho), Sec. III-A (ii), embedded the same
- *   way; the inverse of a Toeplitz Gram is not Toeplitz); every other call
- *   returns BCCB_E_UNSUPPORTED for it.  Memory: about 70 bytes per point of
+ *   lasso_solve_ista, lasso_solve_fista, bccb_objective_kkt, bccb_kkt,
+ *   bccb_extract_peaks, bccb_plan_get_config, bccb_plan_set_config and
+ *   bccb_plan_autotune (the full row and column passes' shapes; sparse_iterate
+ *   and resident_groups are refused) and, at gamma1 = gamma2 = 1/2 only,
+ *   lasso_solve_admm ((G + rho I)^-1 is then the BCCB of spectrum
+ *   1/(Omega + rho), Sec. III-A (ii), embedded the same way; the inverse of a
+ *   Toeplitz Gram is not Toeplitz); every other call returns
+ *   BCCB_E_UNSUPPORTED for it.  Memory: about 70 bytes per point of
  *   the P1 x P2 grid.
  */
 int bccb_plan_spaced(const uint8_t* mask, int M1, int M2, int L1, int L2, double gamma1, double gamma2,

@@ -392,16 +392,31 @@ PEAK_DTYPE = np.dtype([("index", np.int32), ("mag2", np.float32), ("f1", np.floa
                        ("phi", np.float32), ("theta", np.float32), ("amp_re", np.float32), ("amp_im", np.float32)])
 
 
+def extract_peaks_device(plan: "Plan", c: torch.Tensor, max_peaks: int, min_mag2: float = 0.0, peaks=None,
+                         counts=None):
+    """bccb_extract_peaks into device buffers: (peaks, counts), peaks a uint8 tensor of
+    batch * max_peaks bccb_peak records (PEAK_DTYPE), counts int32 [batch] (-1: more than 4096
+    local maxima above min_mag2).  c: [L2][L1] or [batch][L2][L1] complex64 on the GPU."""
+    batch = 1 if c.dim() == 2 else int(c.shape[0])
+    (pc,) = _ptrs((c, batch * plan.L, "c"))
+    nbytes = batch * int(max_peaks) * PEAK_DTYPE.itemsize
+    if peaks is None:
+        peaks = torch.empty(nbytes, dtype=torch.uint8, device=c.device)
+    if counts is None:
+        counts = torch.empty(batch, dtype=torch.int32, device=c.device)
+    if peaks.dtype != torch.uint8 or peaks.numel() != nbytes or counts.dtype != torch.int32 or counts.numel() != batch:
+        raise ValueError("peaks: uint8 [batch * max_peaks * 32], counts: int32 [batch]")
+    check(lib.bccb_extract_peaks(plan.handle, pc, batch, int(max_peaks), float(min_mag2), _raw_ptr(peaks),
+                                 _raw_ptr(counts)), "bccb_extract_peaks")
+    return peaks, counts
+
+
 def extract_peaks(plan: "Plan", c: torch.Tensor, max_peaks: int, min_mag2: float = 0.0):
     """bccb_extract_peaks over c ([L2][L1] or [batch][L2][L1], complex64 on the GPU, the plan's
     grid): a list per grid of PEAK_DTYPE records, strongest first (None for a grid with more
     than 4096 local maxima above min_mag2)."""
     batch = 1 if c.dim() == 2 else int(c.shape[0])
-    (pc,) = _ptrs((c, batch * plan.L, "c"))
-    peaks = torch.empty(batch * int(max_peaks) * PEAK_DTYPE.itemsize, dtype=torch.uint8, device=c.device)
-    counts = torch.empty(batch, dtype=torch.int32, device=c.device)
-    check(lib.bccb_extract_peaks(plan.handle, pc, batch, int(max_peaks), float(min_mag2), _raw_ptr(peaks),
-                                 _raw_ptr(counts)), "bccb_extract_peaks")
+    peaks, counts = extract_peaks_device(plan, c, max_peaks, min_mag2)
     rec = peaks.cpu().numpy().view(PEAK_DTYPE).reshape(batch, int(max_peaks))
     n = counts.cpu().numpy()
     return [None if n[i] < 0 else rec[i, :n[i]].copy() for i in range(batch)]

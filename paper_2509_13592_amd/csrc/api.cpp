@@ -989,7 +989,8 @@ int bccb_plan_get_config(bccb_plan_t p, bccb_config* cfg) {
 
 int bccb_plan_set_config(bccb_plan_t p, const bccb_config* cfg) {
   if (!p || !cfg) return BCCB_E_INVALID;
-  if (p->emb) return BCCB_E_UNSUPPORTED;
+  // padded-embedding plans run the full passes only: their shapes can be set, the other forms not
+  if (p->emb && (cfg->sparse_iterate || cfg->resident_groups)) return BCCB_E_UNSUPPORTED;
   PassCfg r, c;
   r.E = cfg->row_elems;
   r.rpb = cfg->row_rows_per_block;
@@ -1050,8 +1051,7 @@ static RowArgs pruned_work_args(bccb_plan_s* p) {
 }
 
 int bccb_plan_autotune(bccb_plan_t p, int reps, bccb_config* chosen) {
-  if (!p || reps < 1) return BCCB_E_INVALID;
-  if (p->emb) return BCCB_E_UNSUPPORTED;
+  if (!p || reps < 1) return BCCB_E_INVALID;   // padded-embedding plans: the full passes' shapes only
   hipStream_t st = p->stream;
   RowArgs a;
   a.xy = p->d_xy;

@@ -106,3 +106,32 @@ def test_chain_on_gpu_recovers_harmonics():
     print(f"case chain: distances {np.round(d, 5)} (cell {1 / 128:.4f})", flush=True)
     assert len(pairs) == 4 and max(d) <= 1.0 / 128
     plan.close()
+
+
+def test_extract_odd_sized_grid():
+    """A half-spacing grid of 45 x 27 points (an odd count: the kernel reads single points, not
+    pairs), wrapping at the edges."""
+    L1, L2 = 45, 27
+    grids = S.coefficient_grids((9, 2, 3), 3, L1, L2)
+    sc = S.spaced_scene(0.5, 0.5, 7, 5, 20, L1, L2, K=2, snr_db=20.0)
+    plan = B.SpacedPlan(sc.mask, L1, L2, 0.5, 0.5)
+    recs = plan.extract_peaks(B.to_device(grids), 12, 0.0)
+    for b in range(3):
+        _compare(recs[b], X.extract(grids[b], 12, 0.0), (L1, L2, b))
+    plan.close()
+
+
+def test_extract_more_peaks_than_threads():
+    """600 isolated maxima and max_peaks = 400 (more peaks than the selecting workgroup has
+    threads): the 400 strongest, in order, as the oracle lists them."""
+    L = 128
+    rng = np.random.default_rng(21)
+    g = np.zeros((L, L), dtype=np.complex64)
+    pos = rng.choice((L // 2) * (L // 2), 600, replace=False)
+    r2, r1 = 2 * (pos // (L // 2)), 2 * (pos % (L // 2))
+    g[r2, r1] = (rng.uniform(0.1, 1.0, 600) * np.exp(1j * rng.uniform(0, 2 * np.pi, 600))).astype(np.complex64)
+    plan = B.Plan(np.ones((2, 2), dtype=np.uint8), L, L)
+    rec = plan.extract_peaks(B.to_device(g), 400, 0.0)[0]
+    _compare(rec, X.extract(g, 400, 0.0), "many")
+    assert len(rec) == 400
+    plan.close()

@@ -146,12 +146,29 @@ def test_spaced_admm_circulant(geom, rho):
     plan.close()
 
 
+def test_spaced_autotuned_shapes_keep_parity():
+    """Autotuned pass shapes (the only configuration a padded-embedding plan takes) give the
+    oracle's FISTA iterate as the default shapes do."""
+    name, g1, g2, M1, M2, M, L1, L2, K = GEOMS[1]
+    sc, P, plan, emb = _setup(name, g1, g2, M1, M2, M, L1, L2, K)
+    cfg = plan.autotune(5)
+    print(f"  tuned shapes {cfg}", flush=True)
+    assert not cfg["resident_groups"] and not cfg["sparse_iterate"]
+    y = B.to_device(sc.y)
+    T = 150
+    g = _np(plan.fista(y, P.tau, T))
+    ref = P.fista(T)
+    Fr = P.objective(ref)
+    assert abs(P.objective(g) - Fr) <= OBJ_TOL * Fr and _rel(g, ref) <= iter_tol(T, emb[0] * emb[1])
+    plan.close()
+
+
 def test_spaced_plan_refusals():
     sc = S.spaced_scene(0.25, 0.25, 6, 5, 17, 12, 10, K=2, snr_db=20.0)
     plan = B.SpacedPlan(sc.mask, 12, 10, 0.25, 0.25)
     y = B.to_device(sc.y)
-    for call in (lambda: plan.admm(y, 0.1, 1.0, 5), lambda: plan.set_config(row_elems=4), lambda: plan.omega(),
-                 lambda: plan.autotune(2), lambda: plan.fista_noalloc(y, 0.1, 5)):
+    for call in (lambda: plan.admm(y, 0.1, 1.0, 5), lambda: plan.set_config(resident_groups=4), lambda: plan.omega(),
+                 lambda: plan.set_config(sparse_iterate=1), lambda: plan.fista_noalloc(y, 0.1, 5)):
         with pytest.raises(B.BCCBError) as e:
             call()
         assert e.value.code == B.BCCB_E_UNSUPPORTED
