@@ -192,12 +192,13 @@ def _raw_ptr(t) -> int:
     return t.data_ptr()
 
 
-def _release(obj) -> None:
+def _release(obj, _finalizing=sys.is_finalizing) -> None:
     """Finalizer of the handle classes: frees the library object, except while the interpreter
     is shutting down -- then the HIP runtime, torch's streams and the library may already be
     torn down in any order, so nothing is called into and the process exit reclaims the device
-    memory.  Explicit close() calls are unaffected."""
-    if sys.is_finalizing():
+    memory.  Explicit close() calls are unaffected.  (Bound as a default argument of every
+    __del__, since module globals may already be cleared when a finalizer runs at shutdown.)"""
+    if _finalizing():
         return
     try:
         obj.close()
@@ -242,7 +243,7 @@ class Plan:
             lib.bccb_plan_destroy(self._h)
             self._h = _vp()
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
     def _args(self, y, **grids):
@@ -470,7 +471,7 @@ class Batch:
             lib.bccb_batch_destroy(self._h)
             self._h = _vp()
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
     def classes(self):
@@ -553,7 +554,7 @@ class Lista:
             lib.lista_destroy(self._h)
             self._h = _vp()
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
     @staticmethod
@@ -670,7 +671,7 @@ class Dense:
             lib.bccb_dense_destroy(self._h)
             self._h = _vp()
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self)
 
     def apply(self, x, out=None):
