@@ -45,6 +45,7 @@ extern "C" {
 
 typedef struct bccb_plan_s* bccb_plan_t;
 typedef struct { float re, im; } bccb_c32;
+typedef struct { double re, im; } bccb_c64;
 
 enum bccb_status {
   BCCB_OK = 0,
@@ -270,6 +271,24 @@ typedef struct {
  */
 int bccb_extract_peaks(bccb_plan_t plan, const bccb_c32* c, int batch, int max_peaks, float min_mag2,
                        bccb_peak* peaks, int* counts);
+
+/*
+ * FP64 variants -- the same operations in complex128 on the device, for results at the
+ * level of the paper's FP64 regular-vs-fast comparison (Table I, Sec. III-C): eigenvalues by
+ * eq. (21) in FP64, radix-2 FFTs and updates in double precision, the full row and column
+ * passes (no pruned or cooperative forms).  Plans from bccb_plan (power-of-two grids); the
+ * FP64 buffers (56 bytes per grid point) are allocated on the first FP64 call.  Arguments,
+ * layouts and errors as the FP32 calls, with complex128 device buffers (bccb_c64) and FP64
+ * tau and rho; BCCB_E_UNSUPPORTED for a bccb_plan_spaced plan with a padded embedding.
+ */
+int bccb_adjoint_f64(bccb_plan_t plan, const bccb_c64* y, bccb_c64* b);
+int bccb_gram_apply_f64(bccb_plan_t plan, const bccb_c64* x, bccb_c64* gx);
+int lasso_solve_ista_f64(bccb_plan_t plan, const bccb_c64* y, double tau, int iters, const bccb_c64* c0,
+                         bccb_c64* c_out);
+int lasso_solve_fista_f64(bccb_plan_t plan, const bccb_c64* y, double tau, int iters, const bccb_c64* c0,
+                          bccb_c64* c_out);
+int lasso_solve_admm_f64(bccb_plan_t plan, const bccb_c64* y, double tau, double rho, int iters, bccb_c64* z_out,
+                         bccb_c64* c_out);
 
 /*
  * Batched solves -- many independent snapshots, each with its own plan (its

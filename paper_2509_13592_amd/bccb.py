@@ -78,6 +78,11 @@ _SIGS = {
     "bccb_plan_spaced": (_i, [_vp, _i, _i, _i, _i, _d, _d, _vp, ctypes.POINTER(_vp)]),
     "bccb_plan_embedding": (_i, [_vp, _pi, _pi, _vp]),
     "bccb_extract_peaks": (_i, [_vp, _vp, _i, _i, _f, _vp, _vp]),
+    "bccb_adjoint_f64": (_i, [_vp, _vp, _vp]),
+    "bccb_gram_apply_f64": (_i, [_vp, _vp, _vp]),
+    "lasso_solve_ista_f64": (_i, [_vp, _vp, _d, _i, _vp, _vp]),
+    "lasso_solve_fista_f64": (_i, [_vp, _vp, _d, _i, _vp, _vp]),
+    "lasso_solve_admm_f64": (_i, [_vp, _vp, _d, _d, _i, _vp, _vp]),
     "bccb_set_stream": (_i, [_vp, _vp]),
     "bccb_plan_info": (_i, [_vp, _pi, _pd, _vp]),
     "bccb_adjoint": (_i, [_vp, _vp, _vp]),
@@ -295,6 +300,48 @@ class Plan:
         check(lib.lasso_solve_fista(self._h, py, float(tau), int(iters), pc, po),
               "lasso_solve_fista")
         return out
+
+    # --- FP64 variants (complex128 device tensors) ---
+    def _args64(self, y, **grids):
+        for t, n, what in [(y, self.M, "y")] + [(t, self.L, k) for k, t in grids.items()]:
+            _check_host_side(t, n, what, torch.complex128)
+        return [_raw_ptr(y)] + [None if t is None else _raw_ptr(t) for t in grids.values()]
+
+    def grid64(self, device="cuda") -> torch.Tensor:
+        return torch.empty((self.L2, self.L1), dtype=torch.complex128, device=device)
+
+    def adjoint_f64(self, y, out=None):
+        out = self.grid64(y.device) if out is None else out
+        py, po = self._args64(y, out=out)
+        check(lib.bccb_adjoint_f64(self._h, py, po), "bccb_adjoint_f64")
+        return out
+
+    def gram_apply_f64(self, x, out=None):
+        out = self.grid64(x.device) if out is None else out
+        _check_host_side(x, self.L, "x", torch.complex128)
+        _check_host_side(out, self.L, "out", torch.complex128)
+        check(lib.bccb_gram_apply_f64(self._h, _raw_ptr(x), _raw_ptr(out)), "bccb_gram_apply_f64")
+        return out
+
+    def ista_f64(self, y, tau: float, iters: int, c0=None, out=None):
+        out = self.grid64(y.device) if out is None else out
+        py, pc, po = self._args64(y, c0=c0, out=out)
+        check(lib.lasso_solve_ista_f64(self._h, py, float(tau), int(iters), pc, po), "lasso_solve_ista_f64")
+        return out
+
+    def fista_f64(self, y, tau: float, iters: int, c0=None, out=None):
+        out = self.grid64(y.device) if out is None else out
+        py, pc, po = self._args64(y, c0=c0, out=out)
+        check(lib.lasso_solve_fista_f64(self._h, py, float(tau), int(iters), pc, po), "lasso_solve_fista_f64")
+        return out
+
+    def admm_f64(self, y, tau: float, rho: float, iters: int, want_c=False):
+        z = self.grid64(y.device)
+        c = self.grid64(y.device) if want_c else None
+        py, pz, pc = self._args64(y, z=z, c=c)
+        check(lib.lasso_solve_admm_f64(self._h, py, float(tau), float(rho), int(iters), pz, pc),
+              "lasso_solve_admm_f64")
+        return (z, c) if want_c else z
 
     def extract_peaks(self, c, max_peaks: int, min_mag2: float = 0.0):
         return extract_peaks(self, c, max_peaks, min_mag2)

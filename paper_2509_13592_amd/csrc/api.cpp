@@ -57,6 +57,12 @@ void plan_free(bccb_plan_s* p) {
   dfree(p->d_emb_coef);
   dfree(p->d_cand);
   dfree(p->d_ccount);
+  dfree(p->d_omega64);
+  dfree(p->d_tw1_64);
+  dfree(p->d_tw2_64);
+  dfree(p->d_xy64);
+  dfree(p->d_rhs64);
+  dfree(p->d_state64);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   dfree(p->d_omega);
   dfree(p->d_sensor_of);

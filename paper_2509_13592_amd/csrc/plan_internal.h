@@ -115,6 +115,14 @@ struct bccb_plan_s {
   float2* d_emb_coef = nullptr;    // [2] multiplier coefficients of the ADMM passes
   float emb_rho = -1.f;            // rho d_omega_rho was built for
 
+  // FP64 passes (solve_f64.cpp), allocated on the first FP64 call: eigenvalues, twiddles, grids
+  double* d_omega64 = nullptr;
+  double2* d_tw1_64 = nullptr;
+  double2* d_tw2_64 = nullptr;
+  double2* d_xy64 = nullptr;
+  double2* d_rhs64 = nullptr;
+  double2* d_state64 = nullptr;
+
   // peak extraction (bccb_extract_peaks): candidate keys [cand_batch][4096] and counts
   unsigned long long* d_cand = nullptr;
   int* d_ccount = nullptr;
