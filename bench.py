@@ -528,12 +528,12 @@ def large_admm_run(B, S, iters=300, reps=3, launch=None):
             "launch_config": tuned}
 
 
-def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000):
+def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000, weights=None):
     """Scenes/s to r_KKT <= 1e-4: learned 16-layer network + KKT-gated FISTA vs plain FISTA."""
     import numpy as np
     import torch
     from paper_2509_13592_amd import train_lista as T
-    params, rec = T.load_params()
+    params, rec = T.load_params(weights or T.DEFAULT_OUT)
     mask = S.learned_fixed_mask()
     plan = B.Plan(mask, 256, 256)
     ys, taus = T.make_split(B, plan, 1, 0, n, mask)
@@ -554,7 +554,8 @@ def learned_run(B, S, n, target=1e-4, check_every=10, cap=20000):
     out["speedup_learned_over_plain"] = round(out["learned"]["scenes_per_s"] / out["plain"]["scenes_per_s"], 4)
     out["workload"] = (f"{n} held-out scenes, 16x16 URA fixed 64-element mask, 256^2 grid, K~U{{1..8}}, "
                        f"SNR~U[10,30] dB; target r_KKT <= {target}, checked every {check_every} iterations")
-    out["weights"] = {"train_scenes": rec["train_scenes"], "label_iters": rec["label_iters"],
+    out["weights"] = {"file": os.path.basename(weights or T.DEFAULT_OUT),
+                      "train_scenes": rec["train_scenes"], "label_iters": rec["label_iters"],
                       "steps": rec["steps"], "final_val_loss": rec["val_loss_curve"][-1][1]}
     out["fallback"] = "plain FISTA continuing the unrolled momentum (identity weights = plain FISTA)"
     net.close()
@@ -574,6 +575,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-scenes", type=int, default=8192)
+    ap.add_argument("--lista-weights", type=str, default=None,
+                    help="weights file of the learned solver (default: the packaged 16-layer weights)")
     ap.add_argument("--only", choices=["all", "single", "batched", "batch256", "calib", "sweep", "learned", "large",
                                        "extras"],
                     default="all",
@@ -619,7 +622,7 @@ def main():
         print(json.dumps({"spaced_plans": spaced_run(B, S), "extract_peaks": extract_run(B, S)}))
         return
     if args.only == "learned":
-        print(json.dumps({"learned_vs_plain": learned_run(B, S, args.learned_scenes)}))
+        print(json.dumps({"learned_vs_plain": learned_run(B, S, args.learned_scenes, weights=args.lista_weights)}))
         return
     if args.only == "large":
         print(json.dumps({"large_admm": large_admm_run(B, S, launch=json.loads(args.launch) if args.launch else None)}))
@@ -717,7 +720,7 @@ def main():
     if not args.no_large:
         rec["large_admm"] = large_admm_run(B, S)
     if not args.no_learned:
-        rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes)
+        rec["learned_vs_plain"] = learned_run(B, S, args.learned_scenes, weights=args.lista_weights)
     rec["spaced_plans"] = spaced_run(B, S)
     rec["extract_peaks"] = extract_run(B, S)
     rec["hbm_copy_ceiling"] = copy_ceiling(B)
