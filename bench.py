@@ -410,13 +410,24 @@ def _batch_rate(B, scenes, iters, reps, tune=True):
     batch = B.Batch(plans)
     if tune:
         batch.autotune(reps=5)
-    outs = batch.fista(ys, taus, iters)          # warm-up (captures the graph)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        batch.fista(ys, taus, iters, outs=outs)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+
+    def timed():
+        batch.fista(ys, taus, iters, outs=outs)   # warm-up (captures the graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batch.fista(ys, taus, iters, outs=outs)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    outs = [p.grid(ys[0].device) for p in plans]
+    resident = batch.resident_info()
+    graph_dt = None
+    if resident["on"] == 1:
+        batch.set_resident(False)                 # the per-iteration pass graph, for comparison
+        graph_dt = timed()
+        batch.set_resident(True)
+    dt = timed()
     classes = []
     algo = 0
     for (L1, L2, n), cfg in zip(batch.classes(), batch.class_configs()):
@@ -436,6 +447,9 @@ def _batch_rate(B, scenes, iters, reps, tune=True):
     batch.close()
     for p in plans:
         p.close()
+    if resident["on"] == 1:
+        classes.append({"persistent_launch": resident, "pass_graph_s_per_solve": round(graph_dt, 5),
+                        "speedup_over_pass_graph": round(graph_dt / dt, 3)})
     return dt, classes, algo
 
 
@@ -461,6 +475,8 @@ def batched_runs(args):
                           "scene_iters_per_s": round(n2 * it2 / dt2, 1), "classes": cls2,
                           **_batch_roofline(algo2 * it2, dt2)}
     launch = cls2[0]["launch"]
+    if any("persistent_launch" in c for c in cls2):
+        launch = dict(launch, pruned=0)   # the counted pass traffic does not describe the persistent launch
     key = (launch["row_E"], launch["rows_per_block"], launch["col_E"], launch["cols_per_block"])
     counted = BATCH_TRAFFIC.get(_kernel_hash(), {}).get(key) if launch["pruned"] else None
     out["uniform_256"]["counted_bytes_per_point"] = counted

@@ -354,6 +354,31 @@ int bccb_batch_set_sparse_iterate(bccb_batch_t batch, int on);
 int bccb_batch_set_support_columns(bccb_batch_t batch, int on);
 
 /*
+ * bccb_batch_set_resident -- 1 (the default where the batch supports it): run
+ *   the solve as one persistent launch in which each workgroup takes whole
+ *   scenes from a queue (larger grids first) and runs every FISTA iteration of
+ *   a scene (eqs. (10)-(12), the eq. (23) product in the support-column form)
+ *   with its kept row spectra held in LDS; 0: the captured per-iteration pass
+ *   graph.  Supported when every size class is square (L1 = L2 in 32, 64, 128,
+ *   256), every scene has a kept-column set and a workgroup's state fits the
+ *   device's LDS; the path is taken only while support columns are on.
+ *   Results agree with the pass graph to FP32 rounding.  on = 256, 512 or 1024
+ *   selects the persistent launch at that workgroup size (1 takes the size that
+ *   keeps the most waves resident).  BCCB_E_UNSUPPORTED for a nonzero value on a
+ *   batch without support (or a workgroup size whose LDS does not fit),
+ *   BCCB_E_INVALID for a null batch or another value.
+ */
+int bccb_batch_set_resident(bccb_batch_t batch, int on);
+
+/*
+ * bccb_batch_resident_info -- *on = 1 if the persistent launch is selected, 0 if
+ *   it is supported but off, -1 if the batch cannot take it; *threads, *blocks,
+ *   *lds_bytes: its workgroup size, grid and dynamic LDS per workgroup (0 when
+ *   unsupported).  Any output pointer may be null.
+ */
+int bccb_batch_resident_info(bccb_batch_t batch, int* on, int* threads, int* blocks, int* lds_bytes);
+
+/*
  * Learned unrolled FISTA with a KKT-gated plain-FISTA fallback.
  *
  * Network (all scenes share one plan, i.e. one array mask and grid): layer k,

@@ -118,6 +118,8 @@ _SIGS = {
     "bccb_plan_support_columns": (_i, [_vp, _pi, _pi]),
     "bccb_batch_set_sparse_iterate": (_i, [_vp, _i]),
     "bccb_batch_set_support_columns": (_i, [_vp, _i]),
+    "bccb_batch_set_resident": (_i, [_vp, _i]),
+    "bccb_batch_resident_info": (_i, [_vp, _pi, _pi, _pi, _pi]),
     "bccb_batch_class_config": (_i, [_vp, _i, _pi]),
     "lista_autotune": (_i, [_vp, _i]),
     "bccb_stream_copy": (_i, [_vp, _vp, ctypes.c_size_t, _i, _vp]),
@@ -547,6 +549,17 @@ class Batch:
 
     def set_sparse_iterate(self, on: bool):
         check(lib.bccb_batch_set_sparse_iterate(self._h, 1 if on else 0), "bccb_batch_set_sparse_iterate")
+
+    def set_resident(self, on):
+        """False / True, or a workgroup size (256, 512, 1024) for the persistent launch."""
+        v = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        check(lib.bccb_batch_set_resident(self._h, v), "bccb_batch_set_resident")
+
+    def resident_info(self):
+        """{"on": 1 | 0 | -1 (unsupported), "threads", "blocks", "lds_bytes"} of the persistent launch."""
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib.bccb_batch_resident_info(self._h, *[ctypes.byref(x) for x in v]), "bccb_batch_resident_info")
+        return dict(zip(("on", "threads", "blocks", "lds_bytes"), (x.value for x in v)))
 
     def fista(self, ys, taus, iters: int, outs=None):
         n = self.n

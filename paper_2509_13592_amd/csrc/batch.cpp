@@ -10,9 +10,11 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "batch_layout.h"
+#include "batch_resident.h"
 #include "bccb.h"
 #include "kernels.h"
 #include "plan_internal.h"
@@ -79,6 +81,16 @@ struct bccb_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_iters = -1;
+  // whole solves in one persistent launch (batch_resident.h), when every class is a
+  // square support-column class of 32..256 points whose workgroup state fits in LDS
+  bool res_ok = false, res_on = false;
+  ResidentClass* d_rcls = nullptr;
+  int res_ncls = 0, res_threads = 0, res_blocks = 0;
+  size_t res_lds = 0;
+  int* d_queue = nullptr;
+  float* d_beta = nullptr;        // [beta_cap] momentum weights of the last iteration count
+  float* h_beta = nullptr;        // pinned
+  int beta_cap = 0;
 };
 
 namespace {
@@ -105,6 +117,9 @@ void batch_free(bccb_batch_s* b) {
   }
   if (b->d_flag) (void)hipFree(b->d_flag);
   if (b->h_flag) (void)hipHostFree(b->h_flag);
+  for (void* p : {static_cast<void*>(b->d_rcls), static_cast<void*>(b->d_queue), static_cast<void*>(b->d_beta)})
+    if (p) (void)hipFree(p);
+  if (b->h_beta) (void)hipHostFree(b->h_beta);
   if (b->h_desc) (void)hipHostFree(b->h_desc);
   if (b->h_kscale) (void)hipHostFree(b->h_kscale);
   delete b;
@@ -255,6 +270,91 @@ int fista_loop(bccb_batch_s* b, int iters, hipStream_t s) {
   return BCCB_OK;
 }
 
+// The persistent whole-solve path: class table in queue order (larger grids first, so
+// the last scenes taken are the short ones), and the workgroup size that keeps the most
+// waves resident per compute unit.  Leaves res_ok false when some class does not fit.
+int resident_setup(bccb_batch_s* b) {
+  b->res_ok = b->res_on = false;
+  std::vector<int> order(b->cls.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cls[x].L > b->cls[y].L; });
+  std::vector<ResidentClass> table;
+  int first = 0;
+  for (int ci : order) {
+    const BatchClass& c = b->cls[ci];
+    const bool len_ok = c.L1 == 32 || c.L1 == 64 || c.L1 == 128 || c.L1 == 256;
+    if (!c.can_prune || c.L1 != c.L2 || !len_ok || c.ncs < 1) return BCCB_OK;
+    ResidentClass r;
+    r.N = c.L1;
+    r.n = c.n;
+    r.ncs = c.ncs;
+    r.xs = c.ncs | 1;   // odd stride: a column's elements fall in different banks
+    r.first = first;
+    r.colslot = c.d_colslot;
+    r.scol = c.d_scol;
+    r.sup_ptr = c.d_sup_ptr;
+    r.sup = c.d_sup;
+    r.sup_rhs = c.d_sup_rhs;
+    r.coef = c.d_coef;
+    r.kscale = c.d_kscale;
+    r.tw = c.tw1;
+    r.desc = c.d_desc;
+    for (int i = 0; i < 3; ++i) r.buf[i] = class_buf(c, i);
+    table.push_back(r);
+    first += c.n;
+  }
+  if (table.empty()) return BCCB_OK;
+  int best_waves = 0;
+  for (int nt : {256, 512, 1024}) {
+    long lds = 0;
+    for (const ResidentClass& r : table) lds = std::max(lds, resident_lds_bytes(r.N, r.ncs, nt));
+    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds));
+    if (nb * (nt / 64) > best_waves) {
+      best_waves = nb * (nt / 64);
+      b->res_threads = nt;
+      b->res_lds = static_cast<size_t>(lds);
+      b->res_blocks = nb;
+    }
+  }
+  if (best_waves == 0) return BCCB_OK;
+  int dev = 0, cus = 0;
+  BCCB_HIP(hipGetDevice(&dev));
+  BCCB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  b->res_blocks = std::max(1, std::min(first, b->res_blocks * std::max(cus, 1)));
+  b->res_ncls = static_cast<int>(table.size());
+  BCCB_TRY(dalloc(&b->d_rcls, table.size()));
+  BCCB_TRY(dalloc(&b->d_queue, 1));
+  BCCB_HIP(hipMemcpy(b->d_rcls, table.data(), table.size() * sizeof(ResidentClass), hipMemcpyHostToDevice));
+  b->res_ok = b->res_on = true;
+  return BCCB_OK;
+}
+
+// beta_t = (alpha_t - 1) / alpha_{t+1} for t = 1..iters (beta_0 = 0), as the graph loop forms them
+int resident_betas(bccb_batch_s* b, int iters, hipStream_t s) {
+  if (iters + 1 > b->beta_cap) {
+    if (b->d_beta) (void)hipFree(b->d_beta);
+    if (b->h_beta) (void)hipHostFree(b->h_beta);
+    b->d_beta = nullptr;
+    b->h_beta = nullptr;
+    b->beta_cap = 0;
+    BCCB_TRY(dalloc(&b->d_beta, iters + 1));
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_beta), (iters + 1) * sizeof(float)) != hipSuccess) {
+      b->h_beta = nullptr;
+      return BCCB_E_NOMEM;
+    }
+    b->beta_cap = iters + 1;
+  }
+  double alpha = 1.0;
+  b->h_beta[0] = 0.f;
+  for (int t = 1; t <= iters; ++t) {
+    const double alpha_next = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    b->h_beta[t] = static_cast<float>((alpha - 1.0) / alpha_next);
+    alpha = alpha_next;
+  }
+  BCCB_HIP(hipMemcpyAsync(b->d_beta, b->h_beta, (iters + 1) * sizeof(float), hipMemcpyHostToDevice, s));
+  return BCCB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -397,6 +497,7 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
       rc = BCCB_E_DEVICE;
     if (rc != BCCB_OK) break;
   }
+  if (rc == BCCB_OK) rc = resident_setup(b);
   if (rc == BCCB_OK) rc = dalloc(&b->d_flag, 1);
   if (rc == BCCB_OK && (hipHostMalloc(reinterpret_cast<void**>(&b->h_flag), sizeof(int)) != hipSuccess ||
                         hipHostMalloc(reinterpret_cast<void**>(&b->h_desc), nscenes * sizeof(SceneDesc)) != hipSuccess ||
@@ -455,8 +556,10 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
     BCCB_HIP(hipMemcpyAsync(c.d_kscale, b->h_kscale + off, c.n * sizeof(float), hipMemcpyHostToDevice, s));
     off += c.n;
   }
+  bool resident = b->res_on && iters > 0;
+  for (const BatchClass& c : b->cls) resident = resident && c.prune;   // the support-column form is on
   // mu_s * b_s = mu_s * D_s^H y_s for every scene (spectral support bins, or a grid);
-  // c^(0) = 0, DFT_rows(z^(1)) = 0
+  // c^(0) = 0, DFT_rows(z^(1)) = 0 (the persistent launch starts every scene from these itself)
   off = 0;
   for (BatchClass& c : b->cls) {
     if (c.sparse) {
@@ -480,6 +583,7 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
       BCCB_TRY(class_row(c, c.cfg_row, ROW_INV, a, s));
     }
     off += c.n;
+    if (resident) continue;
     BCCB_TRY(kern(launch_fill(c.d_c, static_cast<long>(c.n) * c.L, s)));
     BCCB_TRY(kern(launch_fill(c.d_xy, static_cast<long>(c.n) * c.L, s)));
     if (c.sp_iter) BCCB_TRY(kern(launch_fill_int(c.d_cnt, static_cast<long>(c.n) * c.L2, c.L1 + 1, s)));
@@ -490,7 +594,12 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
       BCCB_TRY(kern(launch_fill(c.d_xyc, static_cast<long>(c.n) * c.L2 * c.ncs, s)));
     }
   }
-  if (iters > 0) {
+  if (resident) {
+    BCCB_TRY(resident_betas(b, iters, s));
+    BCCB_TRY(kern(launch_fill_int(b->d_queue, 1, 0, s)));
+    BCCB_TRY(kern(launch_scene_fista(b->d_rcls, b->res_ncls, b->n, b->d_beta, iters, b->d_queue, b->res_threads,
+                                     b->res_blocks, b->res_lds, s)));
+  } else if (iters > 0) {
     if (!b->exec || b->graph_iters != iters) {
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
       b->exec = nullptr;
@@ -516,7 +625,8 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
     }
     BCCB_HIP(hipGraphLaunch(b->exec, s));
   }
-  for (BatchClass& c : b->cls) BCCB_TRY(kern(launch_gather_batch(c.d_desc, c.n, c.L, c.d_c, s)));
+  if (!resident)
+    for (BatchClass& c : b->cls) BCCB_TRY(kern(launch_gather_batch(c.d_desc, c.n, c.L, c.d_c, s)));
   BCCB_HIP(hipMemcpyAsync(b->h_flag, b->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   BCCB_HIP(hipStreamSynchronize(s));
   return *b->h_flag ? BCCB_E_NONFINITE : BCCB_OK;
@@ -608,6 +718,37 @@ int bccb_batch_set_support_columns(bccb_batch_t b, int on) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
   b->graph_iters = -1;
+  return BCCB_OK;
+}
+
+int bccb_batch_set_resident(bccb_batch_t b, int on) {
+  if (!b || (on != 0 && on != 1 && on != 256 && on != 512 && on != 1024)) return BCCB_E_INVALID;
+  if (on != 0 && !b->res_ok) return BCCB_E_UNSUPPORTED;
+  if (on > 1) {
+    // a given workgroup size: its LDS and the grid it keeps resident
+    long lds = 0;
+    std::vector<ResidentClass> table(b->res_ncls);
+    BCCB_HIP(hipMemcpy(table.data(), b->d_rcls, table.size() * sizeof(ResidentClass), hipMemcpyDeviceToHost));
+    for (const ResidentClass& r : table) lds = std::max(lds, resident_lds_bytes(r.N, r.ncs, on));
+    const int nb = scene_fista_occupancy(on, static_cast<size_t>(lds));
+    if (nb < 1) return BCCB_E_UNSUPPORTED;
+    int dev = 0, cus = 0;
+    BCCB_HIP(hipGetDevice(&dev));
+    BCCB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->res_threads = on;
+    b->res_lds = static_cast<size_t>(lds);
+    b->res_blocks = std::max(1, std::min(b->n, nb * std::max(cus, 1)));
+  }
+  b->res_on = on != 0;
+  return BCCB_OK;
+}
+
+int bccb_batch_resident_info(bccb_batch_t b, int* on, int* threads, int* blocks, int* lds_bytes) {
+  if (!b) return BCCB_E_INVALID;
+  if (on) *on = b->res_on ? 1 : (b->res_ok ? 0 : -1);
+  if (threads) *threads = b->res_ok ? b->res_threads : 0;
+  if (blocks) *blocks = b->res_ok ? b->res_blocks : 0;
+  if (lds_bytes) *lds_bytes = b->res_ok ? static_cast<int>(b->res_lds) : 0;
   return BCCB_OK;
 }
 

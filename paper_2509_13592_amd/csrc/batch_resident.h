@@ -1,0 +1,60 @@
+// Whole batched FISTA solves in one persistent launch (internal to libbccb).
+//
+// A workgroup takes a scene from a queue and runs every iteration of its solve
+// (eqs. (10)-(12), the product of eq. (23) in the pruned form of the batch's
+// support-column classes) before it takes the next one.  The scene's kept row
+// spectra [L2][ncs] stay in LDS for the whole solve; the column pass over the
+// kept columns and the row pass run in the same workgroup, separated by
+// workgroup barriers; the iterate's rows go to the class's slot buffers, which
+// only the workgroup holding the scene touches (its die's L2 keeps them), and
+// the rows' nonzero counts stay in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace bccb {
+
+// One size class of the batch (square grids L1 = L2 = N), every array in class-arena order.
+struct ResidentClass {
+  int N = 0;                     // grid length, one of 32, 64, 128, 256
+  int n = 0;                     // scenes
+  int ncs = 0;                   // kept-column slots per scene
+  int xs = 0;                    // LDS row stride of the kept spectra (ncs rounded up to odd)
+  int first = 0;                 // queue index of the class's first scene
+  const int* colslot = nullptr;  // [n][N] spectral column -> slot (-1 = not kept)
+  const int* scol = nullptr;     // [n][ncs] slot -> spectral column (-1 = padding)
+  const int* sup_ptr = nullptr;  // [n][N + 1] entry offsets of each spectral column
+  const SupEntry* sup = nullptr; // support bins (k2, Omega)
+  const float2* sup_rhs = nullptr;  // mu * spectral right-hand side per entry
+  const float2* coef = nullptr;  // [n] (1/L, -mu/L)
+  const float* kscale = nullptr; // [n] mu * tau
+  const float2* tw = nullptr;    // [N] e^{-j 2 pi j / N}
+  const SceneDesc* desc = nullptr;  // [n] output grids
+  SlotBuf buf[3];                // iterate rows [n][N], rotating c_t, c_{t-1}, c_{t-2}
+};
+
+// Elements per thread of the transforms (N / 4 threads per row or column).
+constexpr int kResidentE = 4;
+
+// Workgroup LDS of a class at `nthreads` threads, in bytes: kept spectra N x xs,
+// N twiddles, two exchange areas per transform group, the row inverse's twiddles
+// (ncs x N/E), three [N] count arrays and the kept-column tables (2 ncs + 8 ints).
+constexpr long resident_lds_bytes(int N, int ncs, int nthreads) {
+  const int T = N / kResidentE;
+  const long G = nthreads / T;
+  const long xs = ncs | 1;
+  return 8L * (N * xs + N + 2L * G * fft_area(N) + static_cast<long>(ncs) * T) + 12L * N + 4L * (2L * ncs + 8);
+}
+
+// Persistent launch over `total` scenes of `ncls` classes (device table `cls`, classes in
+// queue order); beta[t] (t = 1..iters, beta[0] = 0) are the momentum weights; *queue = 0
+// on entry.  Returns -1 for a shape the kernel does not take.
+int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int iters, int* queue,
+                       int nthreads, int blocks, size_t lds, hipStream_t s);
+
+// Workgroups of the kernel one compute unit holds at this shape (0: does not fit).
+int scene_fista_occupancy(int nthreads, size_t lds);
+
+}  // namespace bccb

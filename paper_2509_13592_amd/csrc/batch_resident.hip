@@ -1,0 +1,383 @@
+// Persistent whole-solve FISTA over the batch's support-column classes: one scene
+// per workgroup at a time, taken from a queue (see batch_resident.h).
+#include "batch_resident.h"
+#include "passes.h"
+
+namespace bccb {
+
+namespace {
+
+constexpr int kMaxThreads = 1024;
+
+// The thread's index within its group, as a value the compiler cannot prove loop
+// invariant: the transforms' LDS and twiddle addresses are then formed inside each
+// row's work instead of all being hoisted out of the row loop into registers.
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Accesses through the global address space: the class table hands out plain
+// pointers, and accesses through them would otherwise be flat ones (which also
+// count against the LDS wait counter and hold up the row's exchanges).
+struct alignas(8) P2 {
+  float x, y;
+};
+template <class T>
+__device__ __forceinline__ T ldg(const T* p, size_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+#else
+  return p[i];   // the host pass only parses device code
+#endif
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, size_t i, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+#else
+  p[i] = v;
+#endif
+}
+__device__ __forceinline__ float2 ldg2(const float2* p, size_t i) {
+  const P2 v = ldg(reinterpret_cast<const P2*>(p), i);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stg2(float2* p, size_t i, float2 v) {
+  stg(reinterpret_cast<P2*>(p), i, P2{v.x, v.y});
+}
+
+// Every iteration of one scene's FISTA solve (eqs. (10)-(12)).  The workgroup is cut
+// into groups of T = N / E threads (inside one wavefront), each owning the kept
+// columns q = g, g + G, ... in the column pass and the rows r = g, g + G, ... in the
+// row pass; a group's exchanges order only its wavefront.
+//
+// The kept columns are held in the order of their spectral column k1 modulo E = 4
+// (qoff[j] .. qoff[j + 1] - 1 hold k1 = j mod 4): thread t of a row owns the elements
+// l = t + T e, and the inverse row transform of a row with only the kept bins,
+//   u(t + T e) = sum_q X_q w^{k1_q t} i^{k1_q e}      (w = e^{j 2 pi / N}),
+// is then four sums S_j = sum over the q of class j of X_q w^{k1_q t} followed by one
+// 4-point transform, with the per-thread twiddles w^{k1_q t} read from LDS.
+template <int N, int E>
+__device__ void solve_scene(const ResidentClass& c, int k, const float* beta, int iters, float2* lds) {
+  static_assert(E == 4, "the row inverse is a 4-point transform of four class sums");
+  using F = Stockham<N, E, true>;
+  constexpr int T = F::T;
+  static_assert(T <= 64 && 64 % T == 0, "a transform inside one wavefront");
+  constexpr int FA = fft_area(N);
+  constexpr int CAP = SparseRow<N>::CAP;
+  constexpr int SPT = (CAP + T - 1) / T;
+  const int G = static_cast<int>(blockDim.x) / T;
+  const int g = static_cast<int>(threadIdx.x) / T;
+  const int t0 = static_cast<int>(threadIdx.x) - g * T;
+  const int ncs = c.ncs, xs = c.xs;
+  float2* X = lds;                       // kept row spectra [N][xs], kept column q at q
+  float2* stw = X + N * xs;              // twiddles [N]
+  float2* sa = stw + N + 2 * g * FA;     // the group's exchange areas A, B
+  float2* sb = sa + FA;
+  float2* tw2 = stw + N + 2 * G * FA;    // [ncs][T]: w^{k1_q t}, conjugated table entries
+  int* cntl = reinterpret_cast<int*>(tw2 + ncs * T);   // [3][N] nonzeros of the row of c_t (> CAP: dense)
+  int* qpos = cntl + 3 * N;              // [ncs] slot -> kept-column position q (-1: padding)
+  int* qk1 = qpos + ncs;                 // [ncs] q -> spectral column k1
+  int* qoff = qk1 + ncs;                 // [5] class bounds of q
+  const float2 zero = make_float2(0.f, 0.f);
+
+  const float kappa = c.kscale[k];
+  const float cb = c.coef[k].y;
+  const int* scol = c.scol + static_cast<size_t>(k) * ncs;
+  const int* sptr = c.sup_ptr + static_cast<size_t>(k) * (N + 1);
+  float2* out = c.desc[k].out;
+
+  // z_1 = 0: zero kept spectra; c_0 = c_{-1} = 0: empty rows; the kept columns by class
+  for (int j = threadIdx.x; j < N * xs; j += blockDim.x) X[j] = zero;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    stw[j] = c.tw[j];
+    cntl[j] = 0;
+    cntl[2 * N + j] = 0;
+  }
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int j = 0; j < 4; ++j) {
+      qoff[j] = q;
+      for (int s = 0; s < ncs; ++s) {
+        const int k1 = ldg(scol, s);
+        if (j == 0) qpos[s] = -1;
+        if (k1 >= 0 && (k1 & 3) == j) {
+          qpos[s] = q;
+          qk1[q] = k1;
+          ++q;
+        }
+      }
+    }
+    qoff[4] = q;
+  }
+  __syncthreads();
+  const int nq = qoff[4];
+  for (int j = threadIdx.x; j < nq * T; j += blockDim.x) {
+    const float2 w = stw[(qk1[j / T] * (j % T)) & (N - 1)];
+    tw2[j] = make_float2(w.x, -w.y);   // e^{+j 2 pi k1 t / N}
+  }
+  int kq[E];   // kept-column position of each spectral bin this thread holds after a forward row transform
+  {
+    const int* cs = c.colslot + static_cast<size_t>(k) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int sl = ldg(cs, F::out_index(t0, e));
+      kq[e] = sl >= 0 ? qpos[sl] : -1;
+    }
+  }
+  const int o0 = qoff[0], o1 = qoff[1], o2 = qoff[2], o3 = qoff[3];
+  __syncthreads();
+
+  for (int it = 1; it <= iters; ++it) {
+    // column pass over the kept columns: X[:, q] = IDFT_cols(m . DFT_cols(X[:, q]) + r),
+    // m = b Omega_j and r = rhs_j on the column's support bins, m = r = 0 elsewhere
+    for (int q = g; q < nq; q += G) {
+      const int k1 = qk1[q];
+      const int t = opaque(t0);
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = X[F::in_index(t, e) * xs + q];
+      fft_fwd<F>(v, t, stw, sa, sb, true);
+      float2 src[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        src[e] = v[e];
+        v[e] = zero;
+      }
+      const int j0 = ldg(sptr, k1), j1 = ldg(sptr, k1 + 1);
+      for (int j = j0; j < j1; ++j) {
+        const SupEntry en = ldg(c.sup, j);
+        const float2 r = ldg2(c.sup_rhs, j);
+        const float m = cb * en.omega;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (F::out_index(t, e) == en.k2) v[e] = make_float2(src[e].x * m + r.x, src[e].y * m + r.y);
+      }
+      fft_inv_after_fwd<F>(v, t, stw, sa, sb);
+#pragma unroll
+      for (int e = 0; e < E; ++e) X[F::in_index(t, e) * xs + q] = v[e];
+    }
+    __syncthreads();
+
+    // row pass: z_t = c_{t-1} + beta_{t-1} (c_{t-1} - c_{t-2}); c_t = S_kappa(z_t + IDFT_rows(X));
+    // X = DFT_rows(c_t + beta_t (c_t - c_{t-1})) on the kept columns
+    const int i0 = it % 3, i1 = (it - 1) % 3, i2 = (it + 1) % 3;
+    const float bt = beta[it], bp = beta[it - 1];
+    const bool last = it == iters;
+    const SlotBuf b0 = c.buf[i0], b1 = c.buf[i1], b2 = c.buf[i2];
+    for (int r = g; r < N; r += G) {
+      const int t = opaque(t0);
+      const size_t prow = static_cast<size_t>(k) * N + r;
+      const size_t base = prow * N;
+      float2* xr = X + r * xs;
+      const int n1 = cntl[i1 * N + r], n2 = cntl[i2 * N + r];
+      // u = IDFT_rows(X) at this thread's elements t + T e
+      float2 v[E];
+      {
+        const float2* wt = tw2 + t;
+        float2 S[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) S[j] = zero;
+        for (int q = 0; q < o1; ++q) S[0] = cadd(S[0], cmul(xr[q], wt[q * T]));
+        for (int q = o1; q < o2; ++q) S[1] = cadd(S[1], cmul(xr[q], wt[q * T]));
+        for (int q = o2; q < o3; ++q) S[2] = cadd(S[2], cmul(xr[q], wt[q * T]));
+        for (int q = o3; q < nq; ++q) S[3] = cadd(S[3], cmul(xr[q], wt[q * T]));
+        const float2 a = cadd(S[0], S[2]), b = make_float2(S[0].x - S[2].x, S[0].y - S[2].y);
+        const float2 cc = cadd(S[1], S[3]), d = make_float2(S[1].x - S[3].x, S[1].y - S[3].y);
+        v[0] = cadd(a, cc);                              // i^0
+        v[1] = make_float2(b.x - d.y, b.y + d.x);        // S0 + i S1 - S2 - i S3
+        v[2] = make_float2(a.x - cc.x, a.y - cc.y);      // S0 - S1 + S2 - S3
+        v[3] = make_float2(b.x + d.y, b.y - d.x);        // S0 - i S1 - S2 + i S3
+      }
+      (void)o0;
+      float2 p1[E];
+      if (n1 == 0 && n2 == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          p1[e] = zero;
+          v[e] = shrink(v[e], kappa);
+        }
+      } else {
+        // dense rows straight into registers; slot rows scattered into zeroed areas
+        const bool full1 = n1 > CAP, full2 = n2 > CAP;
+        float2 p2[E];
+        unsigned short q1[SPT], q2[SPT];
+        float2 w1[SPT], w2[SPT];
+        if (full1) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) p1[e] = ldg2(b1.dense, base + F::in_index(t, e));
+        }
+        if (full2) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) p2[e] = ldg2(b2.dense, base + F::in_index(t, e));
+        }
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+          const int j = t + T * q;
+          q1[q] = q2[q] = 0;
+          w1[q] = w2[q] = zero;
+          if (!full1 && j < n1) {
+            q1[q] = ldg(b1.sidx, prow * CAP + j);
+            w1[q] = ldg2(b1.sval, prow * CAP + j);
+          }
+          if (!full2 && j < n2) {
+            q2[q] = ldg(b2.sidx, prow * CAP + j);
+            w2[q] = ldg2(b2.sval, prow * CAP + j);
+          }
+        }
+        lds_sync<true>();   // the group's last use of its areas is done
+        if (!full1) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) sb[F::in_index(t, e)] = zero;
+        }
+        if (!full2) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) sa[F::in_index(t, e)] = zero;
+        }
+        lds_sync<true>();
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+          const int j = t + T * q;
+          if (!full1 && j < n1) sb[q1[q] < N ? q1[q] : N - 1] = w1[q];
+          if (!full2 && j < n2) sa[q2[q] < N ? q2[q] : N - 1] = w2[q];
+        }
+        lds_sync<true>();
+        if (!full1) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) p1[e] = sb[F::in_index(t, e)];
+        }
+        if (!full2) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) p2[e] = sa[F::in_index(t, e)];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const float2 z = make_float2(p1[e].x + bp * (p1[e].x - p2[e].x), p1[e].y + bp * (p1[e].y - p2[e].y));
+          v[e] = shrink(cadd(z, v[e]), kappa);
+        }
+      }
+
+      if (last) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) stg2(out, static_cast<size_t>(r) * N + F::in_index(t, e), v[e]);
+        continue;   // uniform over the workgroup
+      }
+      // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); one scan counts the nonzeros of both rows
+      float2 zn[E];
+      int mine = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        zn[e] = make_float2(v[e].x + bt * (v[e].x - p1[e].x), v[e].y + bt * (v[e].y - p1[e].y));
+        mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
+        mine += (zn[e].x != 0.f || zn[e].y != 0.f) ? (1 << 16) : 0;
+      }
+      int tot2, before2;
+      row_prefix<T>(mine, t, nullptr, tot2, before2);
+      const int total = tot2 & 0xffff, before = before2 & 0xffff;
+      const int ztot = tot2 >> 16, zbefore = before2 >> 16;
+      if (t == 0) cntl[i0 * N + r] = total;
+      // c_t: slots while the row has at most CAP nonzeros, the dense row otherwise
+      if (total > CAP) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) stg2(b0.dense, base + F::in_index(t, e), v[e]);
+      } else if (total > 0) {
+        int o = before;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (v[e].x != 0.f || v[e].y != 0.f) {
+            stg(b0.sidx, prow * CAP + o, static_cast<unsigned short>(F::in_index(t, e)));
+            stg2(b0.sval, prow * CAP + o, v[e]);
+            ++o;
+          }
+        }
+      }
+      // X = DFT_rows(z_{t+1}) on the kept columns: direct sums over its nonzeros when it has
+      // at most CAP of them (none for most rows once the iterate is sparse), else the row FFT
+      if (ztot > CAP) {
+        fft_fwd<F>(zn, t, stw, sa, sb, true);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (kq[e] >= 0) xr[kq[e]] = zn[e];
+      } else if (ztot == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (kq[e] >= 0) xr[kq[e]] = zero;
+      } else {
+        lds_sync<true>();   // the group's last use of its areas is done
+        int* zpos = reinterpret_cast<int*>(sb);
+        int o = zbefore;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (zn[e].x != 0.f || zn[e].y != 0.f) {
+            sa[o] = zn[e];
+            zpos[o] = F::in_index(t, e);
+            ++o;
+          }
+        }
+        lds_sync<true>();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (kq[e] >= 0) {
+            const int kk = F::out_index(t, e);
+            float2 acc = zero;
+            for (int q = 0; q < ztot; ++q) {
+              const float2 w = stw[(kk * zpos[q]) & (N - 1)];   // e^{-j 2 pi k l / N}
+              acc = cadd(acc, cmul(sa[q], w));
+            }
+            xr[kq[e]] = acc;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass* cls, int ncls, int total,
+                                                             const float* beta, int iters, int* queue) {
+  extern __shared__ float2 lds[];
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(item);   // uniform: the class table is read with scalar loads
+    __syncthreads();   // every thread has read the item before thread 0 takes the next
+    if (q >= total) return;   // uniform: every wave leaves together, the queue only grows
+    int ci = 0;
+    while (ci + 1 < ncls && q >= cls[ci + 1].first) ++ci;
+    const ResidentClass& c = cls[ci];
+    const int k = q - c.first;
+    switch (c.N) {
+      case 32: solve_scene<32, kResidentE>(c, k, beta, iters, lds); break;
+      case 64: solve_scene<64, kResidentE>(c, k, beta, iters, lds); break;
+      case 128: solve_scene<128, kResidentE>(c, k, beta, iters, lds); break;
+      case 256: solve_scene<256, kResidentE>(c, k, beta, iters, lds); break;
+      default: break;
+    }
+  }
+}
+
+}  // namespace
+
+int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int iters, int* queue,
+                       int nthreads, int blocks, size_t lds, hipStream_t s) {
+  if (!cls || ncls < 1 || total < 1 || !beta || iters < 1 || !queue) return -1;
+  if (nthreads < 64 || nthreads > kMaxThreads || nthreads % 64 != 0 || blocks < 1) return -1;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scene_fista), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds)) != hipSuccess)
+    return -2;
+  hipLaunchKernelGGL(k_scene_fista, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, iters, queue);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int scene_fista_occupancy(int nthreads, size_t lds) {
+  int nb = 0;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scene_fista), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(lds)) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scene_fista, nthreads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+}  // namespace bccb

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libbccb.so")
 
-SOURCES = ["kernels.hip", "resident.hip", "batch_kernels.hip", "learned_kernels.hip", "dense_kernels.hip", "noalloc.hip", "spaced_kernels.hip", "extract.hip", "passes_f64.hip",
+SOURCES = ["kernels.hip", "resident.hip", "batch_kernels.hip", "batch_resident.hip", "learned_kernels.hip", "dense_kernels.hip", "noalloc.hip", "spaced_kernels.hip", "extract.hip", "passes_f64.hip",
            "plan_math.cpp", "embed_math.cpp", "spaced.cpp", "solve_f64.cpp", "api.cpp", "batch.cpp", "learned.cpp", "dense.cpp"]
 # the pass kernels are compiled once per transform length (parallel build)
 PASS_LENGTHS = [8, 16, 32, 64, 128, 256, 512, 1024]

@@ -203,3 +203,76 @@ def test_batch_dense_grid_path():
         print(f"case dense-grid batch scene {i}: rel F={rel:.2e}", flush=True)
         assert rel <= OBJ_TOL
     batch.close()
+
+
+U32 = 2.0 ** -24
+
+
+def _iter_tol(T, L):
+    # FP32 transforms of log2 L stages per iteration, errors adding at most linearly along T,
+    # a factor 4 for the momentum re-applying the last two (as the full-size tests state)
+    return 4.0 * max(T, 1) * U32 * np.log2(L)
+
+
+def test_resident_launch_matches_pass_graph_and_oracle():
+    """The persistent whole-solve launch (the default where every class supports it) against
+    the captured pass graph and the oracle: 32^2 .. 256^2 grids, 8x8, 16x16 and 32x32 arrays,
+    iteration counts on both sides of the rows turning sparse; same bits on a repeat call."""
+    scenes = [S.batched_scene(500 + i) for i in range(15)]
+    scenes += [S.tiny_scene(i) for i in range(3)]
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    info = batch.resident_info()
+    print("classes", batch.classes(), "resident", info, flush=True)
+    assert info["on"] == 1 and info["threads"] >= 256 and info["blocks"] >= 1
+    for T in (1, 2, 3, 9, 60, 300):
+        batch.set_resident(True)
+        a = [o.clone() for o in batch.fista(ys, taus, T)]
+        again = batch.fista(ys, taus, T)
+        assert all(torch.equal(x, y) for x, y in zip(a, again))
+        batch.set_resident(False)
+        g = batch.fista(ys, taus, T)
+        worst = 0.0
+        for i, sc in enumerate(scenes):
+            x, r = _np(a[i]), _np(g[i])
+            d = np.linalg.norm(x - r) / max(np.linalg.norm(r), 1e-30)
+            worst = max(worst, d / _iter_tol(T, sc.L1 * sc.L2))
+            assert d <= 2 * _iter_tol(T, sc.L1 * sc.L2), (i, T, d)
+        print(f"case resident vs graph T={T}: worst |diff| / bound {worst:.3f}", flush=True)
+    for i, sc in enumerate(scenes):
+        if i % 3:
+            continue
+        P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(300)
+        x = _np(a[i])
+        Fr = P.objective(ref)
+        rel = abs(P.objective(x) - Fr) / Fr
+        eps = np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(f"case resident scene {i} L={sc.L1}: rel F {rel:.2e} eps_r {eps:.2e}", flush=True)
+        assert rel <= OBJ_TOL and eps <= _iter_tol(300, sc.L1 * sc.L2)
+    # zero iterations, and a threshold above max |D^H y|: zero grids
+    batch.set_resident(True)
+    assert all(torch.count_nonzero(o) == 0 for o in batch.fista(ys, taus, 0))
+    big = [1.01 * p.adjoint_maxabs(y) for p, y in zip(plans, ys)]
+    assert all(torch.count_nonzero(o) == 0 for o in batch.fista(ys, big, 7))
+    assert B.lib.bccb_batch_set_resident(batch._h, 3) == B.BCCB_E_INVALID
+    assert B.lib.bccb_batch_set_resident(batch._h, 128) == B.BCCB_E_INVALID
+    batch.close()
+
+
+def test_resident_launch_refusals():
+    """A rectangular class keeps the whole batch on the pass graph."""
+    scenes = [S.batched_scene(600), S.custom_scene(5, 7, 20, 64, 16, K=3, snr_db=15, seed=(21, 0, 0))]
+    plans, ys, taus = _setup(scenes)
+    batch = B.Batch(plans)
+    assert batch.resident_info() == {"on": -1, "threads": 0, "blocks": 0, "lds_bytes": 0}
+    with pytest.raises(B.BCCBError) as e:
+        batch.set_resident(True)
+    assert e.value.code == B.BCCB_E_UNSUPPORTED
+    batch.set_resident(False)
+    outs = batch.fista(ys, taus, 20)
+    for i, sc in enumerate(scenes):
+        P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(20)
+        assert abs(P.objective(_np(outs[i])) - P.objective(ref)) <= OBJ_TOL * P.objective(ref)
+    batch.close()
