@@ -606,6 +606,7 @@ def main():
                          "(profiling runs pin the shape the autotuner chose)")
     ap.add_argument("--no-tune", action="store_true", help="batch256: default launch shapes, no autotuning")
     ap.add_argument("--batch-iters", type=int, default=20, help="batch256: FISTA iterations per solve")
+    ap.add_argument("--uniform-scenes", type=int, default=256, help="batch256: paper-scale scenes in the batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the workloads are single-GPU by design; "
@@ -644,9 +645,10 @@ def main():
         print(json.dumps({"large_admm": large_admm_run(B, S, launch=json.loads(args.launch) if args.launch else None)}))
         return
     if args.only == "batch256":
-        dt, classes, _ = _batch_rate(B, [S.paper_scale_scene(i) for i in range(256)], args.batch_iters, reps=2,
+        n = args.uniform_scenes
+        dt, classes, _ = _batch_rate(B, [S.paper_scale_scene(i) for i in range(n)], args.batch_iters, reps=2,
                                      tune=not args.no_tune)
-        print(json.dumps({"batch256_s_per_solve": dt, "scenes": 256, "iters": args.batch_iters, "classes": classes}))
+        print(json.dumps({"batch256_s_per_solve": dt, "scenes": n, "iters": args.batch_iters, "classes": classes}))
         return
     sc = S.paper_scale_scene(0)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)

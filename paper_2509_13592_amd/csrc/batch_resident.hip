@@ -47,6 +47,16 @@ __device__ __forceinline__ void stg2(float2* p, size_t i, float2 v) {
   stg(reinterpret_cast<P2*>(p), i, P2{v.x, v.y});
 }
 
+// The complex soft threshold of passes.h (zero for |z| <= k, z (1 - k/|z|) above),
+// formed without a branch: the reciprocal square root is taken for every element
+// and the factor selected, so a row's lanes never split over the two cases.
+__device__ __forceinline__ float2 shrink_sel(float2 z, float k) {
+  const float a2 = z.x * z.x + z.y * z.y;
+  const float f = 1.f - k * __builtin_amdgcn_rsqf(a2);
+  const float m = a2 > k * k ? f : 0.f;
+  return make_float2(z.x * m, z.y * m);
+}
+
 // Every iteration of one scene's FISTA solve (eqs. (10)-(12)).  The workgroup is cut
 // into groups of T = N / E threads (inside one wavefront), each owning the kept
 // columns q = g, g + G, ... in the column pass and the rows r = g, g + G, ... in the
@@ -126,7 +136,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       kq[e] = sl >= 0 ? qpos[sl] : -1;
     }
   }
-  const int o0 = qoff[0], o1 = qoff[1], o2 = qoff[2], o3 = qoff[3];
+  const int o1 = qoff[1], o2 = qoff[2], o3 = qoff[3];
   __syncthreads();
 
   for (int it = 1; it <= iters; ++it) {
@@ -179,9 +189,13 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         float2 S[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) S[j] = zero;
+#pragma unroll 4
         for (int q = 0; q < o1; ++q) S[0] = cadd(S[0], cmul(xr[q], wt[q * T]));
+#pragma unroll 4
         for (int q = o1; q < o2; ++q) S[1] = cadd(S[1], cmul(xr[q], wt[q * T]));
+#pragma unroll 4
         for (int q = o2; q < o3; ++q) S[2] = cadd(S[2], cmul(xr[q], wt[q * T]));
+#pragma unroll 4
         for (int q = o3; q < nq; ++q) S[3] = cadd(S[3], cmul(xr[q], wt[q * T]));
         const float2 a = cadd(S[0], S[2]), b = make_float2(S[0].x - S[2].x, S[0].y - S[2].y);
         const float2 cc = cadd(S[1], S[3]), d = make_float2(S[1].x - S[3].x, S[1].y - S[3].y);
@@ -190,13 +204,12 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         v[2] = make_float2(a.x - cc.x, a.y - cc.y);      // S0 - S1 + S2 - S3
         v[3] = make_float2(b.x + d.y, b.y - d.x);        // S0 - i S1 - S2 + i S3
       }
-      (void)o0;
       float2 p1[E];
       if (n1 == 0 && n2 == 0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           p1[e] = zero;
-          v[e] = shrink(v[e], kappa);
+          v[e] = shrink_sel(v[e], kappa);
         }
       } else {
         // dense rows straight into registers; slot rows scattered into zeroed areas
@@ -254,7 +267,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const float2 z = make_float2(p1[e].x + bp * (p1[e].x - p2[e].x), p1[e].y + bp * (p1[e].y - p2[e].y));
-          v[e] = shrink(cadd(z, v[e]), kappa);
+          v[e] = shrink_sel(cadd(z, v[e]), kappa);
         }
       }
 
