@@ -60,6 +60,24 @@ BATCH_TRAFFIC = {
 }
 
 
+# VALU instructions per scene-iteration of the persistent batch solve (SQ_INSTS_VALU of one
+# dispatch / scene-iterations), keyed by the code of its sources and the workload they were
+# counted on: profiles/fista_persistent_batch_256_rocprofv3.md
+PERSISTENT_VALU = {
+    "ca9a33b52babc88e": {"workload": (1024, 256, 100), "valu_per_scene_iteration": 104100},
+}
+VALU_ISSUE_PEAK = 256 * 2.4e9   # wave64 VALU instructions/s: one per compute unit per cycle
+
+
+def _persistent_hash() -> str:
+    """Hash of the code (comments aside) of the persistent batch solve's device sources."""
+    h = hashlib.sha256()
+    for f in ("batch_resident.h", "batch_resident.hip", "fft_device.h", "passes.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2509_13592_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
+    return h.hexdigest()[:16]
+
+
 def pruned_bytes_per_iteration(L1, L2, ncs, row_nnz):
     """Algorithmic bytes of one pruned FISTA iteration of one scene (the form the batches run).
 
@@ -477,6 +495,15 @@ def batched_runs(args):
     launch = cls2[0]["launch"]
     if any("persistent_launch" in c for c in cls2):
         launch = dict(launch, pruned=0)   # the counted pass traffic does not describe the persistent launch
+        pv = PERSISTENT_VALU.get(_persistent_hash())
+        rate = n2 * it2 / dt2
+        if pv and pv["workload"] == (n2, 256, it2):
+            out["uniform_256"]["roofline"] = {
+                "bound": "valu", "unit": "VALU instructions/s",
+                "achieved": round(pv["valu_per_scene_iteration"] * rate, -6), "peak": VALU_ISSUE_PEAK,
+                "frac": round(pv["valu_per_scene_iteration"] * rate / VALU_ISSUE_PEAK, 4),
+                "source": "SQ_INSTS_VALU per scene-iteration from profiles/fista_persistent_batch_256_rocprofv3.md "
+                          "x the scene-iterations/s measured here (wall time of the solve)"}
     key = (launch["row_E"], launch["rows_per_block"], launch["col_E"], launch["cols_per_block"])
     counted = BATCH_TRAFFIC.get(_kernel_hash(), {}).get(key) if launch["pruned"] else None
     out["uniform_256"]["counted_bytes_per_point"] = counted
