@@ -57,6 +57,14 @@ __device__ __forceinline__ float2 shrink_sel(float2 z, float k) {
   return make_float2(z.x * m, z.y * m);
 }
 
+// acc += a b as four fused multiply-adds (one rounding per product term)
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
+  acc.x = __builtin_fmaf(a.x, b.x, acc.x);
+  acc.x = __builtin_fmaf(-a.y, b.y, acc.x);
+  acc.y = __builtin_fmaf(a.x, b.y, acc.y);
+  acc.y = __builtin_fmaf(a.y, b.x, acc.y);
+}
+
 // Every iteration of one scene's FISTA solve (eqs. (10)-(12)).  The workgroup is cut
 // into groups of T = N / E threads (inside one wavefront), each owning the kept
 // columns q = g, g + G, ... in the column pass and the rows r = g, g + G, ... in the
@@ -190,13 +198,13 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
 #pragma unroll
         for (int j = 0; j < 4; ++j) S[j] = zero;
 #pragma unroll 4
-        for (int q = 0; q < o1; ++q) S[0] = cadd(S[0], cmul(xr[q], wt[q * T]));
+        for (int q = 0; q < o1; ++q) cmac(S[0], xr[q], wt[q * T]);
 #pragma unroll 4
-        for (int q = o1; q < o2; ++q) S[1] = cadd(S[1], cmul(xr[q], wt[q * T]));
+        for (int q = o1; q < o2; ++q) cmac(S[1], xr[q], wt[q * T]);
 #pragma unroll 4
-        for (int q = o2; q < o3; ++q) S[2] = cadd(S[2], cmul(xr[q], wt[q * T]));
+        for (int q = o2; q < o3; ++q) cmac(S[2], xr[q], wt[q * T]);
 #pragma unroll 4
-        for (int q = o3; q < nq; ++q) S[3] = cadd(S[3], cmul(xr[q], wt[q * T]));
+        for (int q = o3; q < nq; ++q) cmac(S[3], xr[q], wt[q * T]);
         const float2 a = cadd(S[0], S[2]), b = make_float2(S[0].x - S[2].x, S[0].y - S[2].y);
         const float2 cc = cadd(S[1], S[3]), d = make_float2(S[1].x - S[3].x, S[1].y - S[3].y);
         v[0] = cadd(a, cc);                              // i^0
@@ -277,13 +285,22 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         continue;   // uniform over the workgroup
       }
       // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); one scan counts the nonzeros of both rows
+      // (with c_{t-1} = 0 on the row, z_{t+1} = c_t + beta_t c_t has the same nonzeros)
       float2 zn[E];
       int mine = 0;
+      if (n1 == 0) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        zn[e] = make_float2(v[e].x + bt * (v[e].x - p1[e].x), v[e].y + bt * (v[e].y - p1[e].y));
-        mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
-        mine += (zn[e].x != 0.f || zn[e].y != 0.f) ? (1 << 16) : 0;
+        for (int e = 0; e < E; ++e) {
+          zn[e] = make_float2(__builtin_fmaf(bt, v[e].x, v[e].x), __builtin_fmaf(bt, v[e].y, v[e].y));
+          mine += (v[e].x != 0.f || v[e].y != 0.f) ? (1 << 16) + 1 : 0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          zn[e] = make_float2(v[e].x + bt * (v[e].x - p1[e].x), v[e].y + bt * (v[e].y - p1[e].y));
+          mine += (v[e].x != 0.f || v[e].y != 0.f) ? 1 : 0;
+          mine += (zn[e].x != 0.f || zn[e].y != 0.f) ? (1 << 16) : 0;
+        }
       }
       int tot2, before2;
       row_prefix<T>(mine, t, nullptr, tot2, before2);
