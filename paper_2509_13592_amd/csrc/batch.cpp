@@ -465,8 +465,9 @@ int bccb_batch_create(const bccb_plan_t* plans, int nscenes, void* stream, bccb_
       if (rc == BCCB_OK) rc = dalloc(&c.d_colslot, colslot.size());
       for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
         rc = dalloc(&c.d_pcnt[i], rows);
-        if (rc == BCCB_OK) rc = dalloc(&c.d_psidx[i], rows * (c.L1 / 8));
-        if (rc == BCCB_OK) rc = dalloc(&c.d_psval[i], rows * (c.L1 / 8));
+        // L1/8 slots per row for the passes, L1/kResidentSlotDiv for the persistent solve
+        if (rc == BCCB_OK) rc = dalloc(&c.d_psidx[i], rows * (c.L1 / kResidentSlotDiv));
+        if (rc == BCCB_OK) rc = dalloc(&c.d_psval[i], rows * (c.L1 / kResidentSlotDiv));
         if (rc == BCCB_OK) rc = dalloc(&c.d_pdense[i], pts);
         // rows start out dense over a zeroed grid: nothing unwritten is ever read
         if (rc == BCCB_OK && (hipMemset(c.d_pcnt[i], 0x7f, rows * sizeof(int)) != hipSuccess ||

@@ -37,6 +37,10 @@ struct ResidentClass {
 
 // Elements per thread of the transforms (N / 4 threads per row or column).
 constexpr int kResidentE = 4;
+// The persistent solve keeps an iterate row in slots while it has at most N / 4 nonzeros
+// (the early iterations' rows hold 33..64 nonzeros for several iterations, which the pass
+// graph's N / 8 stores densely): the class's slot buffers hold N / 4 slots per row.
+constexpr int kResidentSlotDiv = 4;
 
 // Workgroup LDS of a class at `nthreads` threads, in bytes: kept spectra N x xs,
 // N twiddles, two exchange areas per transform group, the row inverse's twiddles

@@ -83,7 +83,8 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   constexpr int T = F::T;
   static_assert(T <= 64 && 64 % T == 0, "a transform inside one wavefront");
   constexpr int FA = fft_area(N);
-  constexpr int CAP = SparseRow<N>::CAP;
+  constexpr int CAP = N / kResidentSlotDiv;     // slots per row of the stored iterate
+  constexpr int DIRECT = SparseRow<N>::CAP;     // direct forward sums up to N / 8 nonzeros, else the row FFT
   constexpr int SPT = (CAP + T - 1) / T;
   const int G = static_cast<int>(blockDim.x) / T;
   const int g = static_cast<int>(threadIdx.x) / T;
@@ -323,8 +324,8 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         }
       }
       // X = DFT_rows(z_{t+1}) on the kept columns: direct sums over its nonzeros when it has
-      // at most CAP of them (none for most rows once the iterate is sparse), else the row FFT
-      if (ztot > CAP) {
+      // at most N/8 of them (none for most rows once the iterate is sparse), else the row FFT
+      if (ztot > DIRECT) {
         fft_fwd<F>(zn, t, stw, sa, sb, true);
 #pragma unroll
         for (int e = 0; e < E; ++e)
