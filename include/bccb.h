@@ -462,6 +462,20 @@ int lista_solve(bccb_lista_t net, const float* params, const bccb_c32* y, const 
 int lista_autotune(bccb_lista_t net, int reps);
 
 /*
+ * lista_set_resident -- 1 (the default where the context supports it): the
+ *   gated solve runs each check interval of the fallback FISTA over the active
+ *   scenes as one launch of the persistent whole-solve kernel (see
+ *   bccb_batch_set_resident), the iterate, its kept spectra and the rows'
+ *   counts carried between the intervals in the context's buffers; 0: the
+ *   pruned passes per iteration.  Supported for square grids of 32..256 points
+ *   with a kept-column set whose workgroup state fits the device's LDS.
+ *   Results agree to FP32 rounding.  For callers comparing the two forms.
+ *   BCCB_E_UNSUPPORTED for 1 on a context without support, BCCB_E_INVALID for a
+ *   null context or a value other than 0 or 1.
+ */
+int lista_set_resident(bccb_lista_t net, int on);
+
+/*
  * Dense "regular" baseline (Sec. II-B and the runtime comparison of Sec. III-C):
  * the explicit L x L complex64 iteration matrix, multiplied by the iterate
  * every iteration -- O(L^2) bytes and flops per iteration against the

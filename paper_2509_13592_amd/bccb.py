@@ -122,6 +122,7 @@ _SIGS = {
     "bccb_batch_resident_info": (_i, [_vp, _pi, _pi, _pi, _pi]),
     "bccb_batch_class_config": (_i, [_vp, _i, _pi]),
     "lista_autotune": (_i, [_vp, _i]),
+    "lista_set_resident": (_i, [_vp, _i]),
     "bccb_stream_copy": (_i, [_vp, _vp, ctypes.c_size_t, _i, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -669,6 +670,10 @@ class Lista:
     def autotune(self, reps: int = 5):
         """Tune the fallback FISTA's pruned pass shapes (where the plan has kept columns)."""
         check(lib.lista_autotune(self._h, int(reps)), "lista_autotune")
+
+    def set_resident(self, on: bool):
+        """Run the fallback's check intervals as persistent launches (the default) or as passes."""
+        check(lib.lista_set_resident(self._h, 1 if on else 0), "lista_set_resident")
 
     def solve(self, params, ys, taus, kkt_target=1e-4, check_every=10, max_iters=20000, out=None, restart=False):
         """KKT-gated solve (params=None: plain FISTA from zero); restart=True restarts the

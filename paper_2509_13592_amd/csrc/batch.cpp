@@ -293,6 +293,9 @@ int resident_setup(bccb_batch_s* b) {
     r.colslot = c.d_colslot;
     r.scol = c.d_scol;
     r.sup_ptr = c.d_sup_ptr;
+    r.colslot_stride = c.L1;
+    r.scol_stride = c.ncs;
+    r.sup_ptr_stride = c.L1 + 1;   // entry offsets into the class's concatenated support
     r.sup = c.d_sup;
     r.sup_rhs = c.d_sup_rhs;
     r.coef = c.d_coef;
@@ -598,8 +601,8 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
   if (resident) {
     BCCB_TRY(resident_betas(b, iters, s));
     BCCB_TRY(kern(launch_fill_int(b->d_queue, 1, 0, s)));
-    BCCB_TRY(kern(launch_scene_fista(b->d_rcls, b->res_ncls, b->n, b->d_beta, iters, b->d_queue, b->res_threads,
-                                     b->res_blocks, b->res_lds, s)));
+    BCCB_TRY(kern(launch_scene_fista(b->d_rcls, b->res_ncls, b->n, b->d_beta, 0, iters, 0, b->d_queue,
+                                     b->res_threads, b->res_blocks, b->res_lds, s)));
   } else if (iters > 0) {
     if (!b->exec || b->graph_iters != iters) {
       if (b->exec) (void)hipGraphExecDestroy(b->exec);

@@ -16,23 +16,31 @@
 
 namespace bccb {
 
-// One size class of the batch (square grids L1 = L2 = N), every array in class-arena order.
+// One size class (square grids L1 = L2 = N), every per-scene array in arena order of the
+// physical scene k; a table shared by all scenes takes stride 0.
 struct ResidentClass {
   int N = 0;                     // grid length, one of 32, 64, 128, 256
-  int n = 0;                     // scenes
+  int n = 0;                     // scenes taken from the queue
   int ncs = 0;                   // kept-column slots per scene
   int xs = 0;                    // LDS row stride of the kept spectra (ncs rounded up to odd)
   int first = 0;                 // queue index of the class's first scene
-  const int* colslot = nullptr;  // [n][N] spectral column -> slot (-1 = not kept)
-  const int* scol = nullptr;     // [n][ncs] slot -> spectral column (-1 = padding)
-  const int* sup_ptr = nullptr;  // [n][N + 1] entry offsets of each spectral column
+  const int* colslot = nullptr;  // [N] per scene: spectral column -> slot (-1 = not kept)
+  const int* scol = nullptr;     // [ncs] per scene: slot -> spectral column (-1 = padding)
+  const int* sup_ptr = nullptr;  // [N + 1] per scene: entry offsets of each spectral column
+  long colslot_stride = 0, scol_stride = 0, sup_ptr_stride = 0;
   const SupEntry* sup = nullptr; // support bins (k2, Omega)
-  const float2* sup_rhs = nullptr;  // mu * spectral right-hand side per entry
-  const float2* coef = nullptr;  // [n] (1/L, -mu/L)
-  const float* kscale = nullptr; // [n] mu * tau
+  const float2* sup_rhs = nullptr;  // mu * spectral right-hand side of entry j of scene k at k * rhs_stride + j
+  long rhs_stride = 0;
+  const float2* coef = nullptr;  // per scene (1/L, -mu/L), stride coef_stride
+  long coef_stride = 1;
+  const float* kscale = nullptr; // per scene; the threshold is kmul * kscale[k]
+  float kmul = 1.f;
   const float2* tw = nullptr;    // [N] e^{-j 2 pi j / N}
-  const SceneDesc* desc = nullptr;  // [n] output grids
-  SlotBuf buf[3];                // iterate rows [n][N], rotating c_t, c_{t-1}, c_{t-2}
+  const SceneDesc* desc = nullptr;  // [n] output grids (or out_base + k N^2 when out_base is set)
+  float2* out_base = nullptr;
+  const int* scene_map = nullptr;   // queue position - first -> physical scene (nullable: identity)
+  float2* xkeep = nullptr;       // [scenes][N][ncs] kept spectra of z carried between launches (slot order)
+  SlotBuf buf[3];                // iterate rows [scenes][N], rotating c_t, c_{t-1}, c_{t-2}; counts in cnt
 };
 
 // Elements per thread of the transforms (N / 4 threads per row or column).
@@ -44,19 +52,25 @@ constexpr int kResidentSlotDiv = 4;
 
 // Workgroup LDS of a class at `nthreads` threads, in bytes: kept spectra N x xs,
 // N twiddles, two exchange areas per transform group, the row inverse's twiddles
-// (ncs x N/E), three [N] count arrays and the kept-column tables (2 ncs + 8 ints).
+// (ncs x N/E), three [N] count arrays and the kept-column tables (3 ncs + 8 ints).
 constexpr long resident_lds_bytes(int N, int ncs, int nthreads) {
   const int T = N / kResidentE;
   const long G = nthreads / T;
   const long xs = ncs | 1;
-  return 8L * (N * xs + N + 2L * G * fft_area(N) + static_cast<long>(ncs) * T) + 12L * N + 4L * (2L * ncs + 8);
+  return 8L * (N * xs + N + 2L * G * fft_area(N) + static_cast<long>(ncs) * T) + 12L * N + 4L * (3L * ncs + 8);
 }
 
 // Persistent launch over `total` scenes of `ncls` classes (device table `cls`, classes in
-// queue order); beta[t] (t = 1..iters, beta[0] = 0) are the momentum weights; *queue = 0
-// on entry.  Returns -1 for a shape the kernel does not take.
-int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int iters, int* queue,
-                       int nthreads, int blocks, size_t lds, hipStream_t s);
+// queue order), iterations it0 + 1 .. it0 + steps of each (the iterate buffers rotate with
+// the iteration number); beta[t] is the momentum weight of iteration t (beta[it0] that of
+// the iteration before the first).  carry = 0: every scene starts from zero and only the
+// last iterate is written (to the outputs); carry = 1: the kept spectra of z and the row
+// counts of the iterates are loaded from xkeep and buf[].cnt at the start and stored back
+// at the end, and the last iterate is written densely to the outputs as well, so a later
+// launch continues the solves.  *queue = 0 on entry.  Returns -1 for a shape the kernel
+// does not take.
+int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int it0, int steps,
+                       int carry, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s);
 
 // Workgroups of the kernel one compute unit holds at this shape (0: does not fit).
 int scene_fista_occupancy(int nthreads, size_t lds);

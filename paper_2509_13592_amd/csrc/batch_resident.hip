@@ -77,7 +77,8 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
 // is then four sums S_j = sum over the q of class j of X_q w^{k1_q t} followed by one
 // 4-point transform, with the per-thread twiddles w^{k1_q t} read from LDS.
 template <int N, int E>
-__device__ void solve_scene(const ResidentClass& c, int k, const float* beta, int iters, float2* lds) {
+__device__ void solve_scene(const ResidentClass& c, int k, const float* beta, int it0, int steps, int carry,
+                            float2* lds) {
   static_assert(E == 4, "the row inverse is a 4-point transform of four class sums");
   using F = Stockham<N, E, true>;
   constexpr int T = F::T;
@@ -98,22 +99,19 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   int* cntl = reinterpret_cast<int*>(tw2 + ncs * T);   // [3][N] nonzeros of the row of c_t (> CAP: dense)
   int* qpos = cntl + 3 * N;              // [ncs] slot -> kept-column position q (-1: padding)
   int* qk1 = qpos + ncs;                 // [ncs] q -> spectral column k1
-  int* qoff = qk1 + ncs;                 // [5] class bounds of q
+  int* qsl = qk1 + ncs;                  // [ncs] q -> slot
+  int* qoff = qsl + ncs;                 // [5] class bounds of q
   const float2 zero = make_float2(0.f, 0.f);
 
-  const float kappa = c.kscale[k];
-  const float cb = c.coef[k].y;
-  const int* scol = c.scol + static_cast<size_t>(k) * ncs;
-  const int* sptr = c.sup_ptr + static_cast<size_t>(k) * (N + 1);
-  float2* out = c.desc[k].out;
+  const float kappa = c.kmul * ldg(c.kscale, k);
+  const float cb = ldg2(c.coef, static_cast<size_t>(k) * c.coef_stride).y;
+  const int* scol = c.scol + static_cast<size_t>(k) * c.scol_stride;
+  const int* sptr = c.sup_ptr + static_cast<size_t>(k) * c.sup_ptr_stride;
+  const float2* srhs = c.sup_rhs + static_cast<size_t>(k) * c.rhs_stride;
+  float2* out = c.out_base ? c.out_base + static_cast<size_t>(k) * N * N : c.desc[k].out;
 
-  // z_1 = 0: zero kept spectra; c_0 = c_{-1} = 0: empty rows; the kept columns by class
-  for (int j = threadIdx.x; j < N * xs; j += blockDim.x) X[j] = zero;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    stw[j] = c.tw[j];
-    cntl[j] = 0;
-    cntl[2 * N + j] = 0;
-  }
+  // the kept columns by class; twiddles
+  for (int j = threadIdx.x; j < N; j += blockDim.x) stw[j] = c.tw[j];
   if (threadIdx.x == 0) {
     int q = 0;
     for (int j = 0; j < 4; ++j) {
@@ -124,6 +122,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         if (k1 >= 0 && (k1 & 3) == j) {
           qpos[s] = q;
           qk1[q] = k1;
+          qsl[q] = s;
           ++q;
         }
       }
@@ -132,13 +131,29 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   }
   __syncthreads();
   const int nq = qoff[4];
+  if (carry) {
+    // z's kept spectra (slot order in memory) and the iterates' row counts of the last launch
+    for (int j = threadIdx.x; j < N * nq; j += blockDim.x) {
+      const int r = j / nq, q = j - (j / nq) * nq;
+      X[r * xs + q] = ldg2(c.xkeep, (static_cast<size_t>(k) * N + r) * ncs + qsl[q]);
+    }
+    for (int j = threadIdx.x; j < 3 * N; j += blockDim.x)
+      cntl[j] = ldg(c.buf[j / N].cnt, static_cast<size_t>(k) * N + (j - (j / N) * N));
+  } else {
+    // z_1 = 0: zero kept spectra; c_0 = c_{-1} = 0: empty rows
+    for (int j = threadIdx.x; j < N * xs; j += blockDim.x) X[j] = zero;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      cntl[j] = 0;
+      cntl[2 * N + j] = 0;
+    }
+  }
   for (int j = threadIdx.x; j < nq * T; j += blockDim.x) {
     const float2 w = stw[(qk1[j / T] * (j % T)) & (N - 1)];
     tw2[j] = make_float2(w.x, -w.y);   // e^{+j 2 pi k1 t / N}
   }
   int kq[E];   // kept-column position of each spectral bin this thread holds after a forward row transform
   {
-    const int* cs = c.colslot + static_cast<size_t>(k) * N;
+    const int* cs = c.colslot + static_cast<size_t>(k) * c.colslot_stride;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int sl = ldg(cs, F::out_index(t0, e));
@@ -148,7 +163,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   const int o1 = qoff[1], o2 = qoff[2], o3 = qoff[3];
   __syncthreads();
 
-  for (int it = 1; it <= iters; ++it) {
+  for (int it = it0 + 1; it <= it0 + steps; ++it) {
     // column pass over the kept columns: X[:, q] = IDFT_cols(m . DFT_cols(X[:, q]) + r),
     // m = b Omega_j and r = rhs_j on the column's support bins, m = r = 0 elsewhere
     for (int q = g; q < nq; q += G) {
@@ -167,7 +182,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       const int j0 = ldg(sptr, k1), j1 = ldg(sptr, k1 + 1);
       for (int j = j0; j < j1; ++j) {
         const SupEntry en = ldg(c.sup, j);
-        const float2 r = ldg2(c.sup_rhs, j);
+        const float2 r = ldg2(srhs, j);
         const float m = cb * en.omega;
 #pragma unroll
         for (int e = 0; e < E; ++e)
@@ -183,7 +198,8 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
     // X = DFT_rows(c_t + beta_t (c_t - c_{t-1})) on the kept columns
     const int i0 = it % 3, i1 = (it - 1) % 3, i2 = (it + 1) % 3;
     const float bt = beta[it], bp = beta[it - 1];
-    const bool last = it == iters;
+    const bool fin = it == it0 + steps;   // the launch's last iteration: c_t goes to the outputs
+    const bool last = fin && !carry;      // ... and nothing after it is needed
     const SlotBuf b0 = c.buf[i0], b1 = c.buf[i1], b2 = c.buf[i2];
     for (int r = g; r < N; r += G) {
       const int t = opaque(t0);
@@ -280,10 +296,10 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         }
       }
 
-      if (last) {
+      if (fin) {
 #pragma unroll
         for (int e = 0; e < E; ++e) stg2(out, static_cast<size_t>(r) * N + F::in_index(t, e), v[e]);
-        continue;   // uniform over the workgroup
+        if (last) continue;   // uniform over the workgroup
       }
       // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); one scan counts the nonzeros of both rows
       // (with c_{t-1} = 0 on the row, z_{t+1} = c_t + beta_t c_t has the same nonzeros)
@@ -363,10 +379,21 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
     }
     __syncthreads();
   }
+  if (carry) {
+    // the next launch continues from z's kept spectra and the row counts
+    for (int j = threadIdx.x; j < N * nq; j += blockDim.x) {
+      const int r = j / nq, q = j - (j / nq) * nq;
+      stg2(c.xkeep, (static_cast<size_t>(k) * N + r) * ncs + qsl[q], X[r * xs + q]);
+    }
+    for (int j = threadIdx.x; j < 3 * N; j += blockDim.x)
+      stg(c.buf[j / N].cnt, static_cast<size_t>(k) * N + (j - (j / N) * N), cntl[j]);
+    __syncthreads();   // LDS is reused by the next scene
+  }
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass* cls, int ncls, int total,
-                                                             const float* beta, int iters, int* queue) {
+                                                             const float* beta, int it0, int steps, int carry,
+                                                             int* queue) {
   extern __shared__ float2 lds[];
   __shared__ int item;
   for (;;) {
@@ -378,12 +405,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass
     int ci = 0;
     while (ci + 1 < ncls && q >= cls[ci + 1].first) ++ci;
     const ResidentClass& c = cls[ci];
-    const int k = q - c.first;
+    const int k = c.scene_map ? c.scene_map[q - c.first] : q - c.first;
     switch (c.N) {
-      case 32: solve_scene<32, kResidentE>(c, k, beta, iters, lds); break;
-      case 64: solve_scene<64, kResidentE>(c, k, beta, iters, lds); break;
-      case 128: solve_scene<128, kResidentE>(c, k, beta, iters, lds); break;
-      case 256: solve_scene<256, kResidentE>(c, k, beta, iters, lds); break;
+      case 32: solve_scene<32, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
+      case 64: solve_scene<64, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
+      case 128: solve_scene<128, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
+      case 256: solve_scene<256, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
       default: break;
     }
   }
@@ -391,14 +418,16 @@ __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass
 
 }  // namespace
 
-int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int iters, int* queue,
-                       int nthreads, int blocks, size_t lds, hipStream_t s) {
-  if (!cls || ncls < 1 || total < 1 || !beta || iters < 1 || !queue) return -1;
+int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int it0, int steps,
+                       int carry, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s) {
+  if (!cls || ncls < 1 || total < 1 || !beta || it0 < 0 || steps < 1 || (carry != 0 && carry != 1) || !queue)
+    return -1;
   if (nthreads < 64 || nthreads > kMaxThreads || nthreads % 64 != 0 || blocks < 1) return -1;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scene_fista), hipFuncAttributeMaxDynamicSharedMemorySize,
                           static_cast<int>(lds)) != hipSuccess)
     return -2;
-  hipLaunchKernelGGL(k_scene_fista, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, iters, queue);
+  hipLaunchKernelGGL(k_scene_fista, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, it0, steps, carry,
+                     queue);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -6,6 +6,7 @@
 #include <new>
 #include <vector>
 
+#include "batch_resident.h"
 #include "bccb.h"
 #include "kernels.h"
 #include "lista.h"
@@ -71,6 +72,17 @@ struct bccb_lista_s {
   DilEntry* d_dil = nullptr;
   float2* d_xycd = nullptr;                     // [cap][L2][ncsd]
   PassCfg rcfgd, ccfgd;
+  // the fallback's iterations as chunks of the persistent whole-solve launch (batch_resident.h):
+  // each check interval of the active scenes is one launch carrying the state in d_xyc and
+  // the slot buffers' counts
+  bool res_ok = false, res_on = false;
+  ResidentClass* d_rcls = nullptr;
+  int res_threads = 0, res_blocks = 0;
+  size_t res_lds = 0;
+  int* d_queue = nullptr;
+  float* d_rbeta = nullptr;                     // [rbeta_cap] momentum weights of the fallback
+  float* h_rbeta = nullptr;                     // pinned
+  int rbeta_cap = 0;
 };
 
 namespace {
@@ -92,6 +104,9 @@ void lista_free(bccb_lista_s* n) {
                   n->d_desc, n->d_map, n->d_flag, n->d_sup_rhs, n->d_sdesc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (void* p : {static_cast<void*>(n->d_rcls), static_cast<void*>(n->d_queue), static_cast<void*>(n->d_rbeta)})
+    if (p) (void)hipFree(p);
+  if (n->h_rbeta) (void)hipHostFree(n->h_rbeta);
   for (void* p : {static_cast<void*>(n->d_xyc), static_cast<void*>(n->d_R0), static_cast<void*>(n->d_xyck),
                   static_cast<void*>(n->d_dscol), static_cast<void*>(n->d_dcolslot), static_cast<void*>(n->d_dsup_ptr),
                   static_cast<void*>(n->d_dil), static_cast<void*>(n->d_xycd)})
@@ -320,6 +335,88 @@ int kkt_sums(bccb_lista_s* n, int nact, const int* map) {
   return kern(rows_to_scene(n->d_rows, n->L2, nact, map, n->d_rk, n->stream));
 }
 
+// The persistent launch for the pruned fallback: one class (the plan's square grid), tables
+// shared by every scene, the per-scene right-hand sides and thresholds, the active list as
+// the scene map, the fallback's slot buffers and kept spectra as the carried state, and the
+// dense iterate c as the output.  Leaves res_ok false when the shape does not fit.
+int resident_setup(bccb_lista_s* n) {
+  bccb_plan_s* pl = n->plan;
+  const int N = n->L1;
+  if (n->L1 != n->L2 || (N != 32 && N != 64 && N != 128 && N != 256) || pl->ncs < 1) return BCCB_OK;
+  ResidentClass r;
+  r.N = N;
+  r.n = n->cap;
+  r.ncs = pl->ncs;
+  r.xs = pl->ncs | 1;
+  r.colslot = pl->d_colslot;
+  r.scol = pl->d_scol;
+  r.sup_ptr = pl->d_sup_ptr;
+  r.sup = pl->d_sup;
+  r.sup_rhs = n->d_sup_rhs;
+  r.rhs_stride = pl->nsup;
+  r.coef = n->d_coef_fista;
+  r.kscale = n->d_tau;
+  r.kmul = static_cast<float>(pl->mu);
+  r.tw = pl->d_tw1;
+  r.out_base = n->d_c;
+  r.scene_map = n->d_map;
+  r.xkeep = n->d_xyc;
+  float2* dense[3] = {n->d_R0, n->d_xy, n->d_cprev};
+  for (int i = 0; i < 3; ++i) {
+    r.buf[i].cnt = n->d_pcnt[i];
+    r.buf[i].sidx = n->d_psidx[i];
+    r.buf[i].sval = n->d_psval[i];
+    r.buf[i].dense = dense[i];
+  }
+  int best = 0;
+  for (int nt : {256, 512, 1024}) {
+    const long lds = resident_lds_bytes(N, r.ncs, nt);
+    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds));
+    if (nb * (nt / 64) > best) {
+      best = nb * (nt / 64);
+      n->res_threads = nt;
+      n->res_lds = static_cast<size_t>(lds);
+      n->res_blocks = nb;
+    }
+  }
+  if (best == 0) return BCCB_OK;
+  int dev = 0, cus = 0;
+  BCCB_HIP(hipGetDevice(&dev));
+  BCCB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  n->res_blocks *= std::max(cus, 1);
+  BCCB_TRY(dalloc(&n->d_rcls, 1));
+  BCCB_TRY(dalloc(&n->d_queue, 1));
+  BCCB_HIP(hipMemcpy(n->d_rcls, &r, sizeof(ResidentClass), hipMemcpyHostToDevice));
+  n->res_ok = n->res_on = true;
+  return BCCB_OK;
+}
+
+// Momentum weights of the fallback: beta[0] = the weight before its first iteration,
+// beta[t] = (alpha_t - 1) / alpha_{t+1} from alpha, for t = 1..iters (the graph loop's schedule).
+int resident_betas(bccb_lista_s* n, int iters, double alpha, float beta0) {
+  if (iters + 1 > n->rbeta_cap) {
+    if (n->d_rbeta) (void)hipFree(n->d_rbeta);
+    if (n->h_rbeta) (void)hipHostFree(n->h_rbeta);
+    n->d_rbeta = nullptr;
+    n->h_rbeta = nullptr;
+    n->rbeta_cap = 0;
+    BCCB_TRY(dalloc(&n->d_rbeta, iters + 1));
+    if (hipHostMalloc(reinterpret_cast<void**>(&n->h_rbeta), (iters + 1) * sizeof(float)) != hipSuccess) {
+      n->h_rbeta = nullptr;
+      return BCCB_E_NOMEM;
+    }
+    n->rbeta_cap = iters + 1;
+  }
+  n->h_rbeta[0] = beta0;
+  for (int t = 1; t <= iters; ++t) {
+    const double an = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    n->h_rbeta[t] = static_cast<float>((alpha - 1.0) / an);
+    alpha = an;
+  }
+  BCCB_HIP(hipMemcpyAsync(n->d_rbeta, n->h_rbeta, (iters + 1) * sizeof(float), hipMemcpyHostToDevice, n->stream));
+  return BCCB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -409,8 +506,9 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
     if (rc == BCCB_OK) rc = dalloc(&n->d_R0, pts);
     for (int i = 0; i < 3 && rc == BCCB_OK; ++i) {
       rc = dalloc(&n->d_pcnt[i], rows);
-      if (rc == BCCB_OK) rc = dalloc(&n->d_psidx[i], rows * (n->L1 / 8));
-      if (rc == BCCB_OK) rc = dalloc(&n->d_psval[i], rows * (n->L1 / 8));
+      // L1/8 slots per row for the passes, L1/kResidentSlotDiv for the persistent launch
+      if (rc == BCCB_OK) rc = dalloc(&n->d_psidx[i], rows * (n->L1 / kResidentSlotDiv));
+      if (rc == BCCB_OK) rc = dalloc(&n->d_psval[i], rows * (n->L1 / kResidentSlotDiv));
     }
     n->prune = rc == BCCB_OK;
     n->rcfgp.E = n->L1 >= 16 ? 16 : 8;
@@ -487,11 +585,19 @@ int lista_create(bccb_plan_t plan, int layers, int max_batch, int train, bccb_li
         hipMemcpy(n->d_coef_gram, cg.data(), cg.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       rc = BCCB_E_DEVICE;
   }
+  if (rc == BCCB_OK && n->prune) rc = resident_setup(n);
   if (rc != BCCB_OK) {
     lista_free(n);
     return rc;
   }
   *out = n;
+  return BCCB_OK;
+}
+
+int lista_set_resident(bccb_lista_t n, int on) {
+  if (!n || (on != 0 && on != 1)) return BCCB_E_INVALID;
+  if (on == 1 && !n->res_ok) return BCCB_E_UNSUPPORTED;
+  n->res_on = on == 1;
   return BCCB_OK;
 }
 
@@ -799,10 +905,20 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
       BCCB_TRY(row(n, ROW_FWD, f, na));
     }
   }
+  const bool resident = pruned && n->res_on && !act.empty() && max_iters > 0;
+  if (resident) BCCB_TRY(resident_betas(n, max_iters, alpha, beta_prev));
   while (!act.empty() && done_iters < max_iters) {
     const int na = static_cast<int>(act.size());
     const int steps = std::min(check_every, max_iters - done_iters);
-    for (int t = 0; t < steps; ++t) {
+    if (resident) {
+      // the check interval of every active scene in one persistent launch (iterations
+      // tp + 1 .. tp + steps, the state carried in d_xyc and the slot counts, c_t to d_c)
+      BCCB_TRY(kern(launch_fill_int(n->d_queue, 1, 0, s)));
+      BCCB_TRY(kern(launch_scene_fista(n->d_rcls, 1, na, n->d_rbeta, tp, steps, 1, n->d_queue, n->res_threads,
+                                       std::min(n->res_blocks, na), n->res_lds, s)));
+      tp += steps;
+    }
+    for (int t = 0; t < steps && !resident; ++t) {
       const double an = (1.0 + std::sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
       const float beta = static_cast<float>((alpha - 1.0) / an);
       alpha = an;
