@@ -184,3 +184,34 @@ def test_learned_backward_paper_scale():
         assert err <= 1e-3, (name, err)
     net.close()
     plan.close()
+
+
+def test_uniform_batch_persistent_sampled():
+    """The uniform batch the benchmark times: 1024 paper-scale 256^2 scenes, FISTA 100, as one
+    persistent launch (1024-thread workgroups); a sample of scenes against the oracle one by
+    one, objective and iterate."""
+    n, T = 1024, 100
+    scenes = [S.paper_scale_scene(i) for i in range(n)]
+    plans = [B.Plan(sc.mask, sc.L1, sc.L2) for sc in scenes]
+    ys = [B.to_device(sc.y) for sc in scenes]
+    taus = [float(np.float32(0.1 * p.adjoint_maxabs(y))) for p, y in zip(plans, ys)]
+    batch = B.Batch(plans)
+    info = batch.resident_info()
+    print("persistent launch", info, flush=True)
+    assert info["on"] == 1 and info["threads"] == 1024
+    outs = batch.fista(ys, taus, T)
+    worst = (0.0, 0.0)
+    for i in (0, 1, 255, 511, 700, 1023):
+        sc = scenes[i]
+        P = O.Problem(sc.mask, sc.L1, sc.L2, sc.y, tau=taus[i], dense=False)
+        ref = P.fista(T)
+        g = _np(outs[i])
+        Fr = P.objective(ref)
+        rel, eps = abs(P.objective(g) - Fr) / Fr, _rel(g, ref)
+        worst = (max(worst[0], rel), max(worst[1], eps / iter_tol(T, P.op.L)))
+        print(f"case uniform batch scene {i}: rel F {rel:.2e} eps_r {eps:.2e}", flush=True)
+        assert rel <= OBJ_TOL and eps <= iter_tol(T, P.op.L)
+    print(f"worst rel F {worst[0]:.2e}, worst eps_r / bound {worst[1]:.2f}", flush=True)
+    batch.close()
+    for p in plans:
+        p.close()
