@@ -50,8 +50,9 @@ __device__ __forceinline__ void stg2(float2* p, size_t i, float2 v) {
 // The complex soft threshold of passes.h (zero for |z| <= k, z (1 - k/|z|) above),
 // formed without a branch: the reciprocal square root is taken for every element
 // and the factor selected, so a row's lanes never split over the two cases.
+__device__ __forceinline__ float sq_abs(float2 z) { return __builtin_fmaf(z.x, z.x, z.y * z.y); }
 __device__ __forceinline__ float2 shrink_sel(float2 z, float k) {
-  const float a2 = z.x * z.x + z.y * z.y;
+  const float a2 = sq_abs(z);
   const float f = 1.f - k * __builtin_amdgcn_rsqf(a2);
   const float m = a2 > k * k ? f : 0.f;
   return make_float2(z.x * m, z.y * m);
@@ -230,12 +231,20 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
         v[3] = make_float2(b.x + d.y, b.y - d.x);        // S0 - i S1 - S2 + i S3
       }
       float2 p1[E];
+      bool cold = false;   // c_t and z_{t+1} vanish on the row
       if (n1 == 0 && n2 == 0) {
+        // z_t = 0 on the row: c_t = S_kappa(u).  Where no element of the rows of this
+        // wavefront in this branch exceeds the threshold, the rows stay empty and the
+        // threshold, counts and forward sums are skipped
+        bool hot = false;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           p1[e] = zero;
-          v[e] = shrink_sel(v[e], kappa);
+          hot = hot || sq_abs(v[e]) > kappa * kappa;   // the threshold's own test
         }
+        cold = !__any(hot);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cold ? zero : shrink_sel(v[e], kappa);
       } else {
         // dense rows straight into registers; slot rows scattered into zeroed areas
         const bool full1 = n1 > CAP, full2 = n2 > CAP;
@@ -300,6 +309,13 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
 #pragma unroll
         for (int e = 0; e < E; ++e) stg2(out, static_cast<size_t>(r) * N + F::in_index(t, e), v[e]);
         if (last) continue;   // uniform over the workgroup
+      }
+      if (cold) {
+        if (t == 0) cntl[i0 * N + r] = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (kq[e] >= 0) xr[kq[e]] = zero;
+        continue;
       }
       // z_{t+1} = c_t + beta_t (c_t - c_{t-1}); one scan counts the nonzeros of both rows
       // (with c_{t-1} = 0 on the row, z_{t+1} = c_t + beta_t c_t has the same nonzeros)
