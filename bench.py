@@ -64,7 +64,7 @@ BATCH_TRAFFIC = {
 # dispatch / scene-iterations), keyed by the code of its sources and the workload they were
 # counted on: profiles/fista_persistent_batch_256_rocprofv3.md
 PERSISTENT_VALU = {
-    "2842c35c67b9f1a4": {"workload": (1024, 256, 100), "valu_per_scene_iteration": 81400},
+    "5589f0b87223b834": {"workload": (1024, 256, 100), "valu_per_scene_iteration": 81344},
 }
 VALU_ISSUE_PEAK = 256 * 2.4e9   # wave64 VALU instructions/s: one per compute unit per cycle
 

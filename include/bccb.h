@@ -466,8 +466,9 @@ int lista_autotune(bccb_lista_t net, int reps);
  *   gated solve runs each check interval of the fallback FISTA over the active
  *   scenes as one launch of the persistent whole-solve kernel (see
  *   bccb_batch_set_resident), the iterate, its kept spectra and the rows'
- *   counts carried between the intervals in the context's buffers; 0: the
- *   pruned passes per iteration.  Supported for square grids of 32..256 points
+ *   counts carried between the intervals in the context's buffers, and the
+ *   interval's KKT residuals formed by the same launch; 0: the pruned passes
+ *   per iteration, checked by separate kernels.  Supported for square grids of 32..256 points
  *   with a kept-column set whose workgroup state fits the device's LDS.
  *   Results agree to FP32 rounding.  For callers comparing the two forms.
  *   BCCB_E_UNSUPPORTED for 1 on a context without support, BCCB_E_INVALID for a

@@ -311,7 +311,7 @@ int resident_setup(bccb_batch_s* b) {
   for (int nt : {256, 512, 1024}) {
     long lds = 0;
     for (const ResidentClass& r : table) lds = std::max(lds, resident_lds_bytes(r.N, r.ncs, nt));
-    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds));
+    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds), 0);
     if (nb * (nt / 64) > best_waves) {
       best_waves = nb * (nt / 64);
       b->res_threads = nt;
@@ -601,7 +601,7 @@ int lasso_solve_batch_fista(bccb_batch_t b, const bccb_c32* const* y, const floa
   if (resident) {
     BCCB_TRY(resident_betas(b, iters, s));
     BCCB_TRY(kern(launch_fill_int(b->d_queue, 1, 0, s)));
-    BCCB_TRY(kern(launch_scene_fista(b->d_rcls, b->res_ncls, b->n, b->d_beta, 0, iters, 0, b->d_queue,
+    BCCB_TRY(kern(launch_scene_fista(b->d_rcls, b->res_ncls, b->n, b->d_beta, 0, iters, 0, 0, b->d_queue,
                                      b->res_threads, b->res_blocks, b->res_lds, s)));
   } else if (iters > 0) {
     if (!b->exec || b->graph_iters != iters) {
@@ -734,7 +734,7 @@ int bccb_batch_set_resident(bccb_batch_t b, int on) {
     std::vector<ResidentClass> table(b->res_ncls);
     BCCB_HIP(hipMemcpy(table.data(), b->d_rcls, table.size() * sizeof(ResidentClass), hipMemcpyDeviceToHost));
     for (const ResidentClass& r : table) lds = std::max(lds, resident_lds_bytes(r.N, r.ncs, on));
-    const int nb = scene_fista_occupancy(on, static_cast<size_t>(lds));
+    const int nb = scene_fista_occupancy(on, static_cast<size_t>(lds), 0);
     if (nb < 1) return BCCB_E_UNSUPPORTED;
     int dev = 0, cus = 0;
     BCCB_HIP(hipGetDevice(&dev));

@@ -41,6 +41,12 @@ struct ResidentClass {
   const int* scene_map = nullptr;   // queue position - first -> physical scene (nullable: identity)
   float2* xkeep = nullptr;       // [scenes][N][ncs] kept spectra of z carried between launches (slot order)
   SlotBuf buf[3];                // iterate rows [scenes][N], rotating c_t, c_{t-1}, c_{t-2}; counts in cnt
+  // Carrying launches only (nullable): per physical scene, the sum over the grid of e^2,
+  // the KKT conditions' violation at the launch's last iterate c (e = g - tau c/|c| where
+  // c != 0, max(|g| - tau, 0) elsewhere, g = b - G c, tau = kscale[k]); the column pass
+  // leaves the kept spectra of mu (b - G c) and kkt_scale = 1/mu takes the factor out.
+  double* kkt_sum = nullptr;
+  float kkt_scale = 0.f;
 };
 
 // Elements per thread of the transforms (N / 4 threads per row or column).
@@ -67,12 +73,15 @@ constexpr long resident_lds_bytes(int N, int ncs, int nthreads) {
 // last iterate is written (to the outputs); carry = 1: the kept spectra of z and the row
 // counts of the iterates are loaded from xkeep and buf[].cnt at the start and stored back
 // at the end, and the last iterate is written densely to the outputs as well, so a later
-// launch continues the solves.  *queue = 0 on entry.  Returns -1 for a shape the kernel
-// does not take.
+// launch continues the solves.  check = 1 (carrying launches only) runs the kernel's
+// variant that also leaves each scene's KKT sum in its class's kkt_sum (a separate
+// instantiation, so the plain launches keep their register allocation).  *queue = 0 on
+// entry.  Returns -1 for a shape the kernel does not take.
 int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int it0, int steps,
-                       int carry, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s);
+                       int carry, int check, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s);
 
-// Workgroups of the kernel one compute unit holds at this shape (0: does not fit).
-int scene_fista_occupancy(int nthreads, size_t lds);
+// Workgroups of the kernel (the checking variant for check = 1) one compute unit holds at
+// this shape (0: does not fit).
+int scene_fista_occupancy(int nthreads, size_t lds, int check);
 
 }  // namespace bccb

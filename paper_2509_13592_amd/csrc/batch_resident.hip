@@ -66,6 +66,53 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
   acc.y = __builtin_fmaf(a.y, b.x, acc.y);
 }
 
+// dst[kq[e]] = the DFT of the row x at the bin F::out_index(t, e), for the kept bins
+// (kq[e] >= 0) this thread holds; x holds the row's elements t + T e of thread t of the
+// group, `tot` nonzeros in the row, `before` of them with lower threads.  Direct sums over
+// the nonzeros where the row has at most N / 8 of them, the row FFT above that (x is
+// overwritten).  Uses the group's exchange areas A, B.
+template <class F, int N, int E>
+__device__ __forceinline__ void kept_forward(float2 (&x)[E], int tot, int before, int t, const int (&kq)[E],
+                                             const float2* stw, float2* sa, float2* sb, float2* dst) {
+  constexpr int DIRECT = SparseRow<N>::CAP;
+  const float2 zero = make_float2(0.f, 0.f);
+  if (tot > DIRECT) {
+    fft_fwd<F>(x, t, stw, sa, sb, true);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (kq[e] >= 0) dst[kq[e]] = x[e];
+  } else if (tot == 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (kq[e] >= 0) dst[kq[e]] = zero;
+  } else {
+    lds_sync<true>();   // the group's last use of its areas is done
+    int* zpos = reinterpret_cast<int*>(sb);
+    int o = before;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (x[e].x != 0.f || x[e].y != 0.f) {
+        sa[o] = x[e];
+        zpos[o] = F::in_index(t, e);
+        ++o;
+      }
+    }
+    lds_sync<true>();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (kq[e] >= 0) {
+        const int kk = F::out_index(t, e);
+        float2 acc = zero;
+        for (int q = 0; q < tot; ++q) {
+          const float2 w = stw[(kk * zpos[q]) & (N - 1)];   // e^{-j 2 pi k l / N}
+          acc = cadd(acc, cmul(sa[q], w));
+        }
+        dst[kq[e]] = acc;
+      }
+    }
+  }
+}
+
 // Every iteration of one scene's FISTA solve (eqs. (10)-(12)).  The workgroup is cut
 // into groups of T = N / E threads (inside one wavefront), each owning the kept
 // columns q = g, g + G, ... in the column pass and the rows r = g, g + G, ... in the
@@ -77,7 +124,13 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
 //   u(t + T e) = sum_q X_q w^{k1_q t} i^{k1_q e}      (w = e^{j 2 pi / N}),
 // is then four sums S_j = sum over the q of class j of X_q w^{k1_q t} followed by one
 // 4-point transform, with the per-thread twiddles w^{k1_q t} read from LDS.
-template <int N, int E>
+//
+// A carrying launch of a class with kkt_sum checks the KKT conditions at its last
+// iterate c_t inside the same workgroup once the state is saved: c_t's kept row spectra
+// (from the rows it wrote to the outputs) go to X, one more column pass turns them into
+// those of mu (b - G c_t), and a row pass of class sums forms the sum of e^2 over the
+// scene (the arithmetic of the separate KKT row kernel, in double).
+template <int N, int E, bool KKT>
 __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, int it0, int steps, int carry,
                             float2* lds) {
   static_assert(E == 4, "the row inverse is a 4-point transform of four class sums");
@@ -86,7 +139,6 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   static_assert(T <= 64 && 64 % T == 0, "a transform inside one wavefront");
   constexpr int FA = fft_area(N);
   constexpr int CAP = N / kResidentSlotDiv;     // slots per row of the stored iterate
-  constexpr int DIRECT = SparseRow<N>::CAP;     // direct forward sums up to N / 8 nonzeros, else the row FFT
   constexpr int SPT = (CAP + T - 1) / T;
   const int G = static_cast<int>(blockDim.x) / T;
   const int g = static_cast<int>(threadIdx.x) / T;
@@ -103,6 +155,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   int* qsl = qk1 + ncs;                  // [ncs] q -> slot
   int* qoff = qsl + ncs;                 // [5] class bounds of q
   const float2 zero = make_float2(0.f, 0.f);
+  const bool kkt = KKT && carry && c.kkt_sum != nullptr;   // the launch ends with the KKT check
 
   const float kappa = c.kmul * ldg(c.kscale, k);
   const float cb = ldg2(c.coef, static_cast<size_t>(k) * c.coef_stride).y;
@@ -164,9 +217,9 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
   const int o1 = qoff[1], o2 = qoff[2], o3 = qoff[3];
   __syncthreads();
 
-  for (int it = it0 + 1; it <= it0 + steps; ++it) {
-    // column pass over the kept columns: X[:, q] = IDFT_cols(m . DFT_cols(X[:, q]) + r),
-    // m = b Omega_j and r = rhs_j on the column's support bins, m = r = 0 elsewhere
+  // column pass over the kept columns: X[:, q] = IDFT_cols(m . DFT_cols(X[:, q]) + r),
+  // m = b Omega_j and r = rhs_j on the column's support bins, m = r = 0 elsewhere
+  auto column_pass = [&]() __attribute__((always_inline)) {
     for (int q = g; q < nq; q += G) {
       const int k1 = qk1[q];
       const int t = opaque(t0);
@@ -193,6 +246,31 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
 #pragma unroll
       for (int e = 0; e < E; ++e) X[F::in_index(t, e) * xs + q] = v[e];
     }
+  };
+  // u = IDFT_rows(X) of the row xr at this thread's elements t + T e
+  auto row_inverse = [&](const float2* xr, int t, float2 (&v)[E]) __attribute__((always_inline)) {
+    const float2* wt = tw2 + t;
+    float2 S[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S[j] = zero;
+#pragma unroll 4
+    for (int q = 0; q < o1; ++q) cmac(S[0], xr[q], wt[q * T]);
+#pragma unroll 4
+    for (int q = o1; q < o2; ++q) cmac(S[1], xr[q], wt[q * T]);
+#pragma unroll 4
+    for (int q = o2; q < o3; ++q) cmac(S[2], xr[q], wt[q * T]);
+#pragma unroll 4
+    for (int q = o3; q < nq; ++q) cmac(S[3], xr[q], wt[q * T]);
+    const float2 a = cadd(S[0], S[2]), b = make_float2(S[0].x - S[2].x, S[0].y - S[2].y);
+    const float2 cc = cadd(S[1], S[3]), d = make_float2(S[1].x - S[3].x, S[1].y - S[3].y);
+    v[0] = cadd(a, cc);                              // i^0
+    v[1] = make_float2(b.x - d.y, b.y + d.x);        // S0 + i S1 - S2 - i S3
+    v[2] = make_float2(a.x - cc.x, a.y - cc.y);      // S0 - S1 + S2 - S3
+    v[3] = make_float2(b.x + d.y, b.y - d.x);        // S0 - i S1 - S2 + i S3
+  };
+
+  for (int it = it0 + 1; it <= it0 + steps; ++it) {
+    column_pass();
     __syncthreads();
 
     // row pass: z_t = c_{t-1} + beta_{t-1} (c_{t-1} - c_{t-2}); c_t = S_kappa(z_t + IDFT_rows(X));
@@ -210,26 +288,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       const int n1 = cntl[i1 * N + r], n2 = cntl[i2 * N + r];
       // u = IDFT_rows(X) at this thread's elements t + T e
       float2 v[E];
-      {
-        const float2* wt = tw2 + t;
-        float2 S[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) S[j] = zero;
-#pragma unroll 4
-        for (int q = 0; q < o1; ++q) cmac(S[0], xr[q], wt[q * T]);
-#pragma unroll 4
-        for (int q = o1; q < o2; ++q) cmac(S[1], xr[q], wt[q * T]);
-#pragma unroll 4
-        for (int q = o2; q < o3; ++q) cmac(S[2], xr[q], wt[q * T]);
-#pragma unroll 4
-        for (int q = o3; q < nq; ++q) cmac(S[3], xr[q], wt[q * T]);
-        const float2 a = cadd(S[0], S[2]), b = make_float2(S[0].x - S[2].x, S[0].y - S[2].y);
-        const float2 cc = cadd(S[1], S[3]), d = make_float2(S[1].x - S[3].x, S[1].y - S[3].y);
-        v[0] = cadd(a, cc);                              // i^0
-        v[1] = make_float2(b.x - d.y, b.y + d.x);        // S0 + i S1 - S2 - i S3
-        v[2] = make_float2(a.x - cc.x, a.y - cc.y);      // S0 - S1 + S2 - S3
-        v[3] = make_float2(b.x + d.y, b.y - d.x);        // S0 - i S1 - S2 + i S3
-      }
+      row_inverse(xr, t, v);
       float2 p1[E];
       bool cold = false;   // c_t and z_{t+1} vanish on the row
       if (n1 == 0 && n2 == 0) {
@@ -357,41 +416,7 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       }
       // X = DFT_rows(z_{t+1}) on the kept columns: direct sums over its nonzeros when it has
       // at most N/8 of them (none for most rows once the iterate is sparse), else the row FFT
-      if (ztot > DIRECT) {
-        fft_fwd<F>(zn, t, stw, sa, sb, true);
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (kq[e] >= 0) xr[kq[e]] = zn[e];
-      } else if (ztot == 0) {
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (kq[e] >= 0) xr[kq[e]] = zero;
-      } else {
-        lds_sync<true>();   // the group's last use of its areas is done
-        int* zpos = reinterpret_cast<int*>(sb);
-        int o = zbefore;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if (zn[e].x != 0.f || zn[e].y != 0.f) {
-            sa[o] = zn[e];
-            zpos[o] = F::in_index(t, e);
-            ++o;
-          }
-        }
-        lds_sync<true>();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if (kq[e] >= 0) {
-            const int kk = F::out_index(t, e);
-            float2 acc = zero;
-            for (int q = 0; q < ztot; ++q) {
-              const float2 w = stw[(kk * zpos[q]) & (N - 1)];   // e^{-j 2 pi k l / N}
-              acc = cadd(acc, cmul(sa[q], w));
-            }
-            xr[kq[e]] = acc;
-          }
-        }
-      }
+      kept_forward<F, N, E>(zn, ztot, zbefore, t, kq, stw, sa, sb, xr);
     }
     __syncthreads();
   }
@@ -403,10 +428,74 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
     }
     for (int j = threadIdx.x; j < 3 * N; j += blockDim.x)
       stg(c.buf[j / N].cnt, static_cast<size_t>(k) * N + (j - (j / N) * N), cntl[j]);
-    __syncthreads();   // LDS is reused by the next scene
   }
+  if (kkt) {
+    // X = kept spectra of c_t, read back from the outputs (rows with nonzeros only) ...
+    const int* nc = cntl + ((it0 + steps) % 3) * N;   // the row counts of c_t
+    __syncthreads();   // the state is saved: X is free
+    for (int r = g; r < N; r += G) {
+      const int t = opaque(t0);
+      float2 x[E];
+      int mine = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] = zero;
+      if (nc[r] > 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          x[e] = ldg2(out, static_cast<size_t>(r) * N + F::in_index(t, e));
+          mine += (x[e].x != 0.f || x[e].y != 0.f) ? 1 : 0;
+        }
+      }
+      int tot, before;
+      row_prefix<T>(mine, t, nullptr, tot, before);
+      kept_forward<F, N, E>(x, tot, before, t, kq, stw, sa, sb, X + r * xs);
+    }
+    __syncthreads();
+    // ... -> kept spectra of mu (b - G c_t); then per element g = b - G c_t and e^2 in
+    // double, summed over the scene
+    column_pass();
+    __syncthreads();
+    const double tau = ldg(c.kscale, k), sc = c.kkt_scale;
+    double acc = 0.0;
+    for (int r = g; r < N; r += G) {
+      const int t = opaque(t0);
+      float2 v[E];
+      row_inverse(X + r * xs, t, v);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        // c_t as this thread stored it to the outputs in the last row pass
+        const float2 cv = nc[r] > 0 ? ldg2(out, static_cast<size_t>(r) * N + F::in_index(t, e)) : zero;
+        const double gr = sc * v[e].x, gi = sc * v[e].y;
+        const double cr = cv.x, ci = cv.y;
+        double e2;
+        if (cr != 0.0 || ci != 0.0) {
+          const double ac = sqrt(cr * cr + ci * ci);
+          const double er = gr - tau * cr / ac, ei = gi - tau * ci / ac;
+          e2 = er * er + ei * ei;
+        } else {
+          const double g2 = gr * gr + gi * gi;
+          const double dd = g2 > tau * tau ? sqrt(g2) - tau : 0.0;
+          e2 = dd * dd;
+        }
+        acc += e2;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __syncthreads();   // every row is done with X
+    double* red = reinterpret_cast<double*>(X);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) sum += red[w];
+      stg(c.kkt_sum, static_cast<size_t>(k), sum);
+    }
+  }
+  if (carry) __syncthreads();   // LDS is reused by the next scene
 }
 
+template <bool KKT>
 __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass* cls, int ncls, int total,
                                                              const float* beta, int it0, int steps, int carry,
                                                              int* queue) {
@@ -423,10 +512,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass
     const ResidentClass& c = cls[ci];
     const int k = c.scene_map ? c.scene_map[q - c.first] : q - c.first;
     switch (c.N) {
-      case 32: solve_scene<32, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
-      case 64: solve_scene<64, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
-      case 128: solve_scene<128, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
-      case 256: solve_scene<256, kResidentE>(c, k, beta, it0, steps, carry, lds); break;
+      case 32: solve_scene<32, kResidentE, KKT>(c, k, beta, it0, steps, carry, lds); break;
+      case 64: solve_scene<64, kResidentE, KKT>(c, k, beta, it0, steps, carry, lds); break;
+      case 128: solve_scene<128, kResidentE, KKT>(c, k, beta, it0, steps, carry, lds); break;
+      case 256: solve_scene<256, kResidentE, KKT>(c, k, beta, it0, steps, carry, lds); break;
       default: break;
     }
   }
@@ -435,25 +524,34 @@ __global__ __launch_bounds__(kMaxThreads) void k_scene_fista(const ResidentClass
 }  // namespace
 
 int launch_scene_fista(const ResidentClass* cls, int ncls, int total, const float* beta, int it0, int steps,
-                       int carry, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s) {
+                       int carry, int check, int* queue, int nthreads, int blocks, size_t lds, hipStream_t s) {
   if (!cls || ncls < 1 || total < 1 || !beta || it0 < 0 || steps < 1 || (carry != 0 && carry != 1) || !queue)
     return -1;
+  if ((check != 0 && check != 1) || (check && !carry)) return -1;
   if (nthreads < 64 || nthreads > kMaxThreads || nthreads % 64 != 0 || blocks < 1) return -1;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scene_fista), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(lds)) != hipSuccess)
+  const void* fn = check ? reinterpret_cast<const void*>(k_scene_fista<true>)
+                         : reinterpret_cast<const void*>(k_scene_fista<false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
     return -2;
-  hipLaunchKernelGGL(k_scene_fista, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, it0, steps, carry,
-                     queue);
+  if (check)
+    hipLaunchKernelGGL(k_scene_fista<true>, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, it0, steps,
+                       carry, queue);
+  else
+    hipLaunchKernelGGL(k_scene_fista<false>, dim3(blocks), dim3(nthreads), lds, s, cls, ncls, total, beta, it0,
+                       steps, carry, queue);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int scene_fista_occupancy(int nthreads, size_t lds) {
+int scene_fista_occupancy(int nthreads, size_t lds, int check) {
   int nb = 0;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_scene_fista), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(lds)) != hipSuccess)
+  const void* fn = check ? reinterpret_cast<const void*>(k_scene_fista<true>)
+                         : reinterpret_cast<const void*>(k_scene_fista<false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scene_fista, nthreads, lds) != hipSuccess) return 0;
-  return nb;
+  hipError_t rc;
+  if (check) rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scene_fista<true>, nthreads, lds);
+  else rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scene_fista<false>, nthreads, lds);
+  return rc == hipSuccess ? nb : 0;
 }
 
 }  // namespace bccb

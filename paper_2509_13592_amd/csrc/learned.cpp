@@ -361,6 +361,8 @@ int resident_setup(bccb_lista_s* n) {
   r.out_base = n->d_c;
   r.scene_map = n->d_map;
   r.xkeep = n->d_xyc;
+  r.kkt_sum = n->d_rk;   // each chunk's launch ends with the KKT check of its scenes
+  r.kkt_scale = static_cast<float>(1.0 / pl->mu);
   float2* dense[3] = {n->d_R0, n->d_xy, n->d_cprev};
   for (int i = 0; i < 3; ++i) {
     r.buf[i].cnt = n->d_pcnt[i];
@@ -371,7 +373,7 @@ int resident_setup(bccb_lista_s* n) {
   int best = 0;
   for (int nt : {256, 512, 1024}) {
     const long lds = resident_lds_bytes(N, r.ncs, nt);
-    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds));
+    const int nb = scene_fista_occupancy(nt, static_cast<size_t>(lds), 1);
     if (nb * (nt / 64) > best) {
       best = nb * (nt / 64);
       n->res_threads = nt;
@@ -822,13 +824,16 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     if (na) BCCB_HIP(hipMemcpyAsync(n->d_map, n->h_map, na * sizeof(int), hipMemcpyHostToDevice, s));
     return BCCB_OK;
   };
-  auto residuals = [&](const std::vector<int>& act, std::vector<double>& r) -> int {
-    const int na = static_cast<int>(act.size());
-    BCCB_TRY(kkt_sums(n, na, n->d_map));
+  // r_KKT of the active scenes from the sums in d_rk
+  auto read_residuals = [&](const std::vector<int>& act, std::vector<double>& r) -> int {
     BCCB_HIP(hipMemcpyAsync(n->h_tmp, n->d_rk, batch * sizeof(double), hipMemcpyDeviceToHost, s));
     BCCB_HIP(hipStreamSynchronize(s));
     for (int i : act) r[i] = bn[i] > 0.0 ? std::sqrt(n->h_tmp[i] / bn[i]) : std::sqrt(n->h_tmp[i]);
     return BCCB_OK;
+  };
+  auto residuals = [&](const std::vector<int>& act, std::vector<double>& r) -> int {
+    BCCB_TRY(kkt_sums(n, static_cast<int>(act.size()), n->d_map));
+    return read_residuals(act, r);
   };
   std::vector<int> act(batch);
   for (int i = 0; i < batch; ++i) act[i] = i;
@@ -912,9 +917,10 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     const int steps = std::min(check_every, max_iters - done_iters);
     if (resident) {
       // the check interval of every active scene in one persistent launch (iterations
-      // tp + 1 .. tp + steps, the state carried in d_xyc and the slot counts, c_t to d_c)
+      // tp + 1 .. tp + steps, the state carried in d_xyc and the slot counts, c_t to d_c),
+      // ending with each scene's KKT sum in d_rk
       BCCB_TRY(kern(launch_fill_int(n->d_queue, 1, 0, s)));
-      BCCB_TRY(kern(launch_scene_fista(n->d_rcls, 1, na, n->d_rbeta, tp, steps, 1, n->d_queue, n->res_threads,
+      BCCB_TRY(kern(launch_scene_fista(n->d_rcls, 1, na, n->d_rbeta, tp, steps, 1, 1, n->d_queue, n->res_threads,
                                        std::min(n->res_blocks, na), n->res_lds, s)));
       tp += steps;
     }
@@ -975,7 +981,8 @@ int lista_solve(bccb_lista_t n, const float* params, const bccb_c32* y, const fl
     }
     done_iters += steps;
     for (int i : act) used[i] = done_iters;
-    BCCB_TRY(residuals(act, rk));
+    if (resident) BCCB_TRY(read_residuals(act, rk));
+    else BCCB_TRY(residuals(act, rk));
     std::vector<int> keep;
     for (int i : act)
       if (!(rk[i] <= kkt_target)) keep.push_back(i);

@@ -310,7 +310,9 @@ def test_resident_fallback_matches_passes():
     against the per-iteration pruned passes: the scenes converge after the same number of
     iterations up to 5 % (FISTA's KKT residual is not monotone, and the two forms' different
     FP32 summation orders can move its crossing of the target by a few check intervals), to
-    the same solutions at FP32 rounding, at the oracle's KKT."""
+    the same solutions at FP32 rounding, at the oracle's KKT.  The persistent launches form
+    the residual in the kernel itself (their last row and column passes plus a class-sum row
+    inverse): every scene's returned r_KKT is compared with the oracle's at its solution."""
     from paper_2509_13592_amd import train_lista as T
     params, rec = T.load_params()
     mask, L1, L2 = S.learned_fixed_mask(), 256, 256
@@ -332,7 +334,8 @@ def test_resident_fallback_matches_passes():
         assert abs(it_r.mean() - it_p.mean()) <= 0.01 * it_p.mean()
         # where both stopped at the same check the iterates agree to rounding; where the
         # crossing moved, each stopping point is checked against the oracle's KKT residual
-        # (the iterate still moves a few per cent between checks at this target)
+        # (the iterate still moves a few per cent between checks at this target); every
+        # returned residual against the oracle's at the returned iterate
         moved = [i for i in range(n) if it_r[i] != it_p[i]]
         for i in range(n):
             if i in moved:
@@ -340,7 +343,7 @@ def test_resident_fallback_matches_passes():
             a, b = c_r[i].cpu().numpy(), c_p[i].cpu().numpy()
             assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b)
         ycpu = ys.cpu().numpy()
-        for i in sorted(set([0, n - 1] + moved)):
+        for i in range(n):
             P = O.Problem(mask, L1, L2, ycpu[i].astype(np.complex128), tau=float(taus[i]), dense=False)
             r_ref, _ = P.kkt(c_r[i].cpu().numpy().reshape(-1).astype(np.complex128))
             assert r_ref <= 1.05 * target and abs(r_ref - rk_r[i]) <= 0.05 * target
