@@ -350,3 +350,40 @@ def test_resident_fallback_matches_passes():
     assert B.lib.lista_set_resident(net._h, 2) == B.BCCB_E_INVALID
     net.close()
     plan.close()
+
+
+@pytest.mark.parametrize("M1,M,L", [(8, 32, 32), (8, 40, 64), (16, 100, 128)])
+def test_resident_fallback_small_grids(M1, M, L):
+    """The fallback's persistent launches, and the KKT check each of them ends with, at the grid
+    lengths below the paper's (32^2 .. 128^2; the kernel is instantiated per length), with
+    check intervals of 1 and 7 iterations: iteration counts against the per-iteration passes
+    (checked by separate kernels), every returned r_KKT against the FP64 oracle's at the
+    returned iterate."""
+    mask = S.custom_scene(M1, M1, M, L, L, K=2, snr_db=20, seed=(41, L, 0)).mask
+    n = 6
+    scenes = [S.custom_scene(M1, M1, M, L, L, K=1 + i % 4, snr_db=12 + 2 * i, seed=(41, L, i), mask=mask,
+                             modulus=(0.5, 1.0)) for i in range(n)]
+    plan = B.Plan(mask, L, L)
+    ys = _ys(scenes)
+    taus = [float(np.float32(0.1 * plan.adjoint_maxabs(ys[i]))) for i in range(n)]
+    net = B.Lista(plan, layers=4, max_batch=n)
+    target = 1e-4
+    for every in (1, 7):
+        out = {}
+        for on in (True, False):
+            net.set_resident(on)   # raises where the context cannot take the persistent form
+            out[on] = net.solve(None, ys, taus, kkt_target=target, check_every=every, max_iters=6000)
+        (c_r, it_r, rk_r, rc_r), (c_p, it_p, rk_p, rc_p) = out[True], out[False]
+        print(f"case resident fallback {L}^2 every {every}: iters {it_r.tolist()} vs passes {it_p.tolist()}",
+              flush=True)
+        assert rc_r == 0 and rc_p == 0
+        assert np.all(rk_r <= target)
+        assert np.all(np.abs(it_r - it_p) <= np.maximum(10, 0.05 * it_p))
+        for i, sc in enumerate(scenes):
+            P = O.Problem(mask, L, L, sc.y, tau=taus[i], dense=False)
+            r_ref, _ = P.kkt(c_r[i].cpu().numpy().reshape(-1).astype(np.complex128))
+            print(f"   scene {i}: r_KKT kernel {rk_r[i]:.6e} oracle {r_ref:.6e}", flush=True)
+            # g = b - G c in FP32 errs by a few 1e-7 of ||b|| in norm: 1e-6 on r = ||e|| / ||b||
+            assert abs(r_ref - rk_r[i]) <= 1e-6
+    net.close()
+    plan.close()
