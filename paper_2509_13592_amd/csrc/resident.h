@@ -418,14 +418,6 @@ struct ResidentPrunedShape {
   }
 };
 
-// Threads adding up the parts of one bin: a power of two, at most 16, with
-// every bin of a pass over the block covered.
-__host__ __device__ constexpr int resident_part_lanes(int nsup, int nt) {
-  int q = 1;
-  while (q < 16 && 2 * q * nsup <= nt) q *= 2;
-  return q;
-}
-
 template <int N1, int N2, int MODE, int NT_>
 __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   using S = ResidentPrunedShape<N1, N2, NT_>;
@@ -546,34 +538,38 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
   unsigned epoch = 1;
   if (!resident_sync<false>(a, g, epoch, &s_ok)) return;
 
-  const int Q = resident_part_lanes(nsup, NT);
+  constexpr int W = NT / 64;   // waves per group
+  static_assert(S::RPC * S::AR1 * S::FA1 >= W * 64, "the wave sums of the parts fit the exchange areas");
+  const int lane = tid & 63, wv = tid >> 6;
+  float2* const red = area;   // [W][64] wave sums of the parts, between the barrier and the row IFFT
   const float kappa = a.kappa;
   for (int t = 1; t <= a.iters; ++t) {
     const float beta = kFista ? a.beta[t - 1] : 0.f;
     const bool last = (t == a.iters);
     float2* const part = parts + (t & 1) * pstride;
-    // Z_j: the G parts of every bin, Q threads per bin (adjacent lanes), each
-    // over the groups q, q + Q, ... in order, then a fixed butterfly
-    for (int j0 = 0; j0 < nsup; j0 += NT / Q) {
-      const int j = j0 + tid / Q, q = tid % Q;
+    // Z_j: lane l of wave w adds the parts of groups w, w + W, ... at bin j0 + l in order
+    // (each load of a wave reads 64 consecutive bins of one group's part), then the W
+    // wave sums are added in wave order
+    for (int j0 = 0; j0 < nsup; j0 += 64) {
+      const int j = j0 + lane;
       const int jj = j < nsup ? j : nsup - 1;
       float2 acc = zero;
-      for (int g0 = q; g0 < G; g0 += PB * Q) {
+      for (int g0 = wv; g0 < G; g0 += PB * W) {
         float2 pv[PB];
 #pragma unroll
         for (int k = 0; k < PB; ++k) {
-          const int gg = g0 + k * Q;
+          const int gg = g0 + k * W;
           pv[k] = zero;
           if (gg < G) pv[k] = load_coherent(part + static_cast<size_t>(gg) * nsup + jj);   // none past G
         }
 #pragma unroll
         for (int k = 0; k < PB; ++k) acc = cadd(acc, pv[k]);
       }
-      for (int off = 1; off < Q; off <<= 1) {
-        const float ox = __shfl_xor(acc.x, off, 64), oy = __shfl_xor(acc.y, off, 64);
-        acc = (q & off) ? make_float2(ox + acc.x, oy + acc.y) : make_float2(acc.x + ox, acc.y + oy);
-      }
-      if (q == 0 && j < nsup) {
+      red[wv * 64 + lane] = acc;
+      __syncthreads();
+      if (tid < 64 && j < nsup) {
+        acc = red[lane];
+        for (int w2 = 1; w2 < W; ++w2) acc = cadd(acc, red[w2 * 64 + lane]);
         if constexpr (kAdmm) {
           const float2 p0 = ps[j];
           const float2 vp = make_float2(br[j].x + bq[j] * p0.x + bm[j] * acc.x, br[j].y + bq[j] * p0.y + bm[j] * acc.y);
@@ -585,6 +581,7 @@ __global__ __launch_bounds__(512) void k_resident_pruned(ResidentArgs a) {
           vs[j] = make_float2(acc.x * bm[j] + br[j].x, acc.y * bm[j] + br[j].y);
         }
       }
+      if (j0 + 64 < nsup) __syncthreads();   // red is refilled for the next 64 bins
     }
     __syncthreads();
     // the owned rows' kept spectra of IDFT2(V) at this thread's positions
