@@ -43,9 +43,9 @@ TRAFFIC = {
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
-    "75f002369e8c1b4f": {
-        "resident_pruned": {"bytes_per_iteration": 42729,
-                            "launch": {"resident_groups": 32, "resident_spread": 8, "resident_block": 512,
+    "55f141fd43ba43a4": {
+        "resident_pruned": {"bytes_per_iteration": 367636,
+                            "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 256,
                                        "support_columns": 1}},
     },
 }
