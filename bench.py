@@ -31,22 +31,26 @@ ALGO_BYTES_PER_POINT = {"ista": 28, "fista": 36, "admm": 44}   # per iteration p
 
 # HBM bytes per FISTA iteration (column pass + row pass) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, keyed by the kernel code they were measured on (comments aside),
-# with the launch shape of that run.  When the source or the chosen shape differs the
-# figure does not apply and `traffic` is reported as null.
+# each with the launch shape of its run (a path may hold counts of several shapes).
+# When the source or the chosen shape differs the figure does not apply and `traffic`
+# is reported as null.
 TRAFFIC = {
     # profiles/fista_passes_256_single_rocprofv3.md (FETCH_SIZE x 2 + WRITE_SIZE, KiB per dispatch)
     "89879c138cba15d1": {
-        "full": {"bytes_per_iteration": int((302.0 + 554.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
-                 "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2}},
-        "pruned": {"bytes_per_iteration": int((176.9 + 177.3) * 2 * 1024 + (64.0 + 53.4) * 1024),
-                   "launch": {"prow_elems": 4, "prow_rows_per_block": 2, "pcol_elems": 4, "pcol_cols_per_block": 2}},
+        "full": [{"bytes_per_iteration": int((302.0 + 554.0) * 2 * 1024 + (512.0 + 1023.2) * 1024),
+                  "launch": {"row_elems": 4, "row_rows_per_block": 1, "col_elems": 4, "col_cols_per_block": 2}}],
+        "pruned": [{"bytes_per_iteration": int((176.9 + 177.3) * 2 * 1024 + (64.0 + 53.4) * 1024),
+                    "launch": {"prow_elems": 4, "prow_rows_per_block": 2, "pcol_elems": 4, "pcol_cols_per_block": 2}}],
     },
     # profiles/fista_cooperative_256_single_rocprofv3.md: the pruned cooperative FISTA solve,
     # (FETCH_SIZE x 2 + WRITE_SIZE) per 500-iteration dispatch / 500
     "55f141fd43ba43a4": {
-        "resident_pruned": {"bytes_per_iteration": 367636,
-                            "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 256,
-                                       "support_columns": 1}},
+        "resident_pruned": [
+            {"bytes_per_iteration": 367636,
+             "launch": {"resident_groups": 64, "resident_spread": 1, "resident_block": 256, "support_columns": 1}},
+            {"bytes_per_iteration": 42482,
+             "launch": {"resident_groups": 32, "resident_spread": 8, "resident_block": 512, "support_columns": 1}},
+        ],
     },
 }
 
@@ -102,10 +106,10 @@ def _traffic_for(kh, launch):
         path = "resident_pruned" if launch.get("support_columns") else "resident"
     else:
         path = "pruned" if launch.get("support_columns") else "full"
-    t = TRAFFIC.get(kh, {}).get(path)
-    if not t or any(launch.get(k) != v for k, v in t["launch"].items()):
-        return None, None   # another launch shape moves other bytes (e.g. one die's L2 or all eight)
-    return t["bytes_per_iteration"], t["launch"]
+    for t in TRAFFIC.get(kh, {}).get(path, []):
+        if all(launch.get(k) == v for k, v in t["launch"].items()):
+            return t["bytes_per_iteration"], t["launch"]
+    return None, None   # another launch shape moves other bytes (e.g. one die's L2 or all eight)
 
 
 def _code_only(text: str) -> str:

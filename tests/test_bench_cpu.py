@@ -29,25 +29,27 @@ def test_code_hash_ignores_comments_only():
 def test_traffic_lookup_by_path_and_code():
     # every entry of the table names the launch shape it was counted on
     for paths in bench.TRAFFIC.values():
-        for entry in paths.values():
-            assert entry["bytes_per_iteration"] > 0 and isinstance(entry["launch"], dict)
+        for entries in paths.values():
+            for entry in entries:
+                assert entry["bytes_per_iteration"] > 0 and isinstance(entry["launch"], dict)
     assert bench._traffic_for("0000000000000000", {"support_columns": 0}) == (None, None)
     # a count applies to the launch shape it was taken on only
     for kh, paths in bench.TRAFFIC.items():
-        for path, entry in paths.items():
-            shape = dict(entry["launch"])
-            shape.setdefault("support_columns", 1 if "pruned" in path else 0)
-            if path.startswith("resident"):
-                shape.setdefault("resident_groups", 1)
-            assert bench._traffic_for(kh, shape) == (entry["bytes_per_iteration"], entry["launch"])
-            other = dict(shape)
-            key = next(iter(entry["launch"]))
-            other[key] = -1
-            assert bench._traffic_for(kh, other) == (None, None)
+        for path, entries in paths.items():
+            for entry in entries:
+                shape = dict(entry["launch"])
+                shape.setdefault("support_columns", 1 if "pruned" in path else 0)
+                if path.startswith("resident"):
+                    shape.setdefault("resident_groups", 1)
+                assert bench._traffic_for(kh, shape) == (entry["bytes_per_iteration"], entry["launch"])
+                other = dict(shape)
+                key = next(iter(entry["launch"]))
+                other[key] = -1
+                assert bench._traffic_for(kh, other) == (None, None)
     kh = bench._kernel_hash(True)
-    if kh in bench.TRAFFIC and "resident_pruned" in bench.TRAFFIC[kh]:
+    for entry in bench.TRAFFIC.get(kh, {}).get("resident_pruned", []):
         # the cooperative solve moves less than one dense FISTA iteration's 36 B per point
-        assert bench.TRAFFIC[kh]["resident_pruned"]["bytes_per_iteration"] < 36 * 256 * 256
+        assert entry["bytes_per_iteration"] < 36 * 256 * 256
 
 
 @pytest.mark.parametrize("solver,bytes_per_point", [("ista", 28), ("fista", 36), ("admm", 44)])
