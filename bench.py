@@ -112,6 +112,15 @@ def _traffic_for(kh, launch):
     return None, None   # another launch shape moves other bytes (e.g. one die's L2 or all eight)
 
 
+# Counted HBM bytes per grid point of one steady-state FISTA iteration of the full two-pass form
+# over a batch (row pass + column pass, FETCH_SIZE x 2 + WRITE_SIZE), keyed by the kernel code and
+# the class's launch shape (row E, rows per block, column E, columns per block) they were taken on.
+FULL_BATCH_TRAFFIC = {
+    # profiles/fista_full_passes_256_batch_rocprofv3.md: 1024 paper-scale scenes, default shapes
+    "4ea5bc2b879d30dd": {(16, 16, 16, 16): 48.0},
+}
+
+
 def _code_only(text: str) -> str:
     """Source text without comments, trailing blanks and empty lines (the kernels' code)."""
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -422,14 +431,19 @@ def copy_ceiling(B, gib=4.0, reps=5):
             "what": "read + write of a 4 GiB buffer by bccb_stream_copy, best of its shapes"}
 
 
-def _batch_rate(B, scenes, iters, reps, tune=True):
-    """Build plans + a batch for `scenes`, solve `reps` times; returns (seconds per solve, info)."""
+def _batch_rate(B, scenes, iters, reps, tune=True, full=False):
+    """Build plans + a batch for `scenes`, solve `reps` times; returns (seconds per solve, info).
+    full: the two full passes per iteration (every spectral column transformed, the iterate
+    stored densely) in place of the pruned forms."""
     import numpy as np
     import torch
     plans = [B.Plan(sc.mask, sc.L1, sc.L2) for sc in scenes]
     ys = [B.to_device(sc.y) for sc in scenes]
     taus = [float(np.float32(0.1 * p.adjoint_maxabs(y))) for p, y in zip(plans, ys)]
     batch = B.Batch(plans)
+    if full:
+        batch.set_support_columns(False)
+        batch.set_sparse_iterate(False)
     if tune:
         batch.autotune(reps=5)
 
@@ -443,7 +457,7 @@ def _batch_rate(B, scenes, iters, reps, tune=True):
         return (time.perf_counter() - t0) / reps
 
     outs = [p.grid(ys[0].device) for p in plans]
-    resident = batch.resident_info()
+    resident = batch.resident_info() if not full else {"on": 0}   # the persistent launch takes pruned classes only
     graph_dt = None
     if resident["on"] == 1:
         batch.set_resident(False)                 # the per-iteration pass graph, for comparison
@@ -513,6 +527,20 @@ def batched_runs(args):
     out["uniform_256"]["counted_bytes_per_point"] = counted
     out["uniform_256"]["frac_counted"] = (round(counted * 65536 * n2 * it2 / dt2 / 1e9 / HBM_PEAK_GBS, 4)
                                           if counted else None)
+    # the same batch through the full two passes per iteration (every spectral column, dense
+    # iterate): the HBM-bound form of the iteration, default launch shapes
+    it3 = 20
+    dt3, cls3, algo3 = _batch_rate(B, sc0, it3, reps=3, tune=False, full=True)
+    l3 = cls3[0]["launch"]
+    c3 = FULL_BATCH_TRAFFIC.get(_kernel_hash(), {}).get(
+        (l3["row_E"], l3["rows_per_block"], l3["col_E"], l3["cols_per_block"]))
+    out["uniform_256_full_passes"] = {
+        "workload": f"{n2} paper-scale 256^2 scenes, FISTA {it3} iterations, two full passes per iteration",
+        "scene_iters_per_s": round(n2 * it3 / dt3, 1), "classes": cls3, **_batch_roofline(algo3 * it3, dt3),
+        "counted_bytes_per_point": c3,
+        "frac_counted": round(c3 * 65536 * n2 * it3 / dt3 / 1e9 / HBM_PEAK_GBS, 4) if c3 else None,
+        "note": "wall time of the solve (per-solve uploads included); the passes alone run at 0.66 of HBM peak "
+                "by rocprofv3 (profiles/fista_full_passes_256_batch_rocprofv3.md)"}
     return out
 
 
@@ -638,6 +666,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batch256: default launch shapes, no autotuning")
     ap.add_argument("--batch-iters", type=int, default=20, help="batch256: FISTA iterations per solve")
     ap.add_argument("--uniform-scenes", type=int, default=256, help="batch256: paper-scale scenes in the batch")
+    ap.add_argument("--full-passes", action="store_true",
+                    help="batch256: the two full passes per iteration (no kept-column pruning, dense iterate)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the workloads are single-GPU by design; "
@@ -677,9 +707,13 @@ def main():
         return
     if args.only == "batch256":
         n = args.uniform_scenes
-        dt, classes, _ = _batch_rate(B, [S.paper_scale_scene(i) for i in range(n)], args.batch_iters, reps=2,
-                                     tune=not args.no_tune)
-        print(json.dumps({"batch256_s_per_solve": dt, "scenes": n, "iters": args.batch_iters, "classes": classes}))
+        dt, classes, algo = _batch_rate(B, [S.paper_scale_scene(i) for i in range(n)], args.batch_iters, reps=2,
+                                        tune=not args.no_tune, full=args.full_passes)
+        rec = {"batch256_s_per_solve": dt, "scenes": n, "iters": args.batch_iters, "classes": classes}
+        if args.full_passes:
+            rec["full_passes"] = {"scene_iters_per_s": round(n * args.batch_iters / dt, 1),
+                                  **_batch_roofline(algo * args.batch_iters, dt)}
+        print(json.dumps(rec))
         return
     sc = S.paper_scale_scene(0)
     plan = B.Plan(sc.mask, sc.L1, sc.L2)
