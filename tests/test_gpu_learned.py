@@ -387,3 +387,36 @@ def test_resident_fallback_small_grids(M1, M, L):
             assert abs(r_ref - rk_r[i]) <= 1e-6
     net.close()
     plan.close()
+
+
+def test_resident_fallback_stops_at_the_cap():
+    """A target the fallback cannot reach within the cap: 25 iterations checked every 10 (two full
+    persistent launches and one of 5 iterations, each ending with its KKT check).  Both forms stop
+    every scene at the cap with the not-converged warning, the iterates agree to FP32 rounding,
+    and every returned r_KKT is the FP64 oracle's at the returned iterate."""
+    mask, L1, L2 = _geometry("paper")
+    n = 6
+    scenes = [S.learned_scene(1, 100 + i, mask) for i in range(n)]
+    plan = B.Plan(mask, L1, L2)
+    ys = _ys(scenes)
+    taus = [float(np.float32(0.1 * plan.adjoint_maxabs(ys[i]))) for i in range(n)]
+    net = B.Lista(plan, layers=16, max_batch=n)
+    out = {}
+    for on in (True, False):
+        net.set_resident(on)
+        out[on] = net.solve(None, ys, taus, kkt_target=1e-9, check_every=10, max_iters=25)
+    (c_r, it_r, rk_r, rc_r), (c_p, it_p, rk_p, rc_p) = out[True], out[False]
+    print(f"case resident fallback at the cap: r_KKT {rk_r.tolist()} vs passes {rk_p.tolist()}", flush=True)
+    assert rc_r == 1 and rc_p == 1   # BCCB_W_NOT_CONVERGED
+    assert np.all(it_r == 25) and np.all(it_p == 25)
+    for i, sc in enumerate(scenes):
+        a, b = c_r[i].cpu().numpy(), c_p[i].cpu().numpy()
+        # two FP32 forms, each within 4 T u log2 L of the exact iterate (transforms of log2 L
+        # stages per iteration, errors adding along T, the momentum re-applying two of them)
+        tol = 2 * 4 * 25 * 2.0 ** -24 * np.log2(L1 * L2)
+        assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b)
+        P = O.Problem(mask, L1, L2, sc.y, tau=taus[i], dense=False)
+        r_ref, _ = P.kkt(a.reshape(-1).astype(np.complex128))
+        assert r_ref > 1e-9 and abs(r_ref - rk_r[i]) <= 1e-3 * r_ref
+    net.close()
+    plan.close()
