@@ -129,7 +129,7 @@ __device__ __forceinline__ void kept_forward(float2 (&x)[E], int tot, int before
 // iterate c_t inside the same workgroup once the state is saved: c_t's kept row spectra
 // (from the rows it wrote to the outputs) go to X, one more column pass turns them into
 // those of mu (b - G c_t), and a row pass of class sums forms the sum of e^2 over the
-// scene (the arithmetic of the separate KKT row kernel, in double).
+// scene (the conditions of the separate KKT row kernel; each term in FP32, the sum in FP64).
 template <int N, int E, bool KKT>
 __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, int it0, int steps, int carry,
                             float2* lds) {
@@ -451,11 +451,13 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       kept_forward<F, N, E>(x, tot, before, t, kq, stw, sa, sb, X + r * xs);
     }
     __syncthreads();
-    // ... -> kept spectra of mu (b - G c_t); then per element g = b - G c_t and e^2 in
-    // double, summed over the scene
+    // ... -> kept spectra of mu (b - G c_t); then per element g = b - G c_t and e^2,
+    // summed over the scene
     column_pass();
     __syncthreads();
-    const double tau = ldg(c.kscale, k), sc = c.kkt_scale;
+    // per element in FP32 (g itself comes from FP32 sums, with errors of the order of those
+    // of these few operations), summed in FP64
+    const float tau = ldg(c.kscale, k), sc = c.kkt_scale;
     double acc = 0.0;
     for (int r = g; r < N; r += G) {
       const int t = opaque(t0);
@@ -465,19 +467,14 @@ __device__ void solve_scene(const ResidentClass& c, int k, const float* beta, in
       for (int e = 0; e < E; ++e) {
         // c_t as this thread stored it to the outputs in the last row pass
         const float2 cv = nc[r] > 0 ? ldg2(out, static_cast<size_t>(r) * N + F::in_index(t, e)) : zero;
-        const double gr = sc * v[e].x, gi = sc * v[e].y;
-        const double cr = cv.x, ci = cv.y;
-        double e2;
-        if (cr != 0.0 || ci != 0.0) {
-          const double ac = sqrt(cr * cr + ci * ci);
-          const double er = gr - tau * cr / ac, ei = gi - tau * ci / ac;
-          e2 = er * er + ei * ei;
-        } else {
-          const double g2 = gr * gr + gi * gi;
-          const double dd = g2 > tau * tau ? sqrt(g2) - tau : 0.0;
-          e2 = dd * dd;
-        }
-        acc += e2;
+        const float gr = sc * v[e].x, gi = sc * v[e].y;
+        const float a2 = sq_abs(cv);
+        // c != 0: e = g - tau c / |c|; c = 0: |e| = max(|g| - tau, 0); both formed, one kept
+        const float rc = a2 > 0.f ? __builtin_amdgcn_rsqf(a2) : 0.f;
+        const float er = gr - tau * cv.x * rc, ei = gi - tau * cv.y * rc;
+        const float dd = __builtin_fmaxf(__builtin_sqrtf(__builtin_fmaf(gr, gr, gi * gi)) - tau, 0.f);
+        const float e2 = a2 > 0.f ? __builtin_fmaf(er, er, ei * ei) : dd * dd;
+        acc += static_cast<double>(e2);
       }
     }
 #pragma unroll
