@@ -86,3 +86,20 @@ def test_batch_fraction_is_a_fraction():
     assert abs(r["frac_hbm_peak"] - 1.0) < 1e-9 and "bytes_model" in r
     r = bench._batch_roofline(1e9, 1.0)
     assert 0 < r["frac_hbm_peak"] < 1
+
+
+def test_counted_tables_are_well_formed():
+    # the counted full-pass bytes and the persistent launch's VALU count name the launch
+    # shape / workload they were taken on, and each applies only to its own source version
+    for kh, shapes in bench.FULL_BATCH_TRAFFIC.items():
+        assert len(kh) == 16
+        for shape, bpp in shapes.items():
+            assert len(shape) == 4 and all(isinstance(v, int) and v > 0 for v in shape)
+            # the two full passes move at least the dense iteration's 36 B per point
+            assert 36 <= bpp <= 64
+    for kh, entry in bench.PERSISTENT_VALU.items():
+        assert len(kh) == 16
+        scenes, n, iters = entry["workload"]
+        assert scenes > 0 and n in (32, 64, 128, 256) and iters > 0
+        assert entry["valu_per_scene_iteration"] > 0
+    assert bench._persistent_hash() != bench._kernel_hash()
